@@ -1,0 +1,240 @@
+/*
+ * rpca.h -- l1 filtering for Principal Component Pursuit on AMD MI355X (gfx950).
+ *
+ * The method (Liu, Lin, Wei, Su, "Solving Principal Component Pursuit in
+ * Linear Time via l1 Filtering") recovers M = L + S, L low rank and S sparse,
+ * in the five steps of Algorithm 2:
+ *   1. sample p = os_r*r seed rows I_s and q = os_c*r seed columns J_s (Sec. 3.1);
+ *   2. solve the small PCP (eq. SPCP) on M^s = M[I_s, J_s]            -> rpca_seed
+ *   3. column l1 filtering (eq. l1c'), one l1 regression per column     -> rpca_filter_cols
+ *   4. row l1 filtering (eq. l1r'), one l1 regression per row           -> rpca_filter_rows
+ *   5. complete L (eqs. l1s, l1s') and S = M - L                        -> rpca_reconstruct
+ * rpca_solve runs all five.  Each regression of steps 3-4 is
+ *   min_z ||x - A z||_1,  A^T A = I   (eq. l1g),
+ * solved by the alternating direction method of Algorithm 1.
+ *
+ * Conventions
+ *   Layout     every matrix is column-major with an explicit leading dimension
+ *              (element (i, j) of M is M[i + j*ldm]); a row-major (n, ld)
+ *              tensor holds the same bytes.  Index arrays are int64.
+ *   Memory     M, L, S, the index arrays, U/sigma/V, Qt/Pt and iters are
+ *              DEVICE pointers on the context's device.  rpca_opts,
+ *              rpca_info and scalar outputs (r_used, seed_iters) are host
+ *              pointers.  rpca_sample_indices works on host arrays.
+ *   Ownership  the caller allocates and frees every argument; the library
+ *              never frees or retains caller memory after a call returns (or,
+ *              for asynchronous calls, after the stream reaches the call).
+ *              The context owns only its own workspace.
+ *   Errors     arguments are checked on the host before anything is
+ *              enqueued.  Negative status = error, outputs untouched (or, for
+ *              errors detected on the device, unspecified).  Positive status =
+ *              warning, outputs valid.  rpca_last_error() describes the last
+ *              status of a context in words.
+ *   Streams    filter and reconstruct calls are asynchronous on `stream`
+ *              (NULL = the default stream); seed and solve synchronize.
+ *   Threads    a context is used by one host thread at a time.
+ */
+#ifndef RPCA_H
+#define RPCA_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct rpca_ctx *rpca_ctx_t;
+
+/* Status codes. */
+enum {
+    RPCA_OK = 0,
+    RPCA_WARN_NOT_CONVERGED = 1, /* some regression or the seed missed its stopping test */
+    RPCA_WARN_RANK = 2,          /* rank of the recovered seed differs from the target r */
+    RPCA_ERR_ARG = -1,           /* invalid argument (null, size, layout, indices)        */
+    RPCA_ERR_NOMEM = -2,         /* device workspace could not be allocated              */
+    RPCA_ERR_DEVICE = -3,        /* HIP / rocSOLVER runtime error                         */
+    RPCA_ERR_SEED = -4,          /* the seed PCP returned rank 0                          */
+    RPCA_ERR_NUMERIC = -5,       /* non-finite value in the input                         */
+    RPCA_ERR_UNSUPPORTED = -6    /* shape outside what the kernels were built for        */
+};
+
+/*
+ * Constants of the method.  The paper fixes s_r = s_c = 10 (Sec. 3.1) and
+ * lambda~ = 1/sqrt(max(p, q)) (eq. SPCP); it leaves eps, rho, beta_0 and
+ * beta_bar of Algorithm 1 ("eps > 0, rho > 1, beta_bar >> beta_0 > 0") and
+ * the seed solver's constants open.  rpca_opts_default() gives the values
+ * this library uses; they match the FP64 reference used by the tests.
+ */
+typedef struct {
+    int32_t os_r, os_c;          /* oversampling s_r, s_c: p = os_r*r, q = os_c*r (10, 10) */
+    double seed_lambda;          /* <= 0: 1/sqrt(max(p, q))                                */
+    double seed_tol;             /* stop when ||M^s-L-S||_F/||M^s||_F < seed_tol (1e-9)    */
+    double seed_rho;             /* mu_{k+1} = min(seed_rho*mu_k, mu_bar) (1.5)             */
+    double seed_mu0_scale;       /* mu_0 = seed_mu0_scale / ||M^s||_2 (1.25)                */
+    double seed_mu_max_scale;    /* mu_bar = seed_mu_max_scale * mu_0 (1e7)                 */
+    int32_t seed_max_iter;       /* (500)                                                   */
+    double seed_rank_floor;      /* drop thresholded sigma_i <= floor*sigma_1 (1e-6)        */
+    double filt_eps;             /* Alg. 1 eps, on ||x-Az-e||_inf/||x||_inf (1e-9)          */
+    double filt_rho;             /* Alg. 1 rho (1.5)                                        */
+    double filt_beta0_scale;     /* beta_0 = filt_beta0_scale/||x||_2 per regression (1.25) */
+    double filt_beta_max_scale;  /* beta_bar = filt_beta_max_scale*beta_0 (1e10)            */
+    int32_t filt_max_iter;       /* (500)                                                   */
+    int32_t filt_refresh;        /* recompute x - A z from x every this many steps (8)      */
+    uint64_t rng_seed;           /* seed of rpca_sample_indices inside rpca_solve           */
+    int32_t precision;           /* 0 = FP32 throughout the filter (only value for now)     */
+} rpca_opts;
+
+/* What rpca_solve reports. */
+typedef struct {
+    int32_t r_used;              /* rank of the recovered seed that was used                */
+    int32_t seed_iters;          /* ALM iterations of the seed PCP                          */
+    int32_t seed_converged;      /* 1 if the seed met seed_tol                              */
+    int32_t filt_iters_max;      /* largest iteration count over all regressions            */
+    int64_t filt_iters_total;    /* sum of iteration counts (|count| for unconverged ones)  */
+    int64_t filt_not_converged;  /* number of regressions that missed filt_eps              */
+    double t_seed_ms;            /* wall time of step 2 (seed)                              */
+    double t_filter_ms;          /* device time of steps 3 + 4                              */
+    double t_reconstruct_ms;     /* device time of step 5                                   */
+} rpca_info;
+
+/* Fill *opts with the defaults listed above. */
+void rpca_opts_default(rpca_opts *opts);
+
+/* Create a context on HIP device `device`.  *ctx receives the handle.
+ * Errors: RPCA_ERR_ARG (null ctx, bad device), RPCA_ERR_DEVICE. */
+int rpca_ctx_create(int device, rpca_ctx_t *ctx);
+
+/* Destroy a context and free its workspace (not caller memory). */
+int rpca_ctx_destroy(rpca_ctx_t ctx);
+
+/* Text of the last status set on ctx ("" after success); valid until the
+ * next call on ctx.  With ctx == NULL, the last error of a failed create. */
+const char *rpca_last_error(rpca_ctx_t ctx);
+
+/* Name of a status code. */
+const char *rpca_status_string(int status);
+
+/*
+ * Step 1 (Sec. 3.1; Algorithm 2, step 1): draw p distinct rows of m and q
+ * distinct columns of n, uniformly without replacement, into HOST arrays
+ * rows[p], cols[q], each sorted ascending.  The draw is a partial
+ * Fisher-Yates shuffle driven by SplitMix64 (Steele, Lea, Flood, OOPSLA 2014)
+ * seeded with `seed`; the same seed gives the same indices on every machine.
+ * Errors: RPCA_ERR_ARG unless 1 <= p <= m, 1 <= q <= n and arrays non-null.
+ */
+int rpca_sample_indices(int64_t m, int64_t n, int64_t p, int64_t q, uint64_t seed,
+                        int64_t *rows, int64_t *cols);
+
+/*
+ * Step 2 (Sec. 3.1, eq. SPCP; Sec. 3.2 for the factors): solve
+ *   min ||L^s||_* + lambda~ ||S^s||_1  s.t.  M^s = L^s + S^s
+ * on M^s = M[seed_rows, seed_cols] (p x q) by the inexact augmented Lagrange
+ * multiplier method with singular value thresholding (Sec. 2, eqs. Proxy,
+ * SVT), in FP64 on the device (SVD by rocSOLVER).  From the final
+ * thresholding step, U (p x r_used, ld p), sigma (r_used) and V (q x r_used,
+ * ld q) are the skinny SVD of L^s (singular values already shrunk).
+ *   M          device FP32, m x n, leading dimension ldm >= m.
+ *   seed_rows  device int64[p], sorted, distinct, in [0, m).
+ *   seed_cols  device int64[q], sorted, distinct, in [0, n).
+ *   r          target rank; U, sigma, V are caller buffers for r columns.
+ *   U, sigma, V  device FP64 outputs; columns beyond r_used are zeroed.
+ *   r_used, seed_iters  host outputs (may be NULL).
+ * Synchronous.  Returns RPCA_WARN_RANK when rank(L^s) != r (when larger, the
+ * r leading components are kept), RPCA_WARN_NOT_CONVERGED when seed_tol was
+ * not met, RPCA_ERR_SEED when rank(L^s) = 0, RPCA_ERR_NUMERIC on a
+ * non-finite entry of M^s.
+ */
+int rpca_seed(rpca_ctx_t ctx, const float *M, int64_t m, int64_t n, int64_t ldm,
+              const int64_t *seed_rows, int64_t p, const int64_t *seed_cols, int64_t q,
+              int32_t r, const rpca_opts *opts, double *U, double *sigma, double *V,
+              int32_t *r_used, int32_t *seed_iters);
+
+/*
+ * Step 3 (Sec. 3.2, eq. l1c'; Algorithm 1): for each k < nc, with j = cols[k],
+ * solve min ||M[seed_rows, j] - U q||_1 and write q to Qt[:, k].
+ *   seed_rows  device int64[p], distinct, in [0, m) (the rows U is indexed by).
+ *   cols       device int64[nc], in [0, n) (normally the sorted complement of
+ *              the seed columns; any columns may be filtered).
+ *   U          device FP64, p x r, ld p, orthonormal columns.
+ *   Qt         device FP32 output, r x nc, ld r.
+ *   iters      device int32[nc] output or NULL: iterations used; -filt_max_iter
+ *              when the stopping test was not met (then Qt holds the last
+ *              iterate); 0 for an all-zero column.
+ * Asynchronous on `stream`.  Returns RPCA_ERR_UNSUPPORTED for p or r beyond
+ * the built kernel classes (p <= 304, r <= 64 with p*r bounded by LDS).
+ */
+int rpca_filter_cols(rpca_ctx_t ctx, const float *M, int64_t m, int64_t n, int64_t ldm,
+                     const int64_t *seed_rows, int64_t p, const int64_t *cols, int64_t nc,
+                     const double *U, int32_t r, const rpca_opts *opts, float *Qt,
+                     int32_t *iters, hipStream_t stream);
+
+/*
+ * Step 4 (Sec. 3.2, eq. l1r'): M^r = P~^T V^T + S^r transposes to
+ * (M^r)^T = V P~ + (S^r)^T, so for each k < nr, with i = rows[k], solve
+ * min ||M[i, seed_cols]^T - V p||_1 and write p to Pt[:, k].
+ *   seed_cols  device int64[q], distinct, in [0, n).
+ *   rows       device int64[nr], in [0, m) (normally the complement of the
+ *              seed rows).
+ *   V          device FP64, q x r, ld q, orthonormal columns.
+ *   Pt         device FP32 output, r x nr, ld r.   iters as for columns.
+ */
+int rpca_filter_rows(rpca_ctx_t ctx, const float *M, int64_t m, int64_t n, int64_t ldm,
+                     const int64_t *seed_cols, int64_t q, const int64_t *rows, int64_t nr,
+                     const double *V, int32_t r, const rpca_opts *opts, float *Pt,
+                     int32_t *iters, hipStream_t stream);
+
+/*
+ * Steps 3 and 4 together (Sec. 3.3: the two steps of Algorithm 2 are
+ * independent and may run in parallel): the column regressions of `cols`
+ * against U and the row regressions of `rows` against V, enqueued as one
+ * launch so that both families share the device.  Arguments mean what they
+ * mean in rpca_filter_cols (seed_rows, p, cols, nc, U, Qt, col_iters) and
+ * rpca_filter_rows (seed_cols, q, rows, nr, V, Pt, row_iters); either family
+ * may be empty (nc = 0 or nr = 0).  Asynchronous on `stream`.
+ */
+int rpca_filter(rpca_ctx_t ctx, const float *M, int64_t m, int64_t n, int64_t ldm,
+                const int64_t *seed_rows, int64_t p, const int64_t *seed_cols, int64_t q,
+                const int64_t *cols, int64_t nc, const int64_t *rows, int64_t nr,
+                const double *U, const double *V, int32_t r, const rpca_opts *opts, float *Qt,
+                int32_t *col_iters, float *Pt, int32_t *row_iters, hipStream_t stream);
+
+/*
+ * Step 5 (Sec. 3.2, eqs. row-column-recovery, l1s, l1s'; Algorithm 2,
+ * output): write the whole low-rank part
+ *   L[I_s, J_s] = U Sigma V^T,   L[I_s, J_c] = U Q~,
+ *   L[I_c, J_s] = P~^T V^T,      L[I_c, J_c] = P~^T Sigma^{-1} Q~,
+ * and S = M - L, where I_c, J_c are the sorted complements of the seed
+ * indices.  Qt (r x (n-q), ld r) holds the column filtering of the sorted
+ * J_c, Pt (r x (m-p), ld r) the row filtering of the sorted I_c.
+ *   seed_rows, seed_cols  device int64, sorted ascending, distinct.
+ *   U, sigma, V           device FP64 seed factors (sigma > 0).
+ *   L, S                  device FP32 outputs, m x n, ld ldl / lds >= m.
+ *                         L and S must not overlap M or each other.
+ * Asynchronous on `stream`.
+ */
+int rpca_reconstruct(rpca_ctx_t ctx, const float *M, int64_t m, int64_t n, int64_t ldm,
+                     const int64_t *seed_rows, int64_t p, const int64_t *seed_cols,
+                     int64_t q, const double *U, const double *sigma, const double *V,
+                     int32_t r, const float *Qt, const float *Pt, float *L, int64_t ldl,
+                     float *S, int64_t lds, hipStream_t stream);
+
+/*
+ * Algorithm 2 end to end on M (m x n): steps 1-5 with target rank r.
+ * seed_rows / seed_cols: device int64 arrays of os_r*r and os_c*r sorted
+ * indices, or both NULL to draw them with rpca_sample_indices(opts->rng_seed).
+ * L, S: device FP32 outputs.  info (host, may be NULL) receives the summary.
+ * Synchronous.  Returns the most severe status of the steps.
+ */
+int rpca_solve(rpca_ctx_t ctx, const float *M, int64_t m, int64_t n, int64_t ldm, int32_t r,
+               const rpca_opts *opts, const int64_t *seed_rows, const int64_t *seed_cols,
+               float *L, int64_t ldl, float *S, int64_t lds, rpca_info *info,
+               hipStream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RPCA_H */

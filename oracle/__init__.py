@@ -346,6 +346,9 @@ class SolveResult:
     L: np.ndarray | None
     S: np.ndarray | None
     seed: SeedResult
+    U: np.ndarray       # seed factors actually used (at most r columns)
+    sigma: np.ndarray
+    V: np.ndarray
     Qt: np.ndarray
     Pt: np.ndarray
     col_iters: np.ndarray
@@ -367,15 +370,19 @@ def solve(M: np.ndarray, r: int, seed_rows, seed_cols, seed_params: SeedParams =
     J = np.asarray(seed_cols, dtype=np.int64)
     Ms = np.asarray(M[np.ix_(I, J)], dtype=np.float64)
     seed = seed_pcp(Ms, seed_params)
+    # Reading: the target rank r is known (Sec. 3.6 opens with that
+    # assumption); a seed of larger rank keeps its r leading components.
+    k = min(seed.rank, r)
+    U, sigma, V = seed.U[:, :k], seed.sigma[:k], seed.V[:, :k]
     Jc = complement(J, n)
     Ic = complement(I, m)
-    Qt, kc = filter_cols(M, I, Jc, seed.U, alg1_params, nthreads)
-    Pt, kr = filter_rows(M, J, Ic, seed.V, alg1_params, nthreads)
+    Qt, kc = filter_cols(M, I, Jc, U, alg1_params, nthreads)
+    Pt, kr = filter_rows(M, J, Ic, V, alg1_params, nthreads)
     L = S = None
     if assemble:
-        L, S = complete(M, I, J, seed.U, seed.sigma, seed.V, Qt, Pt)
-    return SolveResult(L=L, S=S, seed=seed, Qt=Qt, Pt=Pt, col_iters=kc, row_iters=kr,
-                       seed_rows=I, seed_cols=J)
+        L, S = complete(M, I, J, U, sigma, V, Qt, Pt)
+    return SolveResult(L=L, S=S, seed=seed, U=U, sigma=sigma, V=V, Qt=Qt, Pt=Pt,
+                       col_iters=kc, row_iters=kr, seed_rows=I, seed_cols=J)
 
 
 # ---------------------------------------------------------------------------

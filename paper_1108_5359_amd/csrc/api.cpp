@@ -1,0 +1,547 @@
+// Host runtime of librpca: argument checks, index sampling, workspace, and
+// the order of the steps of Algorithm 2.  All arithmetic of the method runs
+// in the HIP kernels (filter.hip, reconstruct.hip) and the FP64 seed solver
+// (seed.hip).
+#include "rpca_internal.h"
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+namespace {
+
+thread_local std::string g_create_error;
+
+bool finite_pos(double v) { return std::isfinite(v) && v > 0; }
+
+int check_opts(rpca_ctx *ctx, const rpca_opts &o)
+{
+    if (o.os_r < 1 || o.os_c < 1) return set_status(ctx, RPCA_ERR_ARG, "opts: oversampling must be >= 1");
+    if (!(o.filt_eps >= 0 && o.filt_eps < 1)) return set_status(ctx, RPCA_ERR_ARG, "opts: filt_eps must be in [0, 1)");
+    if (!(o.filt_rho >= 1) || !std::isfinite(o.filt_rho)) return set_status(ctx, RPCA_ERR_ARG, "opts: filt_rho must be >= 1");
+    if (!finite_pos(o.filt_beta0_scale) || !(o.filt_beta_max_scale >= 1) || !std::isfinite(o.filt_beta_max_scale))
+        return set_status(ctx, RPCA_ERR_ARG, "opts: bad beta scales");
+    if (o.filt_max_iter < 1) return set_status(ctx, RPCA_ERR_ARG, "opts: filt_max_iter must be >= 1");
+    if (o.filt_refresh < 0) return set_status(ctx, RPCA_ERR_ARG, "opts: filt_refresh must be >= 0");
+    if (!finite_pos(o.seed_tol) || !(o.seed_rho >= 1) || !finite_pos(o.seed_mu0_scale) ||
+        !(o.seed_mu_max_scale >= 1) || o.seed_max_iter < 1 || !(o.seed_rank_floor >= 0))
+        return set_status(ctx, RPCA_ERR_ARG, "opts: bad seed constants");
+    if (o.precision != 0) return set_status(ctx, RPCA_ERR_UNSUPPORTED, "opts: precision mode not built");
+    return RPCA_OK;
+}
+
+int check_matrix(rpca_ctx *ctx, const void *M, int64_t m, int64_t n, int64_t ld, const char *name)
+{
+    if (!M) return set_status(ctx, RPCA_ERR_ARG, std::string(name) + " is NULL");
+    if (m < 1 || n < 1) return set_status(ctx, RPCA_ERR_ARG, std::string(name) + ": sizes must be >= 1");
+    if (ld < m) return set_status(ctx, RPCA_ERR_ARG, std::string(name) + ": leading dimension < rows");
+    return RPCA_OK;
+}
+
+// Sorted, distinct, in [0, bound): checked on a host copy.
+int check_sorted_indices(rpca_ctx *ctx, const int64_t *dev, int64_t count, int64_t bound,
+                         const char *name, std::vector<int64_t> *host_out)
+{
+    std::vector<int64_t> h((size_t)count);
+    RPCA_HIP_TRY(ctx, hipMemcpy(h.data(), dev, (size_t)count * sizeof(int64_t), hipMemcpyDeviceToHost));
+    for (int64_t i = 0; i < count; ++i) {
+        if (h[i] < 0 || h[i] >= bound)
+            return set_status(ctx, RPCA_ERR_ARG, std::string(name) + ": index out of range");
+        if (i > 0 && h[i] <= h[i - 1])
+            return set_status(ctx, RPCA_ERR_ARG, std::string(name) + ": indices must be sorted and distinct");
+    }
+    if (host_out) host_out->swap(h);
+    return RPCA_OK;
+}
+
+FilterConsts consts_of(const rpca_opts &o)
+{
+    FilterConsts c;
+    c.eps = (float)o.filt_eps;
+    c.rho = (float)o.filt_rho;
+    c.beta0_scale = (float)o.filt_beta0_scale;
+    c.beta_max_scale = (float)o.filt_beta_max_scale;
+    c.max_iter = o.filt_max_iter;
+    c.refresh = o.filt_refresh;
+    return c;
+}
+
+uint64_t splitmix64_next(uint64_t &state)
+{
+    uint64_t z = (state += 0x9E3779B97F4A7C15ull);
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+// Uniform integer in [0, bound) by rejection (no modulo bias).
+uint64_t uniform_below(uint64_t &state, uint64_t bound)
+{
+    const uint64_t limit = UINT64_MAX - (UINT64_MAX % bound);
+    uint64_t v;
+    do v = splitmix64_next(state);
+    while (v >= limit);
+    return v % bound;
+}
+
+// k distinct values of [0, n), sorted: partial Fisher-Yates on a sparse map.
+void sample_sorted(int64_t n, int64_t k, uint64_t &state, int64_t *out)
+{
+    std::vector<std::pair<int64_t, int64_t>> swapped;   // position -> value, small
+    auto get = [&](int64_t pos) {
+        for (auto &pv : swapped)
+            if (pv.first == pos) return pv.second;
+        return pos;
+    };
+    auto set = [&](int64_t pos, int64_t val) {
+        for (auto &pv : swapped)
+            if (pv.first == pos) { pv.second = val; return; }
+        swapped.emplace_back(pos, val);
+    };
+    for (int64_t i = 0; i < k; ++i) {
+        const int64_t jdx = i + (int64_t)uniform_below(state, (uint64_t)(n - i));
+        const int64_t vi = get(i), vj = get(jdx);
+        set(i, vj);
+        set(jdx, vi);
+        out[i] = vj;
+    }
+    std::sort(out, out + k);
+}
+
+std::vector<int64_t> complement_of(const std::vector<int64_t> &sorted_idx, int64_t bound)
+{
+    std::vector<int64_t> c;
+    c.reserve((size_t)(bound - (int64_t)sorted_idx.size()));
+    size_t a = 0;
+    for (int64_t i = 0; i < bound; ++i) {
+        if (a < sorted_idx.size() && sorted_idx[a] == i) ++a;
+        else c.push_back(i);
+    }
+    return c;
+}
+
+} // namespace
+
+int set_status(rpca_ctx *ctx, int status, const std::string &msg)
+{
+    if (ctx) ctx->last_error = msg;
+    return status;
+}
+
+int ensure_buf(rpca_ctx *ctx, DevBuf &buf, size_t bytes)
+{
+    if (buf.bytes >= bytes) return RPCA_OK;
+    if (buf.ptr) {
+        (void)hipFree(buf.ptr);
+        buf.ptr = nullptr;
+        buf.bytes = 0;
+    }
+    const size_t want = bytes + bytes / 4 + 4096;
+    if (hipMalloc(&buf.ptr, want) != hipSuccess) {
+        buf.ptr = nullptr;
+        (void)hipGetLastError();
+        return set_status(ctx, RPCA_ERR_NOMEM, "workspace allocation of " + std::to_string(want) + " bytes failed");
+    }
+    buf.bytes = want;
+    return RPCA_OK;
+}
+
+extern "C" {
+
+void rpca_opts_default(rpca_opts *o)
+{
+    if (!o) return;
+    std::memset(o, 0, sizeof(*o));
+    o->os_r = 10;
+    o->os_c = 10;
+    o->seed_lambda = 0.0;
+    o->seed_tol = 1e-9;
+    o->seed_rho = 1.5;
+    o->seed_mu0_scale = 1.25;
+    o->seed_mu_max_scale = 1e7;
+    o->seed_max_iter = 500;
+    o->seed_rank_floor = 1e-6;
+    o->filt_eps = 1e-9;
+    o->filt_rho = 1.5;
+    o->filt_beta0_scale = 1.25;
+    o->filt_beta_max_scale = 1e10;
+    o->filt_max_iter = 500;
+    o->filt_refresh = 8;
+    o->rng_seed = 1;
+    o->precision = 0;
+}
+
+const char *rpca_status_string(int s)
+{
+    switch (s) {
+    case RPCA_OK: return "RPCA_OK";
+    case RPCA_WARN_NOT_CONVERGED: return "RPCA_WARN_NOT_CONVERGED";
+    case RPCA_WARN_RANK: return "RPCA_WARN_RANK";
+    case RPCA_ERR_ARG: return "RPCA_ERR_ARG";
+    case RPCA_ERR_NOMEM: return "RPCA_ERR_NOMEM";
+    case RPCA_ERR_DEVICE: return "RPCA_ERR_DEVICE";
+    case RPCA_ERR_SEED: return "RPCA_ERR_SEED";
+    case RPCA_ERR_NUMERIC: return "RPCA_ERR_NUMERIC";
+    case RPCA_ERR_UNSUPPORTED: return "RPCA_ERR_UNSUPPORTED";
+    default: return "RPCA_UNKNOWN_STATUS";
+    }
+}
+
+int rpca_ctx_create(int device, rpca_ctx_t *out)
+{
+    if (!out) return RPCA_ERR_ARG;
+    *out = nullptr;
+    int count = 0;
+    if (hipGetDeviceCount(&count) != hipSuccess || count < 1) {
+        (void)hipGetLastError();
+        g_create_error = "no HIP device";
+        return RPCA_ERR_DEVICE;
+    }
+    if (device < 0 || device >= count) {
+        g_create_error = "device index out of range";
+        return RPCA_ERR_ARG;
+    }
+    if (hipSetDevice(device) != hipSuccess) {
+        g_create_error = "hipSetDevice failed";
+        return RPCA_ERR_DEVICE;
+    }
+    rpca_ctx *ctx = new rpca_ctx();
+    ctx->device = device;
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, device) == hipSuccess) {
+        ctx->num_cu = prop.multiProcessorCount;
+        ctx->max_lds = prop.sharedMemPerBlock;
+        if (prop.maxSharedMemoryPerMultiProcessor > ctx->max_lds)
+            ctx->max_lds = prop.maxSharedMemoryPerMultiProcessor;
+    }
+    if (rocblas_create_handle(&ctx->blas) != rocblas_status_success) {
+        delete ctx;
+        g_create_error = "rocblas_create_handle failed";
+        return RPCA_ERR_DEVICE;
+    }
+    for (auto &e : ctx->ev) {
+        if (hipEventCreate(&e) != hipSuccess) {
+            g_create_error = "hipEventCreate failed";
+            rpca_ctx_destroy(ctx);
+            return RPCA_ERR_DEVICE;
+        }
+    }
+    *out = ctx;
+    return RPCA_OK;
+}
+
+int rpca_ctx_destroy(rpca_ctx_t ctx)
+{
+    if (!ctx) return RPCA_ERR_ARG;
+    (void)hipSetDevice(ctx->device);
+    (void)hipDeviceSynchronize();
+    for (DevBuf *b : {&ctx->seed_ws, &ctx->factors, &ctx->solve_ws, &ctx->scratch})
+        if (b->ptr) (void)hipFree(b->ptr);
+    for (auto &e : ctx->ev)
+        if (e) (void)hipEventDestroy(e);
+    if (ctx->blas) rocblas_destroy_handle(ctx->blas);
+    delete ctx;
+    return RPCA_OK;
+}
+
+const char *rpca_last_error(rpca_ctx_t ctx)
+{
+    return ctx ? ctx->last_error.c_str() : g_create_error.c_str();
+}
+
+int rpca_sample_indices(int64_t m, int64_t n, int64_t p, int64_t q, uint64_t seed, int64_t *rows,
+                        int64_t *cols)
+{
+    if (!rows || !cols || p < 1 || q < 1 || p > m || q > n) return RPCA_ERR_ARG;
+    uint64_t state = seed;
+    sample_sorted(m, p, state, rows);
+    sample_sorted(n, q, state, cols);
+    return RPCA_OK;
+}
+
+int rpca_seed(rpca_ctx_t ctx, const float *M, int64_t m, int64_t n, int64_t ldm,
+              const int64_t *seed_rows, int64_t p, const int64_t *seed_cols, int64_t q, int32_t r,
+              const rpca_opts *opts, double *U, double *sigma, double *V, int32_t *r_used,
+              int32_t *seed_iters)
+{
+    if (!ctx) return RPCA_ERR_ARG;
+    ctx->last_error.clear();
+    int st;
+    if ((st = check_matrix(ctx, M, m, n, ldm, "M")) != RPCA_OK) return st;
+    if (!opts || !seed_rows || !seed_cols || !U || !sigma || !V)
+        return set_status(ctx, RPCA_ERR_ARG, "seed: NULL argument");
+    if ((st = check_opts(ctx, *opts)) != RPCA_OK) return st;
+    if (r < 1 || p < 1 || q < 1 || p > m || q > n || r > std::min(p, q))
+        return set_status(ctx, RPCA_ERR_ARG, "seed: need 1 <= r <= min(p, q), p <= m, q <= n");
+    RPCA_HIP_TRY(ctx, hipSetDevice(ctx->device));
+    if ((st = check_sorted_indices(ctx, seed_rows, p, m, "seed_rows", nullptr)) != RPCA_OK) return st;
+    if ((st = check_sorted_indices(ctx, seed_cols, q, n, "seed_cols", nullptr)) != RPCA_OK) return st;
+    SeedOut so;
+    st = run_seed(ctx, M, ldm, seed_rows, p, seed_cols, q, r, *opts, U, sigma, V, &so, nullptr);
+    if (r_used) *r_used = so.r_used;
+    if (seed_iters) *seed_iters = so.iters;
+    return st;
+}
+
+static int make_side(rpca_ctx_t ctx, const float *M, int64_t m, int64_t n, int64_t ldm,
+                     const int64_t *elem_idx, int64_t ne, const int64_t *reg_idx, int64_t nreg,
+                     const double *A, int32_t r, float *Z, int32_t *iters, bool rows_mode,
+                     FilterSide *s)
+{
+    const int64_t ebound = rows_mode ? n : m, rbound = rows_mode ? m : n;
+    if (!elem_idx || !A || (nreg > 0 && (!reg_idx || !Z)))
+        return set_status(ctx, RPCA_ERR_ARG, "filter: NULL argument");
+    if (ne < 1 || ne > ebound || r < 1 || r > ne || nreg < 0)
+        return set_status(ctx, RPCA_ERR_ARG, "filter: need 1 <= r <= p <= dimension and nreg >= 0");
+    if (ne > INT32_MAX) return set_status(ctx, RPCA_ERR_ARG, "filter: p too large");
+    if (!filter_supported(ctx, (int)ne, r))
+        return set_status(ctx, RPCA_ERR_UNSUPPORTED, "filter: p = " + std::to_string(ne) + ", r = " +
+                                                         std::to_string(r) + " outside the built kernel classes");
+    *s = FilterSide{M, elem_idx, reg_idx, rows_mode ? ldm : 1, rows_mode ? 1 : ldm, ebound, rbound,
+                    A, (int32_t)ne, (int32_t)ne, r, nreg, Z, r, iters};
+    return RPCA_OK;
+}
+
+int rpca_filter(rpca_ctx_t ctx, const float *M, int64_t m, int64_t n, int64_t ldm,
+                const int64_t *seed_rows, int64_t p, const int64_t *seed_cols, int64_t q,
+                const int64_t *cols, int64_t nc, const int64_t *rows, int64_t nr, const double *U,
+                const double *V, int32_t r, const rpca_opts *opts, float *Qt, int32_t *col_iters,
+                float *Pt, int32_t *row_iters, hipStream_t stream)
+{
+    if (!ctx) return RPCA_ERR_ARG;
+    ctx->last_error.clear();
+    int st;
+    if ((st = check_matrix(ctx, M, m, n, ldm, "M")) != RPCA_OK) return st;
+    if (!opts) return set_status(ctx, RPCA_ERR_ARG, "filter: NULL opts");
+    if ((st = check_opts(ctx, *opts)) != RPCA_OK) return st;
+    FilterSide sides[2];
+    int ns = 0;
+    if (nc > 0) {
+        if ((st = make_side(ctx, M, m, n, ldm, seed_rows, p, cols, nc, U, r, Qt, col_iters, false,
+                            &sides[ns])) != RPCA_OK)
+            return st;
+        ++ns;
+    }
+    if (nr > 0) {
+        if ((st = make_side(ctx, M, m, n, ldm, seed_cols, q, rows, nr, V, r, Pt, row_iters, true,
+                            &sides[ns])) != RPCA_OK)
+            return st;
+        ++ns;
+    }
+    if (nc < 0 || nr < 0) return set_status(ctx, RPCA_ERR_ARG, "filter: negative count");
+    if (ns == 0) return RPCA_OK;
+    RPCA_HIP_TRY(ctx, hipSetDevice(ctx->device));
+    const FilterConsts c = consts_of(*opts);
+    if (ns == 2 && !filter_same_class(sides[0].p, sides[0].r, sides[1].p, sides[1].r)) {
+        if ((st = launch_filter(ctx, &sides[0], 1, c, stream)) != RPCA_OK) return st;
+        return launch_filter(ctx, &sides[1], 1, c, stream);
+    }
+    return launch_filter(ctx, sides, ns, c, stream);
+}
+
+static int filter_common(rpca_ctx_t ctx, const float *M, int64_t m, int64_t n, int64_t ldm,
+                         const int64_t *elem_idx, int64_t ne, const int64_t *reg_idx, int64_t nreg,
+                         const double *A, int32_t r, const rpca_opts *opts, float *Z,
+                         int32_t *iters, hipStream_t stream, bool rows_mode)
+{
+    if (!ctx) return RPCA_ERR_ARG;
+    ctx->last_error.clear();
+    int st;
+    if ((st = check_matrix(ctx, M, m, n, ldm, "M")) != RPCA_OK) return st;
+    if (!opts || !elem_idx || !A || (nreg > 0 && (!reg_idx || !Z)))
+        return set_status(ctx, RPCA_ERR_ARG, "filter: NULL argument");
+    if ((st = check_opts(ctx, *opts)) != RPCA_OK) return st;
+    const int64_t ebound = rows_mode ? n : m, rbound = rows_mode ? m : n;
+    if (ne < 1 || ne > ebound || r < 1 || r > ne || nreg < 0)
+        return set_status(ctx, RPCA_ERR_ARG, "filter: need 1 <= r <= p <= dimension and nreg >= 0");
+    if (ne > INT32_MAX) return set_status(ctx, RPCA_ERR_ARG, "filter: p too large");
+    if (!filter_supported(ctx, (int)ne, r))
+        return set_status(ctx, RPCA_ERR_UNSUPPORTED, "filter: p = " + std::to_string(ne) + ", r = " +
+                                                         std::to_string(r) + " outside the built kernel classes");
+    if (nreg == 0) return RPCA_OK;
+    RPCA_HIP_TRY(ctx, hipSetDevice(ctx->device));
+    FilterSide s{};
+    s.M = M;
+    s.elem_idx = elem_idx;
+    s.reg_idx = reg_idx;
+    s.elem_stride = rows_mode ? ldm : 1;
+    s.reg_stride = rows_mode ? 1 : ldm;
+    s.elem_bound = ebound;
+    s.reg_bound = rbound;
+    s.A = A;
+    s.lda = (int32_t)ne;
+    s.p = (int32_t)ne;
+    s.r = r;
+    s.nreg = nreg;
+    s.Z = Z;
+    s.ldz = r;
+    s.iters = iters;
+    return launch_filter(ctx, &s, 1, consts_of(*opts), stream);
+}
+
+int rpca_filter_cols(rpca_ctx_t ctx, const float *M, int64_t m, int64_t n, int64_t ldm,
+                     const int64_t *seed_rows, int64_t p, const int64_t *cols, int64_t nc,
+                     const double *U, int32_t r, const rpca_opts *opts, float *Qt, int32_t *iters,
+                     hipStream_t stream)
+{
+    return filter_common(ctx, M, m, n, ldm, seed_rows, p, cols, nc, U, r, opts, Qt, iters, stream,
+                         false);
+}
+
+int rpca_filter_rows(rpca_ctx_t ctx, const float *M, int64_t m, int64_t n, int64_t ldm,
+                     const int64_t *seed_cols, int64_t q, const int64_t *rows, int64_t nr,
+                     const double *V, int32_t r, const rpca_opts *opts, float *Pt, int32_t *iters,
+                     hipStream_t stream)
+{
+    return filter_common(ctx, M, m, n, ldm, seed_cols, q, rows, nr, V, r, opts, Pt, iters, stream,
+                         true);
+}
+
+int rpca_reconstruct(rpca_ctx_t ctx, const float *M, int64_t m, int64_t n, int64_t ldm,
+                     const int64_t *seed_rows, int64_t p, const int64_t *seed_cols, int64_t q,
+                     const double *U, const double *sigma, const double *V, int32_t r,
+                     const float *Qt, const float *Pt, float *L, int64_t ldl, float *S, int64_t lds,
+                     hipStream_t stream)
+{
+    if (!ctx) return RPCA_ERR_ARG;
+    ctx->last_error.clear();
+    int st;
+    if ((st = check_matrix(ctx, M, m, n, ldm, "M")) != RPCA_OK) return st;
+    if ((st = check_matrix(ctx, L, m, n, ldl, "L")) != RPCA_OK) return st;
+    if ((st = check_matrix(ctx, S, m, n, lds, "S")) != RPCA_OK) return st;
+    if (!seed_rows || !seed_cols || !U || !sigma || !V || (n > q && !Qt) || (m > p && !Pt))
+        return set_status(ctx, RPCA_ERR_ARG, "reconstruct: NULL argument");
+    if (p < 1 || q < 1 || p > m || q > n || r < 1 || r > std::min(p, q))
+        return set_status(ctx, RPCA_ERR_ARG, "reconstruct: need 1 <= r <= min(p, q), p <= m, q <= n");
+    if ((const void *)L == (const void *)S || (const void *)L == (const void *)M ||
+        (const void *)S == (const void *)M)
+        return set_status(ctx, RPCA_ERR_ARG, "reconstruct: L, S and M must be distinct buffers");
+    RPCA_HIP_TRY(ctx, hipSetDevice(ctx->device));
+    ReconArgs a{M, m, n, ldm, seed_rows, p, seed_cols, q, U, sigma, V, r, Qt, Pt, L, ldl, S, lds};
+    return launch_reconstruct(ctx, a, stream);
+}
+
+int rpca_solve(rpca_ctx_t ctx, const float *M, int64_t m, int64_t n, int64_t ldm, int32_t r,
+               const rpca_opts *opts, const int64_t *seed_rows, const int64_t *seed_cols, float *L,
+               int64_t ldl, float *S, int64_t lds, rpca_info *info, hipStream_t stream)
+{
+    if (!ctx) return RPCA_ERR_ARG;
+    ctx->last_error.clear();
+    int st;
+    if ((st = check_matrix(ctx, M, m, n, ldm, "M")) != RPCA_OK) return st;
+    if ((st = check_matrix(ctx, L, m, n, ldl, "L")) != RPCA_OK) return st;
+    if ((st = check_matrix(ctx, S, m, n, lds, "S")) != RPCA_OK) return st;
+    if (!opts) return set_status(ctx, RPCA_ERR_ARG, "solve: NULL opts");
+    if ((st = check_opts(ctx, *opts)) != RPCA_OK) return st;
+    if (r < 1) return set_status(ctx, RPCA_ERR_ARG, "solve: r must be >= 1");
+    if ((const void *)L == (const void *)S || (const void *)L == (const void *)M ||
+        (const void *)S == (const void *)M)
+        return set_status(ctx, RPCA_ERR_ARG, "solve: L, S and M must be distinct buffers");
+    const int64_t p = (int64_t)opts->os_r * r, q = (int64_t)opts->os_c * r;
+    if (p > m || q > n) return set_status(ctx, RPCA_ERR_ARG, "solve: seed block larger than M");
+    if ((seed_rows == nullptr) != (seed_cols == nullptr))
+        return set_status(ctx, RPCA_ERR_ARG, "solve: give both seed index arrays or neither");
+    if (!filter_supported(ctx, (int)std::max(p, q), r) || !filter_supported(ctx, (int)std::min(p, q), r))
+        return set_status(ctx, RPCA_ERR_UNSUPPORTED, "solve: seed size outside the built kernel classes");
+    RPCA_HIP_TRY(ctx, hipSetDevice(ctx->device));
+
+    // Step 1: seed indices (host), their complements, and device copies.
+    std::vector<int64_t> I((size_t)p), J((size_t)q);
+    if (seed_rows) {
+        if ((st = check_sorted_indices(ctx, seed_rows, p, m, "seed_rows", &I)) != RPCA_OK) return st;
+        if ((st = check_sorted_indices(ctx, seed_cols, q, n, "seed_cols", &J)) != RPCA_OK) return st;
+    } else {
+        rpca_sample_indices(m, n, p, q, opts->rng_seed, I.data(), J.data());
+    }
+    const std::vector<int64_t> Ic = complement_of(I, m), Jc = complement_of(J, n);
+    const int64_t mc = (int64_t)Ic.size(), nc = (int64_t)Jc.size();
+    // workspace layout: I, J, Ic, Jc (int64) | U (p x r), sigma, V (q x r) (f64) |
+    //                   Qt (r x nc), Pt (r x mc) (f32) | iters (nc + mc, i32)
+    const size_t n_idx = (size_t)(p + q + mc + nc);
+    const size_t n_f64 = (size_t)((p + q) * r + r);
+    const size_t n_f32 = (size_t)(r * (nc + mc));
+    const size_t bytes = n_idx * 8 + n_f64 * 8 + n_f32 * 4 + (size_t)(nc + mc) * 4 + 256;
+    if ((st = ensure_buf(ctx, ctx->solve_ws, bytes)) != RPCA_OK) return st;
+    char *base = static_cast<char *>(ctx->solve_ws.ptr);
+    int64_t *dI = reinterpret_cast<int64_t *>(base);
+    int64_t *dJ = dI + p, *dIc = dJ + q, *dJc = dIc + mc;
+    double *dU = reinterpret_cast<double *>(dJc + nc);
+    double *dsig = dU + p * r, *dV = dsig + r;
+    float *dQt = reinterpret_cast<float *>(dV + q * r);
+    float *dPt = dQt + r * nc;
+    int32_t *dit = reinterpret_cast<int32_t *>(dPt + r * mc);
+
+    hipStream_t sm = stream;
+    RPCA_HIP_TRY(ctx, hipMemcpyAsync(dI, I.data(), p * 8, hipMemcpyHostToDevice, sm));
+    RPCA_HIP_TRY(ctx, hipMemcpyAsync(dJ, J.data(), q * 8, hipMemcpyHostToDevice, sm));
+    if (mc) RPCA_HIP_TRY(ctx, hipMemcpyAsync(dIc, Ic.data(), mc * 8, hipMemcpyHostToDevice, sm));
+    if (nc) RPCA_HIP_TRY(ctx, hipMemcpyAsync(dJc, Jc.data(), nc * 8, hipMemcpyHostToDevice, sm));
+
+    // Step 2: seed.
+    const auto t0 = std::chrono::steady_clock::now();
+    SeedOut so;
+    const int seed_st = run_seed(ctx, M, ldm, dI, p, dJ, q, r, *opts, dU, dsig, dV, &so, sm);
+    const auto t1 = std::chrono::steady_clock::now();
+    if (seed_st < 0) return seed_st;
+    const std::string seed_msg = ctx->last_error;
+    const int ru = so.r_used;
+
+    // Steps 3 and 4 in one launch, then step 5.
+    FilterSide sides[2]{};
+    int ns = 0;
+    if (nc) {
+        FilterSide &s = sides[ns++];
+        s = FilterSide{M, dI, dJc, 1, ldm, m, n, dU, (int32_t)p, (int32_t)p, ru, nc, dQt, ru, dit};
+    }
+    if (mc) {
+        FilterSide &s = sides[ns++];
+        s = FilterSide{M, dJ, dIc, ldm, 1, n, m, dV, (int32_t)q, (int32_t)q, ru, mc, dPt, ru, dit + nc};
+    }
+    const FilterConsts c = consts_of(*opts);
+    RPCA_HIP_TRY(ctx, hipEventRecord(ctx->ev[0], sm));
+    if (ns == 2 && !filter_same_class(sides[0].p, sides[0].r, sides[1].p, sides[1].r)) {
+        // different size classes: two launches
+        if ((st = launch_filter(ctx, &sides[0], 1, c, sm)) != RPCA_OK) return st;
+        if ((st = launch_filter(ctx, &sides[1], 1, c, sm)) != RPCA_OK) return st;
+    } else if (ns > 0) {
+        if ((st = launch_filter(ctx, sides, ns, c, sm)) != RPCA_OK) return st;
+    }
+    RPCA_HIP_TRY(ctx, hipEventRecord(ctx->ev[1], sm));
+    ReconArgs a{M, m, n, ldm, dI, p, dJ, q, dU, dsig, dV, ru, dQt, dPt, L, ldl, S, lds};
+    if ((st = launch_reconstruct(ctx, a, sm)) != RPCA_OK) return st;
+    RPCA_HIP_TRY(ctx, hipEventRecord(ctx->ev[2], sm));
+
+    std::vector<int32_t> its((size_t)(nc + mc));
+    if (!its.empty())
+        RPCA_HIP_TRY(ctx, hipMemcpyAsync(its.data(), dit, its.size() * 4, hipMemcpyDeviceToHost, sm));
+    RPCA_HIP_TRY(ctx, hipStreamSynchronize(sm));
+    int64_t total = 0, bad = 0;
+    int32_t kmax = 0;
+    for (int32_t k : its) {
+        if (k < 0) ++bad;
+        const int32_t ak = k < 0 ? -k : k;
+        total += ak;
+        kmax = std::max(kmax, ak);
+    }
+    if (info) {
+        float tf = 0, tr = 0;
+        (void)hipEventElapsedTime(&tf, ctx->ev[0], ctx->ev[1]);
+        (void)hipEventElapsedTime(&tr, ctx->ev[1], ctx->ev[2]);
+        info->r_used = ru;
+        info->seed_iters = so.iters;
+        info->seed_converged = so.converged;
+        info->filt_iters_max = kmax;
+        info->filt_iters_total = total;
+        info->filt_not_converged = bad;
+        info->t_seed_ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
+        info->t_filter_ms = tf;
+        info->t_reconstruct_ms = tr;
+    }
+    if (seed_st > 0) return set_status(ctx, seed_st, seed_msg);
+    if (bad) return set_status(ctx, RPCA_WARN_NOT_CONVERGED, std::to_string(bad) + " regressions missed filt_eps");
+    return RPCA_OK;
+}
+
+} // extern "C"

@@ -1,0 +1,186 @@
+// Completion of L and S = M - L (Algorithm 2, step 5 and output).
+//
+// The four blocks of L (eqs. partition, row-column-recovery, l1s, l1s')
+//   L[I_s,J_s] = U Sigma V^T,  L[I_s,J_c] = U Q~,
+//   L[I_c,J_s] = P~^T V^T,     L[I_c,J_c] = P~^T Sigma^{-1} Q~
+// are one rank-r product L = F G^T over the whole matrix once the row factor
+// F (m x r) and column factor G (n x r) are assembled as
+//   F[I_s] = U Sigma,  F[I_c] = P~^T,   G[J_s] = V,  G[J_c] = Q~^T Sigma^{-1}.
+// (The pseudo-inverse of L^s = U Sigma V^T is V Sigma^{-1} U^T, so the
+// Nystrom block needs only r FP64 reciprocals.)  The product is HBM bound
+// (12 bytes per element: read M, write L and S, for 2r flops), so one pass
+// streams M with non-temporal loads, keeps the row factor of 4 rows per lane
+// in VGPRs and the column factor in scalar registers (uniform across the
+// wave), and writes L and S with non-temporal stores.
+#include "rpca_internal.h"
+
+#include <climits>
+
+namespace {
+
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+
+// Index of the first element >= key in the sorted array a[0..n).
+__device__ __forceinline__ int64_t lower_bound_i64(const int64_t *a, int64_t n, int64_t key)
+{
+    int64_t lo = 0, hi = n;
+    while (lo < hi) {
+        const int64_t mid = (lo + hi) >> 1;
+        if (a[mid] < key) lo = mid + 1;
+        else hi = mid;
+    }
+    return lo;
+}
+
+// F: m x R4 row-major, G: n x R4 row-major, zero-padded to R4 >= r.
+__global__ void assemble_factors(const int64_t *__restrict__ seed_rows, int64_t p,
+                                 const int64_t *__restrict__ seed_cols, int64_t q,
+                                 const double *__restrict__ U, const double *__restrict__ sigma,
+                                 const double *__restrict__ V, int r,
+                                 const float *__restrict__ Qt, const float *__restrict__ Pt,
+                                 int64_t m, int64_t n, int R4, float *__restrict__ F,
+                                 float *__restrict__ G)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < m) {
+        const int64_t i = t;
+        const int64_t a = lower_bound_i64(seed_rows, p, i);
+        float *f = F + i * R4;
+        if (a < p && seed_rows[a] == i) {
+            for (int k = 0; k < R4; ++k) f[k] = k < r ? (float)(U[a + (int64_t)k * p] * sigma[k]) : 0.0f;
+        } else {
+            const int64_t b = i - a;   // position of i in the sorted complement
+            const bool ok = b >= 0 && b < m - p;
+            for (int k = 0; k < R4; ++k) f[k] = (ok && k < r) ? Pt[k + b * r] : 0.0f;
+        }
+    } else if (t < m + n) {
+        const int64_t jj = t - m;
+        const int64_t a = lower_bound_i64(seed_cols, q, jj);
+        float *gp = G + jj * R4;
+        if (a < q && seed_cols[a] == jj) {
+            for (int k = 0; k < R4; ++k) gp[k] = k < r ? (float)V[a + (int64_t)k * q] : 0.0f;
+        } else {
+            const int64_t b = jj - a;
+            const bool ok = b >= 0 && b < n - q;
+            for (int k = 0; k < R4; ++k)
+                gp[k] = (ok && k < r) ? (float)((double)Qt[k + b * r] / sigma[k]) : 0.0f;
+        }
+    }
+}
+
+constexpr int kRowsPerLane = 4;
+constexpr int kRowsPerWave = 64 * kRowsPerLane;
+constexpr int kColsPerWave = 32;
+
+// One wave computes a 256-row x 32-column tile of L and S.
+template <int R4, bool VEC>
+__global__ void __launch_bounds__(64)
+reconstruct_kernel(const float *__restrict__ M, int64_t ldm, const float *__restrict__ F,
+                   const float *__restrict__ G, int64_t m, int64_t n, float *__restrict__ Lo,
+                   int64_t ldl, float *__restrict__ So, int64_t lds)
+{
+    const int lane = threadIdx.x;
+    const int64_t i0 = (int64_t)blockIdx.x * kRowsPerWave + lane * kRowsPerLane;
+    const int64_t j0 = (int64_t)blockIdx.y * kColsPerWave;
+
+    float f[kRowsPerLane][R4];
+#pragma unroll
+    for (int rr = 0; rr < kRowsPerLane; ++rr) {
+        const int64_t i = i0 + rr;
+#pragma unroll
+        for (int k = 0; k < R4; k += 4) {
+            floatx4 v = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
+            if (i < m) v = *reinterpret_cast<const floatx4 *>(F + i * R4 + k);
+            f[rr][k] = v[0];
+            f[rr][k + 1] = v[1];
+            f[rr][k + 2] = v[2];
+            f[rr][k + 3] = v[3];
+        }
+    }
+    const int64_t jend = (j0 + kColsPerWave < n) ? j0 + kColsPerWave : n;
+    const bool full_rows = i0 + kRowsPerLane <= m;
+    for (int64_t j = j0; j < jend; ++j) {
+        const float *gj = G + j * R4;     // uniform across the wave
+        float acc[kRowsPerLane] = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+        for (int k = 0; k < R4; ++k) {
+            const float gk = gj[k];
+#pragma unroll
+            for (int rr = 0; rr < kRowsPerLane; ++rr) acc[rr] = fmaf(f[rr][k], gk, acc[rr]);
+        }
+        if (VEC && full_rows) {
+            const floatx4 mv = __builtin_nontemporal_load(
+                reinterpret_cast<const floatx4 *>(M + j * ldm + i0));
+            const floatx4 lv = floatx4{acc[0], acc[1], acc[2], acc[3]};
+            __builtin_nontemporal_store(lv, reinterpret_cast<floatx4 *>(Lo + j * ldl + i0));
+            __builtin_nontemporal_store(mv - lv, reinterpret_cast<floatx4 *>(So + j * lds + i0));
+        } else {
+#pragma unroll
+            for (int rr = 0; rr < kRowsPerLane; ++rr) {
+                const int64_t i = i0 + rr;
+                if (i < m) {
+                    const float mv = M[j * ldm + i];
+                    Lo[j * ldl + i] = acc[rr];
+                    So[j * lds + i] = mv - acc[rr];
+                }
+            }
+        }
+    }
+}
+
+template <int R4>
+int launch_r4(rpca_ctx *ctx, const ReconArgs &a, const float *F, const float *G, bool vec,
+              hipStream_t stream)
+{
+    const dim3 grid((unsigned)((a.m + kRowsPerWave - 1) / kRowsPerWave),
+                    (unsigned)((a.n + kColsPerWave - 1) / kColsPerWave));
+    if (vec)
+        hipLaunchKernelGGL((reconstruct_kernel<R4, true>), grid, dim3(64), 0, stream, a.M, a.ldm, F,
+                           G, a.m, a.n, a.L, a.ldl, a.S, a.lds);
+    else
+        hipLaunchKernelGGL((reconstruct_kernel<R4, false>), grid, dim3(64), 0, stream, a.M, a.ldm,
+                           F, G, a.m, a.n, a.L, a.ldl, a.S, a.lds);
+    RPCA_HIP_TRY(ctx, hipGetLastError());
+    return RPCA_OK;
+}
+
+} // namespace
+
+int launch_reconstruct(rpca_ctx *ctx, const ReconArgs &a, hipStream_t stream)
+{
+    const int R4 = (a.r + 3) / 4 * 4;
+    if (R4 > 64) return set_status(ctx, RPCA_ERR_UNSUPPORTED, "reconstruct: rank above 64");
+    const size_t fbytes = (size_t)(a.m + a.n) * R4 * sizeof(float);
+    int st = ensure_buf(ctx, ctx->factors, fbytes);
+    if (st != RPCA_OK) return st;
+    float *F = static_cast<float *>(ctx->factors.ptr);
+    float *G = F + (size_t)a.m * R4;
+    const int64_t nthreads = a.m + a.n;
+    hipLaunchKernelGGL(assemble_factors, dim3((unsigned)((nthreads + 255) / 256)), dim3(256), 0,
+                       stream, a.seed_rows, a.p, a.seed_cols, a.q, a.U, a.sigma, a.V, a.r, a.Qt,
+                       a.Pt, a.m, a.n, R4, F, G);
+    RPCA_HIP_TRY(ctx, hipGetLastError());
+
+    const bool vec = (a.ldm % 4 == 0) && (a.ldl % 4 == 0) && (a.lds % 4 == 0) &&
+                     ((uintptr_t)a.M % 16 == 0) && ((uintptr_t)a.L % 16 == 0) &&
+                     ((uintptr_t)a.S % 16 == 0);
+    switch (R4) {
+    case 4: return launch_r4<4>(ctx, a, F, G, vec, stream);
+    case 8: return launch_r4<8>(ctx, a, F, G, vec, stream);
+    case 12: return launch_r4<12>(ctx, a, F, G, vec, stream);
+    case 16: return launch_r4<16>(ctx, a, F, G, vec, stream);
+    case 20: return launch_r4<20>(ctx, a, F, G, vec, stream);
+    case 24: return launch_r4<24>(ctx, a, F, G, vec, stream);
+    case 28: return launch_r4<28>(ctx, a, F, G, vec, stream);
+    case 32: return launch_r4<32>(ctx, a, F, G, vec, stream);
+    case 36: return launch_r4<36>(ctx, a, F, G, vec, stream);
+    case 40: return launch_r4<40>(ctx, a, F, G, vec, stream);
+    case 44: return launch_r4<44>(ctx, a, F, G, vec, stream);
+    case 48: return launch_r4<48>(ctx, a, F, G, vec, stream);
+    case 52: return launch_r4<52>(ctx, a, F, G, vec, stream);
+    case 56: return launch_r4<56>(ctx, a, F, G, vec, stream);
+    case 60: return launch_r4<60>(ctx, a, F, G, vec, stream);
+    case 64: return launch_r4<64>(ctx, a, F, G, vec, stream);
+    default: return set_status(ctx, RPCA_ERR_UNSUPPORTED, "reconstruct: rank class not built");
+    }
+}

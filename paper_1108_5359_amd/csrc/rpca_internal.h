@@ -1,0 +1,113 @@
+// Internal declarations shared by the host runtime (api.cpp) and the HIP
+// kernels (filter.hip, reconstruct.hip, seed.hip) of librpca.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <rocblas/rocblas.h>
+
+#include <cstdint>
+#include <string>
+
+#include "../../include/rpca.h"
+
+// Grow-only device buffer owned by a context.
+struct DevBuf {
+    void *ptr = nullptr;
+    size_t bytes = 0;
+};
+
+struct rpca_ctx {
+    int device = 0;
+    int num_cu = 0;
+    size_t max_lds = 0;
+    std::string last_error;
+    rocblas_handle blas = nullptr;
+    hipEvent_t ev[6] = {};
+    DevBuf seed_ws;     // FP64 matrices of the seed solver
+    DevBuf factors;     // F (m x R4) and G (n x R4), FP32, for the completion
+    DevBuf solve_ws;    // indices and filter outputs inside rpca_solve
+    DevBuf scratch;     // small reductions / flags
+};
+
+// Set ctx->last_error and return status.
+int set_status(rpca_ctx *ctx, int status, const std::string &msg);
+
+// Make sure buf holds at least `bytes`; returns RPCA_OK or RPCA_ERR_NOMEM.
+int ensure_buf(rpca_ctx *ctx, DevBuf &buf, size_t bytes);
+
+#define RPCA_HIP_TRY(ctx, expr)                                                        \
+    do {                                                                               \
+        hipError_t _e = (expr);                                                        \
+        if (_e != hipSuccess)                                                          \
+            return set_status((ctx), RPCA_ERR_DEVICE,                                  \
+                              std::string(#expr ": ") + hipGetErrorString(_e));        \
+    } while (0)
+
+// ---------------------------------------------------------------- filter
+// One family of independent regressions: element e of regression k is
+// M[elem_idx[e] * elem_stride + reg_idx[k] * reg_stride], regressed on the
+// p x r FP64 basis A (ld lda); the coefficients go to Z[:, k] (ld ldz).
+struct FilterSide {
+    const float *M;
+    const int64_t *elem_idx;
+    const int64_t *reg_idx;
+    int64_t elem_stride;
+    int64_t reg_stride;
+    int64_t elem_bound;   // valid element indices are [0, elem_bound)
+    int64_t reg_bound;    // valid regression indices are [0, reg_bound)
+    const double *A;
+    int32_t lda;
+    int32_t p;
+    int32_t r;
+    int64_t nreg;
+    float *Z;
+    int64_t ldz;
+    int32_t *iters;
+};
+
+struct FilterConsts {
+    float eps, rho, beta0_scale, beta_max_scale;
+    int32_t max_iter, refresh;
+};
+
+// Enqueue the regressions of up to two sides (same p class and r class) in
+// one launch.  Returns an RPCA status.
+int launch_filter(rpca_ctx *ctx, const FilterSide *sides, int nsides, const FilterConsts &c,
+                  hipStream_t stream);
+
+// Whether launch_filter supports (p, r).
+bool filter_supported(rpca_ctx *ctx, int p, int r);
+
+// Whether two (p, r) pairs use the same kernel and can share one launch.
+bool filter_same_class(int p0, int r0, int p1, int r1);
+
+// ---------------------------------------------------------------- completion
+struct ReconArgs {
+    const float *M;
+    int64_t m, n, ldm;
+    const int64_t *seed_rows;
+    int64_t p;
+    const int64_t *seed_cols;
+    int64_t q;
+    const double *U, *sigma, *V;
+    int32_t r;
+    const float *Qt, *Pt;
+    float *L;
+    int64_t ldl;
+    float *S;
+    int64_t lds;
+};
+
+int launch_reconstruct(rpca_ctx *ctx, const ReconArgs &a, hipStream_t stream);
+
+// ---------------------------------------------------------------- seed
+struct SeedOut {
+    int32_t r_used = 0;
+    int32_t iters = 0;
+    int32_t converged = 0;
+    int32_t rank_found = 0;
+};
+
+int run_seed(rpca_ctx *ctx, const float *M, int64_t ldm, const int64_t *seed_rows, int64_t p,
+             const int64_t *seed_cols, int64_t q, int32_t r, const rpca_opts &o, double *U,
+             double *sigma, double *V, SeedOut *out, hipStream_t stream);

@@ -1,0 +1,219 @@
+"""ctypes binding of librpca (``include/rpca.h``): argument marshalling only.
+
+Every function has the name and argument order of the C entry point.  Device
+buffers are torch tensors on the context's device (used only as device memory
+and for their streams); layouts are column-major, so an m x n matrix with
+leading dimension ld is a row-major torch tensor of shape (n, ld).  Negative
+statuses raise :class:`RpcaError`; positive statuses (warnings) are returned.
+
+There is no fallback: if ``librpca.so`` has not been built, importing this
+module raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import pathlib
+
+import numpy as np
+
+_LIB_PATH = pathlib.Path(__file__).resolve().parent / "librpca.so"
+if not _LIB_PATH.exists():
+    raise ImportError(f"{_LIB_PATH} is not built; run __graft_entry__.build() or "
+                      "python paper_1108_5359_amd/build.py")
+lib = ctypes.CDLL(str(_LIB_PATH))
+
+RPCA_OK = 0
+RPCA_WARN_NOT_CONVERGED = 1
+RPCA_WARN_RANK = 2
+RPCA_ERR_ARG = -1
+RPCA_ERR_NOMEM = -2
+RPCA_ERR_DEVICE = -3
+RPCA_ERR_SEED = -4
+RPCA_ERR_NUMERIC = -5
+RPCA_ERR_UNSUPPORTED = -6
+
+
+class rpca_opts(ctypes.Structure):
+    _fields_ = [
+        ("os_r", ctypes.c_int32), ("os_c", ctypes.c_int32),
+        ("seed_lambda", ctypes.c_double), ("seed_tol", ctypes.c_double),
+        ("seed_rho", ctypes.c_double), ("seed_mu0_scale", ctypes.c_double),
+        ("seed_mu_max_scale", ctypes.c_double), ("seed_max_iter", ctypes.c_int32),
+        ("seed_rank_floor", ctypes.c_double),
+        ("filt_eps", ctypes.c_double), ("filt_rho", ctypes.c_double),
+        ("filt_beta0_scale", ctypes.c_double), ("filt_beta_max_scale", ctypes.c_double),
+        ("filt_max_iter", ctypes.c_int32), ("filt_refresh", ctypes.c_int32),
+        ("rng_seed", ctypes.c_uint64), ("precision", ctypes.c_int32),
+    ]
+
+
+class rpca_info(ctypes.Structure):
+    _fields_ = [
+        ("r_used", ctypes.c_int32), ("seed_iters", ctypes.c_int32),
+        ("seed_converged", ctypes.c_int32), ("filt_iters_max", ctypes.c_int32),
+        ("filt_iters_total", ctypes.c_int64), ("filt_not_converged", ctypes.c_int64),
+        ("t_seed_ms", ctypes.c_double), ("t_filter_ms", ctypes.c_double),
+        ("t_reconstruct_ms", ctypes.c_double),
+    ]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+_vp = ctypes.c_void_p
+_i64 = ctypes.c_int64
+_i32 = ctypes.c_int32
+
+lib.rpca_opts_default.argtypes = [ctypes.POINTER(rpca_opts)]
+lib.rpca_opts_default.restype = None
+lib.rpca_ctx_create.argtypes = [ctypes.c_int, ctypes.POINTER(_vp)]
+lib.rpca_ctx_destroy.argtypes = [_vp]
+lib.rpca_last_error.argtypes = [_vp]
+lib.rpca_last_error.restype = ctypes.c_char_p
+lib.rpca_status_string.argtypes = [ctypes.c_int]
+lib.rpca_status_string.restype = ctypes.c_char_p
+lib.rpca_sample_indices.argtypes = [_i64, _i64, _i64, _i64, ctypes.c_uint64, _vp, _vp]
+lib.rpca_seed.argtypes = [_vp, _vp, _i64, _i64, _i64, _vp, _i64, _vp, _i64, _i32,
+                          ctypes.POINTER(rpca_opts), _vp, _vp, _vp,
+                          ctypes.POINTER(_i32), ctypes.POINTER(_i32)]
+lib.rpca_filter_cols.argtypes = [_vp, _vp, _i64, _i64, _i64, _vp, _i64, _vp, _i64, _vp, _i32,
+                                 ctypes.POINTER(rpca_opts), _vp, _vp, _vp]
+lib.rpca_filter_rows.argtypes = lib.rpca_filter_cols.argtypes
+lib.rpca_filter.argtypes = [_vp, _vp, _i64, _i64, _i64, _vp, _i64, _vp, _i64, _vp, _i64, _vp, _i64,
+                            _vp, _vp, _i32, ctypes.POINTER(rpca_opts), _vp, _vp, _vp, _vp, _vp]
+lib.rpca_reconstruct.argtypes = [_vp, _vp, _i64, _i64, _i64, _vp, _i64, _vp, _i64, _vp, _vp,
+                                 _vp, _i32, _vp, _vp, _vp, _i64, _vp, _i64, _vp]
+lib.rpca_solve.argtypes = [_vp, _vp, _i64, _i64, _i64, _i32, ctypes.POINTER(rpca_opts), _vp,
+                           _vp, _vp, _i64, _vp, _i64, ctypes.POINTER(rpca_info), _vp]
+for _f in ("rpca_ctx_create", "rpca_ctx_destroy", "rpca_sample_indices", "rpca_seed",
+           "rpca_filter", "rpca_filter_cols", "rpca_filter_rows", "rpca_reconstruct", "rpca_solve"):
+    getattr(lib, _f).restype = ctypes.c_int
+
+
+class RpcaError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{rpca_status_string(status)}: {message}")
+        self.status = status
+
+
+def rpca_status_string(status: int) -> str:
+    return lib.rpca_status_string(int(status)).decode()
+
+
+def rpca_opts_default(**overrides) -> rpca_opts:
+    o = rpca_opts()
+    lib.rpca_opts_default(ctypes.byref(o))
+    for k, v in overrides.items():
+        if not hasattr(o, k):
+            raise AttributeError(k)
+        setattr(o, k, v)
+    return o
+
+
+class Context:
+    """Owns an ``rpca_ctx_t`` on one device."""
+
+    def __init__(self, device: int = 0):
+        h = _vp()
+        st = lib.rpca_ctx_create(int(device), ctypes.byref(h))
+        if st != RPCA_OK:
+            raise RpcaError(st, lib.rpca_last_error(None).decode())
+        self.handle = h
+        self.device = device
+
+    def close(self):
+        if self.handle:
+            lib.rpca_ctx_destroy(self.handle)
+            self.handle = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def check(self, st: int) -> int:
+        if st < 0:
+            raise RpcaError(st, lib.rpca_last_error(self.handle).decode())
+        return st
+
+    def last_error(self) -> str:
+        return lib.rpca_last_error(self.handle).decode()
+
+
+def _ptr(t) -> int | None:
+    if t is None:
+        return None
+    return t.data_ptr()
+
+
+def _stream(stream) -> int | None:
+    if stream is None:
+        import torch
+        return torch.cuda.current_stream().cuda_stream
+    if isinstance(stream, int):
+        return stream
+    return stream.cuda_stream
+
+
+def rpca_sample_indices(m: int, n: int, p: int, q: int, seed: int):
+    rows = np.empty(p, dtype=np.int64)
+    cols = np.empty(q, dtype=np.int64)
+    st = lib.rpca_sample_indices(m, n, p, q, ctypes.c_uint64(seed), rows.ctypes.data, cols.ctypes.data)
+    if st != RPCA_OK:
+        raise RpcaError(st, "invalid sampling sizes")
+    return rows, cols
+
+
+def rpca_seed(ctx: Context, M, m, n, ldm, seed_rows, p, seed_cols, q, r, opts, U, sigma, V):
+    ru = _i32(0)
+    it = _i32(0)
+    st = ctx.check(lib.rpca_seed(ctx.handle, _ptr(M), m, n, ldm, _ptr(seed_rows), p,
+                                 _ptr(seed_cols), q, r, ctypes.byref(opts), _ptr(U), _ptr(sigma),
+                                 _ptr(V), ctypes.byref(ru), ctypes.byref(it)))
+    return st, ru.value, it.value
+
+
+def rpca_filter_cols(ctx: Context, M, m, n, ldm, seed_rows, p, cols, nc, U, r, opts, Qt, iters,
+                     stream=None):
+    return ctx.check(lib.rpca_filter_cols(ctx.handle, _ptr(M), m, n, ldm, _ptr(seed_rows), p,
+                                          _ptr(cols), nc, _ptr(U), r, ctypes.byref(opts), _ptr(Qt),
+                                          _ptr(iters), _stream(stream)))
+
+
+def rpca_filter_rows(ctx: Context, M, m, n, ldm, seed_cols, q, rows, nr, V, r, opts, Pt, iters,
+                     stream=None):
+    return ctx.check(lib.rpca_filter_rows(ctx.handle, _ptr(M), m, n, ldm, _ptr(seed_cols), q,
+                                          _ptr(rows), nr, _ptr(V), r, ctypes.byref(opts), _ptr(Pt),
+                                          _ptr(iters), _stream(stream)))
+
+
+def rpca_filter(ctx: Context, M, m, n, ldm, seed_rows, p, seed_cols, q, cols, nc, rows, nr, U, V,
+                r, opts, Qt, col_iters, Pt, row_iters, stream=None):
+    return ctx.check(lib.rpca_filter(ctx.handle, _ptr(M), m, n, ldm, _ptr(seed_rows), p,
+                                     _ptr(seed_cols), q, _ptr(cols), nc, _ptr(rows), nr, _ptr(U),
+                                     _ptr(V), r, ctypes.byref(opts), _ptr(Qt), _ptr(col_iters),
+                                     _ptr(Pt), _ptr(row_iters), _stream(stream)))
+
+
+def rpca_reconstruct(ctx: Context, M, m, n, ldm, seed_rows, p, seed_cols, q, U, sigma, V, r, Qt,
+                     Pt, L, ldl, S, lds, stream=None):
+    return ctx.check(lib.rpca_reconstruct(ctx.handle, _ptr(M), m, n, ldm, _ptr(seed_rows), p,
+                                          _ptr(seed_cols), q, _ptr(U), _ptr(sigma), _ptr(V), r,
+                                          _ptr(Qt), _ptr(Pt), _ptr(L), ldl, _ptr(S), lds,
+                                          _stream(stream)))
+
+
+def rpca_solve(ctx: Context, M, m, n, ldm, r, opts, seed_rows, seed_cols, L, ldl, S, lds,
+               stream=None):
+    info = rpca_info()
+    st = ctx.check(lib.rpca_solve(ctx.handle, _ptr(M), m, n, ldm, r, ctypes.byref(opts),
+                                  _ptr(seed_rows), _ptr(seed_cols), _ptr(L), ldl, _ptr(S), lds,
+                                  ctypes.byref(info), _stream(stream)))
+    return st, info
