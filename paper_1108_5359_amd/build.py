@@ -19,6 +19,8 @@ LIB = HERE / "librpca.so"
 BUILD = HERE / "_build"
 ROCM = pathlib.Path(os.environ.get("ROCM_PATH", "/opt/rocm"))
 SOURCES = ["api.cpp", "filter.hip", "reconstruct.hip", "seed.hip"]
+# filter_inst.hip is compiled once per tile class (one object each)
+FILTER_PT = [1, 2, 3, 4, 5, 7, 8, 10, 13, 16, 19, 26, 32]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950",
@@ -32,8 +34,8 @@ HIPCC_FLAGS = [
 ]
 
 
-def _compile(src: pathlib.Path, obj: pathlib.Path) -> None:
-    cmd = [str(ROCM / "bin" / "hipcc"), *HIPCC_FLAGS]
+def _compile(src: pathlib.Path, obj: pathlib.Path, defines=()) -> None:
+    cmd = [str(ROCM / "bin" / "hipcc"), *HIPCC_FLAGS, *defines]
     if src.suffix == ".cpp":
         cmd += ["-x", "hip"]
     cmd += ["-c", str(src), "-o", str(obj)]
@@ -55,6 +57,10 @@ def build(jobs: int | None = None) -> pathlib.Path:
     jobs = jobs or min(8, os.cpu_count() or 4)
     with concurrent.futures.ThreadPoolExecutor(max_workers=jobs) as ex:
         futs = []
+        for pt in sorted(FILTER_PT, reverse=True):     # largest first: they take longest
+            obj = BUILD / f"filter_inst_pt{pt}.o"
+            objs.append(obj)
+            futs.append(ex.submit(_compile, CSRC / "filter_inst.hip", obj, (f"-DRPCA_PT={pt}",)))
         for s in SOURCES:
             obj = BUILD / (s.replace(".", "_") + ".o")
             objs.append(obj)

@@ -28,7 +28,8 @@ int check_opts(rpca_ctx *ctx, const rpca_opts &o)
     if (!finite_pos(o.seed_tol) || !(o.seed_rho >= 1) || !finite_pos(o.seed_mu0_scale) ||
         !(o.seed_mu_max_scale >= 1) || o.seed_max_iter < 1 || !(o.seed_rank_floor >= 0))
         return set_status(ctx, RPCA_ERR_ARG, "opts: bad seed constants");
-    if (o.precision != 0) return set_status(ctx, RPCA_ERR_UNSUPPORTED, "opts: precision mode not built");
+    if (o.precision != 0 && o.precision != 1)
+        return set_status(ctx, RPCA_ERR_ARG, "opts: precision must be 0 (FP32) or 1 (FP16 + FP32 refinement)");
     return RPCA_OK;
 }
 
@@ -65,6 +66,7 @@ FilterConsts consts_of(const rpca_opts &o)
     c.beta_max_scale = (float)o.filt_beta_max_scale;
     c.max_iter = o.filt_max_iter;
     c.refresh = o.filt_refresh;
+    c.precision = o.precision;
     return c;
 }
 
@@ -237,7 +239,7 @@ int rpca_ctx_destroy(rpca_ctx_t ctx)
     if (!ctx) return RPCA_ERR_ARG;
     (void)hipSetDevice(ctx->device);
     (void)hipDeviceSynchronize();
-    for (DevBuf *b : {&ctx->seed_ws, &ctx->factors, &ctx->solve_ws, &ctx->scratch})
+    for (DevBuf *b : {&ctx->seed_ws, &ctx->factors, &ctx->solve_ws, &ctx->scratch, &ctx->frag_ws})
         if (b->ptr) (void)hipFree(b->ptr);
     for (auto &e : ctx->ev)
         if (e) (void)hipEventDestroy(e);
@@ -288,7 +290,7 @@ int rpca_seed(rpca_ctx_t ctx, const float *M, int64_t m, int64_t n, int64_t ldm,
 static int make_side(rpca_ctx_t ctx, const float *M, int64_t m, int64_t n, int64_t ldm,
                      const int64_t *elem_idx, int64_t ne, const int64_t *reg_idx, int64_t nreg,
                      const double *A, int32_t r, float *Z, int32_t *iters, bool rows_mode,
-                     FilterSide *s)
+                     int precision, FilterSide *s)
 {
     const int64_t ebound = rows_mode ? n : m, rbound = rows_mode ? m : n;
     if (!elem_idx || !A || (nreg > 0 && (!reg_idx || !Z)))
@@ -296,7 +298,7 @@ static int make_side(rpca_ctx_t ctx, const float *M, int64_t m, int64_t n, int64
     if (ne < 1 || ne > ebound || r < 1 || r > ne || nreg < 0)
         return set_status(ctx, RPCA_ERR_ARG, "filter: need 1 <= r <= p <= dimension and nreg >= 0");
     if (ne > INT32_MAX) return set_status(ctx, RPCA_ERR_ARG, "filter: p too large");
-    if (!filter_supported(ctx, (int)ne, r))
+    if (!filter_supported(ctx, (int)ne, r, precision))
         return set_status(ctx, RPCA_ERR_UNSUPPORTED, "filter: p = " + std::to_string(ne) + ", r = " +
                                                          std::to_string(r) + " outside the built kernel classes");
     *s = FilterSide{M, elem_idx, reg_idx, rows_mode ? ldm : 1, rows_mode ? 1 : ldm, ebound, rbound,
@@ -320,13 +322,13 @@ int rpca_filter(rpca_ctx_t ctx, const float *M, int64_t m, int64_t n, int64_t ld
     int ns = 0;
     if (nc > 0) {
         if ((st = make_side(ctx, M, m, n, ldm, seed_rows, p, cols, nc, U, r, Qt, col_iters, false,
-                            &sides[ns])) != RPCA_OK)
+                            opts->precision, &sides[ns])) != RPCA_OK)
             return st;
         ++ns;
     }
     if (nr > 0) {
         if ((st = make_side(ctx, M, m, n, ldm, seed_cols, q, rows, nr, V, r, Pt, row_iters, true,
-                            &sides[ns])) != RPCA_OK)
+                            opts->precision, &sides[ns])) != RPCA_OK)
             return st;
         ++ns;
     }
@@ -357,7 +359,7 @@ static int filter_common(rpca_ctx_t ctx, const float *M, int64_t m, int64_t n, i
     if (ne < 1 || ne > ebound || r < 1 || r > ne || nreg < 0)
         return set_status(ctx, RPCA_ERR_ARG, "filter: need 1 <= r <= p <= dimension and nreg >= 0");
     if (ne > INT32_MAX) return set_status(ctx, RPCA_ERR_ARG, "filter: p too large");
-    if (!filter_supported(ctx, (int)ne, r))
+    if (!filter_supported(ctx, (int)ne, r, opts->precision))
         return set_status(ctx, RPCA_ERR_UNSUPPORTED, "filter: p = " + std::to_string(ne) + ", r = " +
                                                          std::to_string(r) + " outside the built kernel classes");
     if (nreg == 0) return RPCA_OK;
@@ -443,7 +445,8 @@ int rpca_solve(rpca_ctx_t ctx, const float *M, int64_t m, int64_t n, int64_t ldm
     if (p > m || q > n) return set_status(ctx, RPCA_ERR_ARG, "solve: seed block larger than M");
     if ((seed_rows == nullptr) != (seed_cols == nullptr))
         return set_status(ctx, RPCA_ERR_ARG, "solve: give both seed index arrays or neither");
-    if (!filter_supported(ctx, (int)std::max(p, q), r) || !filter_supported(ctx, (int)std::min(p, q), r))
+    if (!filter_supported(ctx, (int)std::max(p, q), r, opts->precision) ||
+        !filter_supported(ctx, (int)std::min(p, q), r, opts->precision))
         return set_status(ctx, RPCA_ERR_UNSUPPORTED, "solve: seed size outside the built kernel classes");
     RPCA_HIP_TRY(ctx, hipSetDevice(ctx->device));
 

@@ -1,0 +1,678 @@
+// l1 filtering kernel: many independent regressions min ||x - A z||_1 with
+// A^T A = I (eq. l1g), each solved by the ADM of Algorithm 1.
+//
+// Arithmetic: the iteration is carried in the equivalent "clip" form that
+// follows from S_tau(t) = t - clip(t, -tau, tau) and A^T A = I:
+//     g     = clip(beta u + y, -1, 1)            with u = x - A z
+//     w     = A^T g,   z += w / beta,   v = A w
+//     y_new = g - v,   u -= v / beta
+//     ||x - A z_new - e_new||_inf = ||y_new - y||_inf / beta   (stopping test)
+//     beta  = min(rho beta, beta_bar)
+// It is algebraically identical to steps 1-3 of Algorithm 1 (E is never
+// formed), only the well-scaled g in [-1, 1] and w enter the contractions,
+// and u is recomputed from x every `refresh` steps to cancel FP32 drift.
+//
+// Layout on the chip (one wavefront = a tile of 16 regressions):
+//   * both contractions run on MFMA v_mfma_f32_16x16x4_f32.  The state u, y
+//     (p x 16) sits in VGPRs in the MFMA accumulator layout: lane l = 16 g + c
+//     holds rows 16 t + 4 g + v (v = 0..3) of regression column c for every
+//     16-row tile t.  That layout is directly the B operand of both
+//     contractions once the contraction index is permuted consistently in the
+//     A operand, so no data moves between lanes except two xor-shuffles for
+//     ||.||_inf per step.
+//   * A (FP64 in HBM) is converted once per workgroup into two FP32 copies in
+//     LDS, stored in "fragment order" so that each MFMA's A operand comes from
+//     one conflict-free ds_read_b128 per lane.
+//   * rank permutation: row c of output tile mt of w = A^T g holds rank
+//     16 mt + 4 (c % 4) + c / 4, so lane (g, c) register v holds rank
+//     16 mt + 4 v + g and the K-step ks = 4 mt + v of v = A w covers ranks
+//     4 ks .. 4 ks + 3: only KS = ceil(r / 4) K-steps are issued.
+//   * beta, ||x||_inf, the stopping flag and the iteration count are per
+//     regression (per lane column); a converged regression is frozen through a
+//     zero step size, never by branching around MFMA.
+//   * PT (16-row tiles of p) and KS are compile-time: the loop body is
+//     straight-line code.
+#pragma once
+
+#include "rpca_internal.h"
+
+#include <climits>
+
+namespace filterk {
+
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+
+constexpr int kWavesPerBlock = 4;
+
+struct FilterLaunch {
+    FilterSide side[2];
+    const float *frag32[2];   // precision form: FP32 refresh fragments in HBM (or null = in LDS)
+    int32_t nblocks0;         // blocks of side 0; the rest belong to side 1
+    FilterConsts c;
+};
+
+// Built classes: PT = tiles of 16 elements, KS = K-steps of 4 ranks.
+constexpr int kPT[] = {1, 2, 3, 4, 5, 7, 8, 10, 13, 16, 19};
+constexpr int kNumPT = sizeof(kPT) / sizeof(kPT[0]);
+constexpr int kKS[] = {1, 2, 3, 4, 5, 6, 8, 10, 13, 16};
+constexpr int kNumKS = sizeof(kKS) / sizeof(kKS[0]);
+
+// Precision form: more tile classes (p up to 512).
+constexpr int kPTh[] = {1, 2, 3, 4, 5, 7, 8, 10, 13, 16, 19, 26, 32};
+constexpr int kNumPTh = sizeof(kPTh) / sizeof(kPTh[0]);
+
+inline size_t lds_bytes(int PT, int KS)
+{
+    const int RT = (KS + 3) / 4;
+    return (size_t)2 * PT * RT * 256 * sizeof(float) + (size_t)PT * 16 * sizeof(int64_t);
+}
+
+// Precision form: FP16 fragments (w = A^T g over tile pairs, v = A w over
+// rank-tile pairs) plus, when ref_in_lds, the FP32 fragments of the refresh.
+inline size_t lds_bytes_f16(int PT, int KS, bool ref_in_lds)
+{
+    const int RT = (KS + 3) / 4, PP = (PT + 1) / 2, RP = (RT + 1) / 2;
+    size_t b = (size_t)PP * RT * 512 * sizeof(_Float16) + (size_t)PT * RP * 512 * sizeof(_Float16) +
+               (size_t)PT * 16 * sizeof(int64_t);
+    if (ref_in_lds) b += (size_t)PT * RT * 256 * sizeof(float);
+    return b;
+}
+
+typedef _Float16 halfx8 __attribute__((ext_vector_type(8)));
+
+__device__ __forceinline__ floatx4 mfma4(float a, float b, floatx4 acc)
+{
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc, 0, 0, 0);
+}
+
+__device__ __forceinline__ floatx4 mfma16h(halfx8 a, halfx8 b, floatx4 acc)
+{
+    return __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, acc, 0, 0, 0);
+}
+
+__device__ __forceinline__ halfx8 pack8(const float *lo, const float *hi)
+{
+    halfx8 h;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        h[i] = (_Float16)lo[i];
+        h[i + 4] = (_Float16)hi[i];
+    }
+    return h;
+}
+
+// Max / sum over the four lanes that share a regression column (c, c+16, c+32, c+48).
+__device__ __forceinline__ float colmax(float v)
+{
+    v = fmaxf(v, __shfl_xor(v, 16));
+    v = fmaxf(v, __shfl_xor(v, 32));
+    return v;
+}
+
+__device__ __forceinline__ float colsum(float v)
+{
+    v += __shfl_xor(v, 16);
+    v += __shfl_xor(v, 32);
+    return v;
+}
+
+template <int PT, int KS>
+__global__ void __launch_bounds__(kWavesPerBlock * 64)
+__attribute__((amdgpu_waves_per_eu(PT <= 13 ? 2 : 1)))
+l1_filter_kernel(FilterLaunch L)
+{
+    constexpr int RT = (KS + 3) / 4;
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+    float *fragA1 = reinterpret_cast<float *>(lds_raw);          // for w = A^T g
+    float *fragA2 = fragA1 + PT * RT * 256;                        // for v = A w, A z
+    int64_t *eoff = reinterpret_cast<int64_t *>(fragA2 + PT * RT * 256);
+
+    // Pick this block's side field by field (scalar selects on kernel
+    // arguments; no copy of the argument struct).
+    const bool second = (int)blockIdx.x >= L.nblocks0;
+#define SIDE(f) (second ? L.side[1].f : L.side[0].f)
+    const int block_in_side = second ? (int)blockIdx.x - L.nblocks0 : (int)blockIdx.x;
+    const int p = SIDE(p), r = SIDE(r);
+    const double *__restrict__ A = SIDE(A);
+    const int lda = SIDE(lda);
+    const int64_t *__restrict__ elem_idx = SIDE(elem_idx);
+    const int64_t *__restrict__ reg_idx = SIDE(reg_idx);
+    const int64_t elem_stride = SIDE(elem_stride), reg_stride = SIDE(reg_stride);
+    const int64_t elem_bound = SIDE(elem_bound), reg_bound = SIDE(reg_bound);
+    const int64_t nreg = SIDE(nreg);
+    const float *__restrict__ M = SIDE(M);
+    float *__restrict__ Zout = SIDE(Z);
+    const int64_t ldz = SIDE(ldz);
+    int32_t *__restrict__ iters = SIDE(iters);
+    floatx4 *__restrict__ xbuf = reinterpret_cast<floatx4 *>(SIDE(xbuf));
+#undef SIDE
+
+    // ---- stage the basis in LDS, in the two fragment orders -------------
+    for (int idx = threadIdx.x; idx < PT * RT * 256; idx += kWavesPerBlock * 64) {
+        const int v = idx & 3;
+        const int ln = (idx >> 2) & 63;
+        const int tm = idx >> 8;
+        const int t = tm / RT, mt = tm - t * RT;
+        const int g = ln >> 4, c = ln & 15;
+        const int e1 = 16 * t + 4 * g + v, k1 = 16 * mt + 4 * (c & 3) + (c >> 2);
+        fragA1[idx] = (e1 < p && k1 < r) ? (float)A[e1 + (int64_t)k1 * lda] : 0.0f;
+        const int e2 = 16 * t + c, k2 = 16 * mt + 4 * v + g;
+        fragA2[idx] = (e2 < p && k2 < r) ? (float)A[e2 + (int64_t)k2 * lda] : 0.0f;
+    }
+    for (int e = threadIdx.x; e < PT * 16; e += kWavesPerBlock * 64) {
+        int64_t off = -1;
+        if (e < p) {
+            const int64_t ei = elem_idx[e];
+            if (ei >= 0 && ei < elem_bound) off = ei * elem_stride;
+        }
+        eoff[e] = off;
+    }
+    __syncthreads();
+
+    const int wave = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63;
+    const int g = lane >> 4, c = lane & 15;
+    const int64_t tile = (int64_t)block_in_side * kWavesPerBlock + wave;
+    const int64_t j = tile * 16 + c;
+    if (tile * 16 >= nreg) return;     // whole wave idle (no barrier follows)
+
+    bool valid = j < nreg;
+    int64_t roff = 0;
+    if (valid) {
+        const int64_t ri = reg_idx[j];
+        if (ri >= 0 && ri < reg_bound) roff = ri * reg_stride;
+        else valid = false;
+    }
+
+    // ---- load x, its norms, and the starting state -----------------------
+    float u[PT][4], y[PT][4];
+    float xinf = 0.0f, xx = 0.0f;
+    // x is gathered once from M (random seed rows / columns) and kept in
+    // fragment order in HBM, so the refresh reads it back coalesced.
+    floatx4 *xtile = xbuf + tile * PT * 64 + lane;
+#pragma unroll
+    for (int t = 0; t < PT; ++t) {
+        floatx4 xv;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int64_t off = eoff[16 * t + 4 * g + v];
+            const float x = (valid && off >= 0) ? M[roff + off] : 0.0f;
+            xv[v] = x;
+            u[t][v] = x;
+            y[t][v] = 0.0f;
+            xinf = fmaxf(xinf, fabsf(x));
+            xx = fmaf(x, x, xx);
+        }
+        xtile[t * 64] = xv;
+    }
+    xinf = colmax(xinf);
+    xx = colsum(xx);
+
+    float beta = xx > 0.0f ? L.c.beta0_scale / sqrtf(xx) : 1.0f;
+    const float beta_bar = L.c.beta_max_scale * beta;
+    const float tol = L.c.eps * xinf;
+    bool done = !(valid && xinf > 0.0f);
+    int K = 0;
+
+    floatx4 z[RT];
+#pragma unroll
+    for (int mt = 0; mt < RT; ++mt) z[mt] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
+
+    const floatx4 *F1 = reinterpret_cast<const floatx4 *>(fragA1) + lane;
+    const floatx4 *F2 = reinterpret_cast<const floatx4 *>(fragA2) + lane;
+
+    for (int k = 0; k < L.c.max_iter; ++k) {
+        if (!__any(!done)) break;                                   // wave-uniform
+        // The basis fragments are re-read from LDS every step instead of
+        // being kept in VGPRs: that leaves room for two waves per SIMD.
+        asm volatile("" ::: "memory");
+
+        // w = A^T g, two accumulator chains (even / odd tiles) for ILP
+        floatx4 Wa[RT], Wb[RT];
+#pragma unroll
+        for (int mt = 0; mt < RT; ++mt) {
+            Wa[mt] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
+            Wb[mt] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
+        }
+#pragma unroll
+        for (int t = 0; t < PT; ++t) {
+            float gv[4];
+#pragma unroll
+            for (int v = 0; v < 4; ++v)
+                gv[v] = __builtin_amdgcn_fmed3f(fmaf(beta, u[t][v], y[t][v]), -1.0f, 1.0f);
+#pragma unroll
+            for (int mt = 0; mt < RT; ++mt) {
+                const floatx4 a = F1[(t * RT + mt) * 64];
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    if (t & 1) Wb[mt] = mfma4(a[v], gv[v], Wb[mt]);
+                    else Wa[mt] = mfma4(a[v], gv[v], Wa[mt]);
+                }
+            }
+        }
+        floatx4 W[RT];
+#pragma unroll
+        for (int mt = 0; mt < RT; ++mt) W[mt] = Wa[mt] + Wb[mt];
+
+        // A converged regression keeps z and u frozen through a zero step
+        // size; its y keeps moving but feeds nothing that is kept.
+        const float inv_beta = 1.0f / beta;
+        const float ib = done ? 0.0f : inv_beta;
+#pragma unroll
+        for (int mt = 0; mt < RT; ++mt)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) z[mt][v] = fmaf(W[mt][v], ib, z[mt][v]);
+
+        // v = A w for two tiles at a time, then the dual / residual update
+        float res = 0.0f;
+#pragma unroll
+        for (int t = 0; t < PT; t += 2) {
+            floatx4 Va = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
+            floatx4 Vb = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+            for (int mt = 0; mt < RT; ++mt) {
+                const floatx4 a0 = F2[(t * RT + mt) * 64];
+                floatx4 a1 = a0;
+                if (t + 1 < PT) a1 = F2[((t + 1) * RT + mt) * 64];
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    if (4 * mt + v < KS) {
+                        Va = mfma4(a0[v], W[mt][v], Va);
+                        if (t + 1 < PT) Vb = mfma4(a1[v], W[mt][v], Vb);
+                    }
+                }
+            }
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const int tt = t + h;
+                if (tt < PT) {
+                    const floatx4 Vt = h ? Vb : Va;
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) {
+                        // g again from the unchanged u, y (cheaper than keeping it)
+                        const float gg =
+                            __builtin_amdgcn_fmed3f(fmaf(beta, u[tt][v], y[tt][v]), -1.0f, 1.0f);
+                        const float yn = gg - Vt[v];
+                        res = fmaxf(res, fabsf(yn - y[tt][v]));
+                        u[tt][v] = fmaf(-Vt[v], ib, u[tt][v]);
+                        y[tt][v] = yn;
+                    }
+                }
+            }
+        }
+        res = colmax(res);
+        if (!done) {
+            ++K;
+            if (!(res * inv_beta >= tol)) done = true;   // ||x-Az-e||_inf < eps ||x||_inf
+        }
+        beta = fminf(L.c.rho * beta, beta_bar);
+
+        // periodic u = x - A z from the input, against FP32 drift
+        if (L.c.refresh > 0 && ((k + 1) % L.c.refresh) == 0) {
+#pragma unroll
+            for (int t = 0; t < PT; ++t) {
+                floatx4 Az = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+                for (int mt = 0; mt < RT; ++mt) {
+                    const floatx4 a = F2[(t * RT + mt) * 64];
+#pragma unroll
+                    for (int v = 0; v < 4; ++v)
+                        if (4 * mt + v < KS) Az = mfma4(a[v], z[mt][v], Az);
+                }
+                const floatx4 xv = xtile[t * 64];
+#pragma unroll
+                for (int v = 0; v < 4; ++v) u[t][v] = xv[v] - Az[v];
+            }
+        }
+    }
+
+    if (j < nreg) {
+        if (valid) {
+#pragma unroll
+            for (int mt = 0; mt < RT; ++mt)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int kk = 16 * mt + 4 * v + g;
+                    if (kk < r) Zout[kk + j * ldz] = z[mt][v];
+                }
+        }
+        if (iters && g == 0)
+            iters[j] = !valid ? INT_MIN : (done ? K : -L.c.max_iter);
+    }
+}
+
+
+// ---------------------------------------------------------------------------
+// Precision form: the two contractions on v_mfma_f32_16x16x32_f16 (FP16
+// operands, FP32 accumulation); the residual u = x - A z is recomputed from x
+// in FP32 (v_mfma_f32_16x16x4_f32) every `refresh` steps, which cancels the
+// drift of the FP16 products (FP32 residual refinement).  g in [-1, 1] and
+// the orthonormal basis fit FP16's range; z, u, y, beta stay FP32.
+//
+// Operand layouts (K = 32 per MFMA; any K order shared by A and B is exact):
+//   w = A^T g : lane (g, c) slot i <-> element 16 (2 pp + i / 4) + 4 g + i % 4
+//               (tiles 2 pp and 2 pp + 1 of the FP32 state, no data movement);
+//               A operand row c <-> rank 16 mt + 4 (c % 4) + c / 4 as before.
+//   v = A w   : lane (g, c) slot i <-> rank 16 (2 rp + i / 4) + 4 (i % 4) + g,
+//               i.e. registers v = i % 4 of W tiles 2 rp and 2 rp + 1.
+// ---------------------------------------------------------------------------
+template <int PT, int KS>
+__global__ void __launch_bounds__(kWavesPerBlock * 64)
+__attribute__((amdgpu_waves_per_eu(PT <= 13 ? 2 : 1)))
+l1_filter_kernel_f16(FilterLaunch L)
+{
+    constexpr int RT = (KS + 3) / 4;
+    constexpr int PP = (PT + 1) / 2;
+    constexpr int RP = (RT + 1) / 2;
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+    _Float16 *h1 = reinterpret_cast<_Float16 *>(lds_raw);              // [PP][RT][64][8]
+    _Float16 *h2 = h1 + PP * RT * 512;                                   // [PT][RP][64][8]
+    int64_t *eoff = reinterpret_cast<int64_t *>(h2 + PT * RP * 512);    // [PT*16]
+    float *f2lds = reinterpret_cast<float *>(eoff + PT * 16);            // [PT][RT][64][4]
+
+    const bool second = (int)blockIdx.x >= L.nblocks0;
+#define SIDE(f) (second ? L.side[1].f : L.side[0].f)
+    const int block_in_side = second ? (int)blockIdx.x - L.nblocks0 : (int)blockIdx.x;
+    const int p = SIDE(p), r = SIDE(r);
+    const double *__restrict__ A = SIDE(A);
+    const int lda = SIDE(lda);
+    const int64_t *__restrict__ elem_idx = SIDE(elem_idx);
+    const int64_t *__restrict__ reg_idx = SIDE(reg_idx);
+    const int64_t elem_stride = SIDE(elem_stride), reg_stride = SIDE(reg_stride);
+    const int64_t elem_bound = SIDE(elem_bound), reg_bound = SIDE(reg_bound);
+    const int64_t nreg = SIDE(nreg);
+    const float *__restrict__ M = SIDE(M);
+    float *__restrict__ Zout = SIDE(Z);
+    const int64_t ldz = SIDE(ldz);
+    int32_t *__restrict__ iters = SIDE(iters);
+    floatx4 *__restrict__ xbuf = reinterpret_cast<floatx4 *>(SIDE(xbuf));
+#undef SIDE
+    const float *f2glob = second ? L.frag32[1] : L.frag32[0];
+
+    // ---- stage the basis -------------------------------------------------
+    for (int idx = threadIdx.x; idx < PP * RT * 512; idx += kWavesPerBlock * 64) {
+        const int i = idx & 7, ln = (idx >> 3) & 63, pm = idx >> 9;
+        const int pp = pm / RT, mt = pm - pp * RT;
+        const int g = ln >> 4, c = ln & 15;
+        const int e = 16 * (2 * pp + (i >> 2)) + 4 * g + (i & 3);
+        const int k = 16 * mt + 4 * (c & 3) + (c >> 2);
+        h1[idx] = (_Float16)((e < p && k < r) ? A[e + (int64_t)k * lda] : 0.0);
+    }
+    for (int idx = threadIdx.x; idx < PT * RP * 512; idx += kWavesPerBlock * 64) {
+        const int i = idx & 7, ln = (idx >> 3) & 63, tr = idx >> 9;
+        const int t = tr / RP, rp = tr - t * RP;
+        const int g = ln >> 4, c = ln & 15;
+        const int e = 16 * t + c;
+        const int k = 16 * (2 * rp + (i >> 2)) + 4 * (i & 3) + g;
+        h2[idx] = (_Float16)((e < p && k < r) ? A[e + (int64_t)k * lda] : 0.0);
+    }
+    if (!f2glob) {
+        for (int idx = threadIdx.x; idx < PT * RT * 256; idx += kWavesPerBlock * 64) {
+            const int v = idx & 3, ln = (idx >> 2) & 63, tm = idx >> 8;
+            const int t = tm / RT, mt = tm - t * RT;
+            const int g = ln >> 4, c = ln & 15;
+            const int e2 = 16 * t + c, k2 = 16 * mt + 4 * v + g;
+            f2lds[idx] = (e2 < p && k2 < r) ? (float)A[e2 + (int64_t)k2 * lda] : 0.0f;
+        }
+    }
+    for (int e = threadIdx.x; e < PT * 16; e += kWavesPerBlock * 64) {
+        int64_t off = -1;
+        if (e < p) {
+            const int64_t ei = elem_idx[e];
+            if (ei >= 0 && ei < elem_bound) off = ei * elem_stride;
+        }
+        eoff[e] = off;
+    }
+    __syncthreads();
+
+    const int wave = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63;
+    const int g = lane >> 4, c = lane & 15;
+    const int64_t tile = (int64_t)block_in_side * kWavesPerBlock + wave;
+    const int64_t j = tile * 16 + c;
+    if (tile * 16 >= nreg) return;     // whole wave idle (no barrier follows)
+
+    bool valid = j < nreg;
+    int64_t roff = 0;
+    if (valid) {
+        const int64_t ri = reg_idx[j];
+        if (ri >= 0 && ri < reg_bound) roff = ri * reg_stride;
+        else valid = false;
+    }
+
+    float u[PT][4], y[PT][4];
+    float xinf = 0.0f, xx = 0.0f;
+    // x is gathered once from M (random seed rows / columns) and kept in
+    // fragment order in HBM, so the refresh reads it back coalesced.
+    floatx4 *xtile = xbuf + tile * PT * 64 + lane;
+#pragma unroll
+    for (int t = 0; t < PT; ++t) {
+        floatx4 xv;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int64_t off = eoff[16 * t + 4 * g + v];
+            const float x = (valid && off >= 0) ? M[roff + off] : 0.0f;
+            xv[v] = x;
+            u[t][v] = x;
+            y[t][v] = 0.0f;
+            xinf = fmaxf(xinf, fabsf(x));
+            xx = fmaf(x, x, xx);
+        }
+        xtile[t * 64] = xv;
+    }
+    xinf = colmax(xinf);
+    xx = colsum(xx);
+
+    float beta = xx > 0.0f ? L.c.beta0_scale / sqrtf(xx) : 1.0f;
+    const float beta_bar = L.c.beta_max_scale * beta;
+    const float tol = L.c.eps * xinf;
+    bool done = !(valid && xinf > 0.0f);
+    int K = 0;
+
+    floatx4 z[RT];
+#pragma unroll
+    for (int mt = 0; mt < RT; ++mt) z[mt] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
+
+    const halfx8 *H1 = reinterpret_cast<const halfx8 *>(h1) + lane;
+    const halfx8 *H2 = reinterpret_cast<const halfx8 *>(h2) + lane;
+    const floatx4 *F2 = f2glob ? reinterpret_cast<const floatx4 *>(f2glob) + lane
+                               : reinterpret_cast<const floatx4 *>(f2lds) + lane;
+
+    for (int k = 0; k < L.c.max_iter; ++k) {
+        if (!__any(!done)) break;                                   // wave-uniform
+        asm volatile("" ::: "memory");
+
+        // w = A^T g over tile pairs (K = 32 elements per MFMA)
+        floatx4 Wa[RT], Wb[RT];
+#pragma unroll
+        for (int mt = 0; mt < RT; ++mt) {
+            Wa[mt] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
+            Wb[mt] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
+        }
+#pragma unroll
+        for (int pp = 0; pp < PP; ++pp) {
+            float glo[4], ghi[4];
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                glo[v] = __builtin_amdgcn_fmed3f(fmaf(beta, u[2 * pp][v], y[2 * pp][v]), -1.0f, 1.0f);
+                ghi[v] = (2 * pp + 1 < PT)
+                    ? __builtin_amdgcn_fmed3f(fmaf(beta, u[2 * pp + 1 < PT ? 2 * pp + 1 : 0][v],
+                                                   y[2 * pp + 1 < PT ? 2 * pp + 1 : 0][v]), -1.0f, 1.0f)
+                    : 0.0f;
+            }
+            const halfx8 gb = pack8(glo, ghi);
+#pragma unroll
+            for (int mt = 0; mt < RT; ++mt) {
+                const halfx8 a = H1[(pp * RT + mt) * 64];
+                // one rank tile: alternate two chains for ILP; several: one chain each
+                if (RT == 1 && (pp & 1)) Wb[mt] = mfma16h(a, gb, Wb[mt]);
+                else Wa[mt] = mfma16h(a, gb, Wa[mt]);
+            }
+        }
+        floatx4 W[RT];
+#pragma unroll
+        for (int mt = 0; mt < RT; ++mt) W[mt] = (RT == 1) ? Wa[mt] + Wb[mt] : Wa[mt];
+
+        const float inv_beta = 1.0f / beta;
+        const float ib = done ? 0.0f : inv_beta;
+#pragma unroll
+        for (int mt = 0; mt < RT; ++mt)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) z[mt][v] = fmaf(W[mt][v], ib, z[mt][v]);
+
+        // w as the FP16 B operand of v = A w, rank-tile pairs
+        halfx8 wb[RP];
+#pragma unroll
+        for (int rp = 0; rp < RP; ++rp) {
+            float lo[4], hi[4];
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                lo[v] = W[2 * rp][v];
+                hi[v] = (2 * rp + 1 < RT) ? W[2 * rp + 1 < RT ? 2 * rp + 1 : 0][v] : 0.0f;
+            }
+            wb[rp] = pack8(lo, hi);
+        }
+
+        float res = 0.0f;
+#pragma unroll
+        for (int t = 0; t < PT; t += 2) {
+            floatx4 Va = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
+            floatx4 Vb = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+            for (int rp = 0; rp < RP; ++rp) {
+                Va = mfma16h(H2[(t * RP + rp) * 64], wb[rp], Va);
+                if (t + 1 < PT) Vb = mfma16h(H2[((t + 1) * RP + rp) * 64], wb[rp], Vb);
+            }
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const int tt = t + h;
+                if (tt < PT) {
+                    const floatx4 Vt = h ? Vb : Va;
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) {
+                        const float gg =
+                            __builtin_amdgcn_fmed3f(fmaf(beta, u[tt][v], y[tt][v]), -1.0f, 1.0f);
+                        const float yn = gg - Vt[v];
+                        res = fmaxf(res, fabsf(yn - y[tt][v]));
+                        u[tt][v] = fmaf(-Vt[v], ib, u[tt][v]);
+                        y[tt][v] = yn;
+                    }
+                }
+            }
+        }
+        res = colmax(res);
+        if (!done) {
+            ++K;
+            if (!(res * inv_beta >= tol)) done = true;   // ||x-Az-e||_inf < eps ||x||_inf
+        }
+        beta = fminf(L.c.rho * beta, beta_bar);
+
+        // FP32 residual refinement: u = x - A z from the input
+        if (L.c.refresh > 0 && ((k + 1) % L.c.refresh) == 0) {
+#pragma unroll
+            for (int t = 0; t < PT; ++t) {
+                // keep the refresh tile by tile (it runs rarely; hoisting all
+                // of its fragment loads would cost registers the loop needs)
+                __builtin_amdgcn_sched_barrier(0);
+                floatx4 Az = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+                for (int mt = 0; mt < RT; ++mt) {
+                    const floatx4 a = F2[(t * RT + mt) * 64];
+#pragma unroll
+                    for (int v = 0; v < 4; ++v)
+                        if (4 * mt + v < KS) Az = mfma4(a[v], z[mt][v], Az);
+                }
+                const floatx4 xv = xtile[t * 64];
+#pragma unroll
+                for (int v = 0; v < 4; ++v) u[t][v] = xv[v] - Az[v];
+            }
+        }
+    }
+
+    if (j < nreg) {
+        if (valid) {
+#pragma unroll
+            for (int mt = 0; mt < RT; ++mt)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int kk = 16 * mt + 4 * v + g;
+                    if (kk < r) Zout[kk + j * ldz] = z[mt][v];
+                }
+        }
+        if (iters && g == 0)
+            iters[j] = !valid ? INT_MIN : (done ? K : -L.c.max_iter);
+    }
+}
+
+// FP32 refresh fragments of the precision form, for classes whose LDS cannot
+// hold them: out[(t RT + mt) 256 + lane 4 + v] = A[16 t + c][16 mt + 4 v + g].
+static __global__ void prep_frag32(const double *__restrict__ A, int lda, int p, int r, int PT, int RT,
+                            float *__restrict__ out)
+{
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= PT * RT * 256) return;
+    const int v = idx & 3, ln = (idx >> 2) & 63, tm = idx >> 8;
+    const int t = tm / RT, mt = tm - t * RT;
+    const int g = ln >> 4, c = ln & 15;
+    const int e = 16 * t + c, k = 16 * mt + 4 * v + g;
+    out[idx] = (e < p && k < r) ? (float)A[e + (int64_t)k * lda] : 0.0f;
+}
+
+template <int PT, int KS>
+int launch_pt_ks(rpca_ctx *ctx, const FilterLaunch &L, int nblocks, hipStream_t stream)
+{
+    if (L.c.precision == 1) {
+        // the FP32 refresh fragments live in HBM when the launcher prepared them
+        const size_t lds = lds_bytes_f16(PT, KS, L.frag32[0] == nullptr);
+        static bool attr_set_h = false;
+        if (!attr_set_h) {
+            RPCA_HIP_TRY(ctx, hipFuncSetAttribute((const void *)l1_filter_kernel_f16<PT, KS>,
+                                                  hipFuncAttributeMaxDynamicSharedMemorySize,
+                                                  (int)lds_bytes_f16(PT, KS, true) > (int)ctx->max_lds
+                                                      ? (int)lds_bytes_f16(PT, KS, false)
+                                                      : (int)lds_bytes_f16(PT, KS, true)));
+            attr_set_h = true;
+        }
+        hipLaunchKernelGGL((l1_filter_kernel_f16<PT, KS>), dim3(nblocks), dim3(kWavesPerBlock * 64),
+                           lds, stream, L);
+        RPCA_HIP_TRY(ctx, hipGetLastError());
+        return RPCA_OK;
+    }
+    if constexpr (PT <= 19) {
+        const size_t lds = lds_bytes(PT, KS);
+        static bool attr_set = false;
+        if (!attr_set) {
+            RPCA_HIP_TRY(ctx, hipFuncSetAttribute((const void *)l1_filter_kernel<PT, KS>,
+                                                  hipFuncAttributeMaxDynamicSharedMemorySize,
+                                                  (int)lds));
+            attr_set = true;
+        }
+        hipLaunchKernelGGL((l1_filter_kernel<PT, KS>), dim3(nblocks), dim3(kWavesPerBlock * 64),
+                           lds, stream, L);
+        RPCA_HIP_TRY(ctx, hipGetLastError());
+        return RPCA_OK;
+    } else {
+        return set_status(ctx, RPCA_ERR_UNSUPPORTED, "filter: FP32 form not built for this p class");
+    }
+}
+
+// Launch the class (PT, KS); defined in filter_inst.hip, one object per PT.
+template <int PT>
+int launch_filter_pt(rpca_ctx *ctx, int KS, const FilterLaunch &L, int nblocks, hipStream_t stream)
+{
+    switch (KS) {
+    case 1: return launch_pt_ks<PT, 1>(ctx, L, nblocks, stream);
+    case 2: return launch_pt_ks<PT, 2>(ctx, L, nblocks, stream);
+    case 3: return launch_pt_ks<PT, 3>(ctx, L, nblocks, stream);
+    case 4: return launch_pt_ks<PT, 4>(ctx, L, nblocks, stream);
+    case 5: return launch_pt_ks<PT, 5>(ctx, L, nblocks, stream);
+    case 6: return launch_pt_ks<PT, 6>(ctx, L, nblocks, stream);
+    case 8: return launch_pt_ks<PT, 8>(ctx, L, nblocks, stream);
+    case 10: return launch_pt_ks<PT, 10>(ctx, L, nblocks, stream);
+    case 13: return launch_pt_ks<PT, 13>(ctx, L, nblocks, stream);
+    case 16: return launch_pt_ks<PT, 16>(ctx, L, nblocks, stream);
+    default: return set_status(ctx, RPCA_ERR_UNSUPPORTED, "filter: rank class not built");
+    }
+}
+
+} // namespace filterk

@@ -14,6 +14,7 @@
 // wave), and writes L and S with non-temporal stores.
 #include "rpca_internal.h"
 
+#include <algorithm>
 #include <climits>
 
 namespace {
@@ -33,20 +34,39 @@ __device__ __forceinline__ int64_t lower_bound_i64(const int64_t *a, int64_t n, 
 }
 
 // F: m x R4 row-major, G: n x R4 row-major, zero-padded to R4 >= r.
-__global__ void assemble_factors(const int64_t *__restrict__ seed_rows, int64_t p,
-                                 const int64_t *__restrict__ seed_cols, int64_t q,
-                                 const double *__restrict__ U, const double *__restrict__ sigma,
-                                 const double *__restrict__ V, int r,
-                                 const float *__restrict__ Qt, const float *__restrict__ Pt,
-                                 int64_t m, int64_t n, int R4, float *__restrict__ F,
-                                 float *__restrict__ G)
+// Threads [0, m) build rows of F, threads [m, m + n) rows of G; the sorted
+// seed indices are staged in LDS (when they fit) for the binary searches.
+constexpr int kAssembleThreads = 256;
+constexpr int kIdxLds = 4096;
+
+__global__ void __launch_bounds__(kAssembleThreads)
+assemble_factors(const int64_t *__restrict__ seed_rows, int64_t p,
+                 const int64_t *__restrict__ seed_cols, int64_t q,
+                 const double *__restrict__ U, const double *__restrict__ sigma,
+                 const double *__restrict__ V, int r,
+                 const float *__restrict__ Qt, const float *__restrict__ Pt,
+                 int64_t m, int64_t n, int R4, float *__restrict__ F, float *__restrict__ G)
 {
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    __shared__ int64_t sidx[kIdxLds];
+    const int64_t first = (int64_t)blockIdx.x * blockDim.x;
+    // a block lies entirely in the F part, entirely in the G part, or straddles
+    const bool need_rows = first < m;
+    const bool need_cols = first + blockDim.x > m;
+    const bool rows_in_lds = need_rows && !need_cols && p <= kIdxLds;
+    const bool cols_in_lds = need_cols && !need_rows && q <= kIdxLds;
+    if (rows_in_lds)
+        for (int64_t a = threadIdx.x; a < p; a += blockDim.x) sidx[a] = seed_rows[a];
+    if (cols_in_lds)
+        for (int64_t a = threadIdx.x; a < q; a += blockDim.x) sidx[a] = seed_cols[a];
+    __syncthreads();
+
+    const int64_t t = first + threadIdx.x;
     if (t < m) {
         const int64_t i = t;
-        const int64_t a = lower_bound_i64(seed_rows, p, i);
+        const int64_t *idx = rows_in_lds ? sidx : seed_rows;
+        const int64_t a = lower_bound_i64(idx, p, i);
         float *f = F + i * R4;
-        if (a < p && seed_rows[a] == i) {
+        if (a < p && idx[a] == i) {
             for (int k = 0; k < R4; ++k) f[k] = k < r ? (float)(U[a + (int64_t)k * p] * sigma[k]) : 0.0f;
         } else {
             const int64_t b = i - a;   // position of i in the sorted complement
@@ -55,9 +75,10 @@ __global__ void assemble_factors(const int64_t *__restrict__ seed_rows, int64_t 
         }
     } else if (t < m + n) {
         const int64_t jj = t - m;
-        const int64_t a = lower_bound_i64(seed_cols, q, jj);
+        const int64_t *idx = cols_in_lds ? sidx : seed_cols;
+        const int64_t a = lower_bound_i64(idx, q, jj);
         float *gp = G + jj * R4;
-        if (a < q && seed_cols[a] == jj) {
+        if (a < q && idx[a] == jj) {
             for (int k = 0; k < R4; ++k) gp[k] = k < r ? (float)V[a + (int64_t)k * q] : 0.0f;
         } else {
             const int64_t b = jj - a;
@@ -70,9 +91,11 @@ __global__ void assemble_factors(const int64_t *__restrict__ seed_rows, int64_t 
 
 constexpr int kRowsPerLane = 4;
 constexpr int kRowsPerWave = 64 * kRowsPerLane;
-constexpr int kColsPerWave = 32;
+constexpr int kColBatch = 4;    // columns whose loads are in flight together
 
-// One wave computes a 256-row x 32-column tile of L and S.
+// One wave owns a 256-row block and a contiguous range of columns; the
+// ranges of the waves sharing a row block split its n columns evenly
+// (blockIdx.y of gridDim.y), so every wave streams the same number of bytes.
 template <int R4, bool VEC>
 __global__ void __launch_bounds__(64)
 reconstruct_kernel(const float *__restrict__ M, int64_t ldm, const float *__restrict__ F,
@@ -81,7 +104,8 @@ reconstruct_kernel(const float *__restrict__ M, int64_t ldm, const float *__rest
 {
     const int lane = threadIdx.x;
     const int64_t i0 = (int64_t)blockIdx.x * kRowsPerWave + lane * kRowsPerLane;
-    const int64_t j0 = (int64_t)blockIdx.y * kColsPerWave;
+    const int64_t j0 = n * (int64_t)blockIdx.y / gridDim.y;
+    const int64_t jend = n * ((int64_t)blockIdx.y + 1) / gridDim.y;
 
     float f[kRowsPerLane][R4];
 #pragma unroll
@@ -97,9 +121,34 @@ reconstruct_kernel(const float *__restrict__ M, int64_t ldm, const float *__rest
             f[rr][k + 3] = v[3];
         }
     }
-    const int64_t jend = (j0 + kColsPerWave < n) ? j0 + kColsPerWave : n;
     const bool full_rows = i0 + kRowsPerLane <= m;
-    for (int64_t j = j0; j < jend; ++j) {
+    int64_t j = j0;
+    if (VEC && full_rows) {
+        // batches of kColBatch columns, loads issued first
+#pragma unroll 1
+        for (; j + kColBatch <= jend; j += kColBatch) {
+            floatx4 mv[kColBatch];
+#pragma unroll
+            for (int cb = 0; cb < kColBatch; ++cb)
+                mv[cb] = __builtin_nontemporal_load(
+                    reinterpret_cast<const floatx4 *>(M + (j + cb) * ldm + i0));
+#pragma unroll
+            for (int cb = 0; cb < kColBatch; ++cb) {
+                const float *gj = G + (j + cb) * R4;     // uniform across the wave
+                floatx4 lv = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+                for (int k = 0; k < R4; ++k) {
+                    const float gk = gj[k];
+#pragma unroll
+                    for (int rr = 0; rr < kRowsPerLane; ++rr) lv[rr] = fmaf(f[rr][k], gk, lv[rr]);
+                }
+                __builtin_nontemporal_store(lv, reinterpret_cast<floatx4 *>(Lo + (j + cb) * ldl + i0));
+                __builtin_nontemporal_store(mv[cb] - lv,
+                                            reinterpret_cast<floatx4 *>(So + (j + cb) * lds + i0));
+            }
+        }
+    }
+    for (; j < jend; ++j) {
         const float *gj = G + j * R4;     // uniform across the wave
         float acc[kRowsPerLane] = {0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
@@ -132,8 +181,15 @@ template <int R4>
 int launch_r4(rpca_ctx *ctx, const ReconArgs &a, const float *F, const float *G, bool vec,
               hipStream_t stream)
 {
-    const dim3 grid((unsigned)((a.m + kRowsPerWave - 1) / kRowsPerWave),
-                    (unsigned)((a.n + kColsPerWave - 1) / kColsPerWave));
+    // ~recon_waves_per_cu waves per CU across the chip (32 measured best for
+    // this column-block pattern), at least 4 columns each
+    const int64_t row_blocks = (a.m + kRowsPerWave - 1) / kRowsPerWave;
+    const int64_t target_waves =
+        (int64_t)(ctx->num_cu > 0 ? ctx->num_cu : 256) * ctx->recon_waves_per_cu;
+    int64_t per_block = (target_waves + row_blocks - 1) / row_blocks;
+    per_block = std::max<int64_t>(1, std::min<int64_t>(per_block, (a.n + 3) / 4));
+    per_block = std::min<int64_t>(per_block, 65535);
+    const dim3 grid((unsigned)row_blocks, (unsigned)per_block);
     if (vec)
         hipLaunchKernelGGL((reconstruct_kernel<R4, true>), grid, dim3(64), 0, stream, a.M, a.ldm, F,
                            G, a.m, a.n, a.L, a.ldl, a.S, a.lds);
@@ -156,7 +212,9 @@ int launch_reconstruct(rpca_ctx *ctx, const ReconArgs &a, hipStream_t stream)
     float *F = static_cast<float *>(ctx->factors.ptr);
     float *G = F + (size_t)a.m * R4;
     const int64_t nthreads = a.m + a.n;
-    hipLaunchKernelGGL(assemble_factors, dim3((unsigned)((nthreads + 255) / 256)), dim3(256), 0,
+    hipLaunchKernelGGL(assemble_factors,
+                       dim3((unsigned)((nthreads + kAssembleThreads - 1) / kAssembleThreads)),
+                       dim3(kAssembleThreads), 0,
                        stream, a.seed_rows, a.p, a.seed_cols, a.q, a.U, a.sigma, a.V, a.r, a.Qt,
                        a.Pt, a.m, a.n, R4, F, G);
     RPCA_HIP_TRY(ctx, hipGetLastError());

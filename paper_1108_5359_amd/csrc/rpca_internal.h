@@ -21,12 +21,15 @@ struct rpca_ctx {
     int num_cu = 0;
     size_t max_lds = 0;
     std::string last_error;
+    int recon_waves_per_cu = 32;  // launch shape of the completion (tunable)
     rocblas_handle blas = nullptr;
     hipEvent_t ev[6] = {};
     DevBuf seed_ws;     // FP64 matrices of the seed solver
     DevBuf factors;     // F (m x R4) and G (n x R4), FP32, for the completion
     DevBuf solve_ws;    // indices and filter outputs inside rpca_solve
     DevBuf scratch;     // small reductions / flags
+    DevBuf frag_ws;     // FP32 refresh fragments of the precision form (large p)
+    DevBuf xbuf_ws;     // the regressions' x in fragment order (read by the refresh)
 };
 
 // Set ctx->last_error and return status.
@@ -63,11 +66,13 @@ struct FilterSide {
     float *Z;
     int64_t ldz;
     int32_t *iters;
+    float *xbuf;          // workspace: x in fragment order, for the periodic refresh
 };
 
 struct FilterConsts {
     float eps, rho, beta0_scale, beta_max_scale;
     int32_t max_iter, refresh;
+    int32_t precision;    // 0 = FP32 contractions, 1 = FP16 contractions + FP32 refinement
 };
 
 // Enqueue the regressions of up to two sides (same p class and r class) in
@@ -75,8 +80,8 @@ struct FilterConsts {
 int launch_filter(rpca_ctx *ctx, const FilterSide *sides, int nsides, const FilterConsts &c,
                   hipStream_t stream);
 
-// Whether launch_filter supports (p, r).
-bool filter_supported(rpca_ctx *ctx, int p, int r);
+// Whether launch_filter supports (p, r) in the given precision mode.
+bool filter_supported(rpca_ctx *ctx, int p, int r, int precision);
 
 // Whether two (p, r) pairs use the same kernel and can share one launch.
 bool filter_same_class(int p0, int r0, int p1, int r1);

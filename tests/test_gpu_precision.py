@@ -1,0 +1,100 @@
+"""Precision form on the GPU: the filter's contractions in FP16 MFMA with FP32
+accumulation and FP32 residual refinement (opts.precision = 1), against the
+same FP64 oracle and the same tolerance as the FP32 form (relative Frobenius
+1e-5 on L^c = U Q~, L^r = P~^T V^T, L and S)."""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from gpu_util import REL_TOL, dev_f64_colmajor, dev_i64, dev_matrix, host_matrix, relF, say, support_mismatch
+from test_gpu_parity import R, case, ctx, small_case  # noqa: F401  (fixtures and cached cases)
+
+pytestmark = pytest.mark.gpu
+
+
+def _opts(R, **kw):
+    return R.rpca_opts_default(precision=1, **kw)
+
+
+@pytest.mark.parametrize("seed", [1, 2])
+def test_precision_filter_cols_rows_c1(R, ctx, seed):
+    import torch
+    pr, r, I, J, res = case("c1", seed)
+    Jc, Ic = oracle.complement(J, pr.n), oracle.complement(I, pr.m)
+    k = res.U.shape[1]
+    say(f"precision filter c1 seed={seed}")
+    Md = dev_matrix(pr.M)
+    Qt = torch.full((len(Jc), k), float("nan"), device="cuda")
+    Pt = torch.full((len(Ic), k), float("nan"), device="cuda")
+    kc = torch.zeros(len(Jc), dtype=torch.int32, device="cuda")
+    kr = torch.zeros(len(Ic), dtype=torch.int32, device="cuda")
+    st = R.rpca_filter(ctx, Md, pr.m, pr.n, pr.m, dev_i64(I), len(I), dev_i64(J), len(J),
+                       dev_i64(Jc), len(Jc), dev_i64(Ic), len(Ic), dev_f64_colmajor(res.U),
+                       dev_f64_colmajor(res.V), k, _opts(R), Qt, kc, Pt, kr)
+    torch.cuda.synchronize()
+    assert st == R.RPCA_OK
+    Qh, Ph = Qt.double().cpu().numpy().T, Pt.double().cpu().numpy().T
+    assert relF(res.U @ Qh, res.U @ res.Qt) <= REL_TOL
+    assert relF(Ph.T @ res.V.T, res.Pt.T @ res.V.T) <= REL_TOL
+    kall = np.concatenate([kc.cpu().numpy(), kr.cpu().numpy()])
+    assert (kall > 0).all()
+
+
+@pytest.mark.parametrize("seed", [1, 3])
+def test_precision_solve_c1(R, ctx, seed):
+    import torch
+    pr, r, I, J, res = case("c1", seed)
+    say(f"precision solve c1 seed={seed}")
+    Md = dev_matrix(pr.M)
+    L = torch.full_like(Md, float("nan"))
+    S = torch.full_like(Md, float("nan"))
+    st, info = R.rpca_solve(ctx, Md, pr.m, pr.n, pr.m, r, _opts(R), dev_i64(I), dev_i64(J), L,
+                            pr.m, S, pr.m)
+    torch.cuda.synchronize()
+    assert st == R.RPCA_OK, ctx.last_error()
+    Lh, Sh = host_matrix(L, pr.m), host_matrix(S, pr.m)
+    assert relF(Lh, res.L) <= REL_TOL and relF(Sh, res.S) <= REL_TOL
+    assert support_mismatch(Sh, res.S, float(np.abs(pr.M).max())) == 0
+
+
+def test_precision_solve_c2_sampled(R, ctx):
+    import torch
+    pr, r, I, J, res = case("c2", 1)
+    say("precision solve c2 (full size)")
+    Md = dev_matrix(pr.M)
+    L = torch.empty_like(Md)
+    S = torch.empty_like(Md)
+    st, info = R.rpca_solve(ctx, Md, pr.m, pr.n, pr.m, r, _opts(R), dev_i64(I), dev_i64(J), L,
+                            pr.m, S, pr.m)
+    torch.cuda.synchronize()
+    assert st == R.RPCA_OK, ctx.last_error()
+    rng = np.random.default_rng(1)
+    rows = rng.integers(0, pr.m, 200000)
+    cols = rng.integers(0, pr.n, 200000)
+    Lref = oracle.complete_entries(rows, cols, I, J, pr.m, pr.n, res.U, res.sigma, res.V, res.Qt,
+                                   res.Pt)
+    lin = torch.as_tensor(cols * pr.m + rows).cuda()
+    Lg = L.reshape(-1)[lin].double().cpu().numpy()
+    Sg = S.reshape(-1)[lin].double().cpu().numpy()
+    Sref = pr.M[rows, cols].astype(np.float64) - Lref
+    assert relF(Lg, Lref) <= REL_TOL and relF(Sg, Sref) <= REL_TOL
+    assert support_mismatch(Sg, Sref, float(np.abs(pr.M).max())) == 0
+    assert info.filt_not_converged == 0
+
+
+@pytest.mark.parametrize("m,n,r", [(333, 517, 3), (1200, 700, 1), (2000, 1500, 25)])
+def test_precision_ragged(R, ctx, m, n, r):
+    import torch
+    pr, I, J, res = small_case(m, n, r, 0.05, 7 + r)
+    say(f"precision solve ragged m={m} n={n} r={r}")
+    Md = dev_matrix(pr.M)
+    L = torch.full_like(Md, float("nan"))
+    S = torch.full_like(Md, float("nan"))
+    st, info = R.rpca_solve(ctx, Md, m, n, m, r, _opts(R), dev_i64(I), dev_i64(J), L, m, S, m)
+    torch.cuda.synchronize()
+    assert st >= 0, ctx.last_error()
+    assert relF(host_matrix(L, m), res.L) <= REL_TOL
+    assert relF(host_matrix(S, m), res.S) <= REL_TOL
