@@ -1,13 +1,19 @@
 """Benchmark: l1-filter solves/s on one MI355X.
 
-Workload (default): M = L0 + S0 with m = n = 10000, rank r = 20 (Gaussian
-factors N(0, 1/10000)), 10% +-1 corruptions at uniformly random positions,
-seed block 200 x 200 at random rows/columns.  One "step" is the whole hot path
-of l1 filtering over that matrix: the 9800 column and 9800 row l1 regressions
-(Algorithm 1, one fused launch) and the completion of L and S = M - L over all
-10^8 entries.  The seed PCP (a separate support stage) runs once before the
-timed region and is reported as ``t_seed_ms``.  Inputs are resident in HBM
-when timing starts.
+Default workload (``--config c2``, the plain FP32 form): M = L0 + S0 with
+m = n = 10000, rank r = 20 (Gaussian factors N(0, 1/10000)), 10% +-1
+corruptions at uniformly random positions, seed block 200 x 200 at random
+rows/columns.  One "step" is the whole hot path of l1 filtering over that
+matrix: the 9800 column and 9800 row l1 regressions (Algorithm 1, one fused
+launch) and the completion of L and S = M - L over all 10^8 entries.  The
+seed PCP (a separate support stage) runs once before the timed region and is
+reported as ``t_seed_ms``.  Inputs are resident in HBM when timing starts.
+The precision form (FP16 contractions + FP32 refinement) is timed on the same
+matrix and reported under ``detail.precision_form`` with its difference from
+the FP32 result.
+
+``--config c3``: m = n = 50000, r = 50, N(0, 2e-5) factors, 5% corruptions
+uniform in [-1, 1], 500 x 500 seed, precision form (M: 10 GB).
 
 Prints ONE JSON line.  ``value`` = (column + row regressions) per second of
 step time.  ``roofline`` describes the dominant kernel: algorithmic bytes or
@@ -20,7 +26,6 @@ from __future__ import annotations
 import argparse
 import hashlib
 import json
-import os
 import pathlib
 import sys
 import time
@@ -32,6 +37,20 @@ sys.path.insert(0, str(ROOT))
 
 PEAK_HBM_GBS = 8000.0          # MI355X HBM3E, GB/s
 PEAK_FP32_MFMA_TFLOPS = 157.3  # MI355X dense FP32 matrix
+PEAK_FP16_MFMA_TFLOPS = 2500.0  # MI355X dense FP16/BF16 matrix
+
+WORKLOADS = {
+    "c2": dict(m=10000, n=10000, r=20, factor_std=np.sqrt(1e-4), sparsity=0.10, values="pm1",
+               precision=0,
+               text="plain form: m=n=10000, r=20, N(0,1e-4) factors, 10% +-1 corruptions, 200x200 "
+                    "seed, 9800 column + 9800 row regressions of length 200, L and S over all 1e8 "
+                    "entries"),
+    "c3": dict(m=50000, n=50000, r=50, factor_std=np.sqrt(2e-5), sparsity=0.05, values="unif11",
+               precision=1,
+               text="precision form: m=n=50000, r=50, N(0,2e-5) factors, 5% U[-1,1] corruptions, "
+                    "500x500 seed (FP64), 49500 column + 49500 row regressions of length 500 with "
+                    "FP16 MFMA contractions and FP32 refinement, L and S over all 2.5e9 entries"),
+}
 
 
 def log(*a):
@@ -57,15 +76,98 @@ def counter_traffic(kernel_key: str, digest: str):
     return d.get("hbm_bytes_per_launch")
 
 
+class Workload:
+    """Device-resident inputs and outputs of one l1-filtering run."""
+
+    def __init__(self, name, seed, R, torch):
+        import synth
+        w = WORKLOADS[name]
+        self.name, self.R, self.torch = name, R, torch
+        self.m, self.n, self.r = w["m"], w["n"], w["r"]
+        self.p = self.q = 10 * self.r
+        dev = torch.device("cuda:0")
+        self.dev = dev
+        log(f"bench: generating {name}: m=n={self.m} r={self.r} (seed {seed})")
+        self.Md, self.A0, self.B0 = synth.lowrank_plus_sparse_device(
+            self.m, self.n, self.r, factor_std=w["factor_std"], sparsity=w["sparsity"],
+            values=w["values"], seed=seed, device=dev)
+        self.I, self.J = synth.seed_indices(self.m, self.n, self.p, self.q, seed=seed)
+        self.Ic = np.setdiff1d(np.arange(self.m), self.I)
+        self.Jc = np.setdiff1d(np.arange(self.n), self.J)
+        self.nc, self.mr = len(self.Jc), len(self.Ic)
+        T = lambda a: torch.as_tensor(a).to(dev)
+        self.dI, self.dJ, self.dIc, self.dJc = T(self.I), T(self.J), T(self.Ic), T(self.Jc)
+        r, p, q = self.r, self.p, self.q
+        self.U = torch.zeros((r, p), dtype=torch.float64, device=dev)
+        self.sg = torch.zeros(r, dtype=torch.float64, device=dev)
+        self.V = torch.zeros((r, q), dtype=torch.float64, device=dev)
+        self.Qt = torch.empty((self.nc, r), dtype=torch.float32, device=dev)
+        self.Pt = torch.empty((self.mr, r), dtype=torch.float32, device=dev)
+        self.kc = torch.empty(self.nc, dtype=torch.int32, device=dev)
+        self.kr = torch.empty(self.mr, dtype=torch.int32, device=dev)
+        self.L = torch.empty_like(self.Md)
+        self.S = torch.empty_like(self.Md)
+        self.ctx = R.Context(0)
+
+    def seed(self):
+        R, torch = self.R, self.torch
+        t0 = time.perf_counter()
+        st, self.r_used, self.seed_iters = R.rpca_seed(
+            self.ctx, self.Md, self.m, self.n, self.m, self.dI, self.p, self.dJ, self.q, self.r,
+            R.rpca_opts_default(), self.U, self.sg, self.V)
+        torch.cuda.synchronize()
+        self.t_seed_ms = (time.perf_counter() - t0) * 1e3
+        log(f"bench: seed status={R.rpca_status_string(st)} r_used={self.r_used} "
+            f"iters={self.seed_iters} t={self.t_seed_ms:.1f} ms")
+
+    def step(self, opts, stream, evs=None):
+        R = self.R
+        if evs:
+            evs[0].record(stream)
+        R.rpca_filter(self.ctx, self.Md, self.m, self.n, self.m, self.dI, self.p, self.dJ, self.q,
+                      self.dJc, self.nc, self.dIc, self.mr, self.U, self.V, self.r_used, opts,
+                      self.Qt, self.kc, self.Pt, self.kr, stream)
+        if evs:
+            evs[1].record(stream)
+        R.rpca_reconstruct(self.ctx, self.Md, self.m, self.n, self.m, self.dI, self.p, self.dJ,
+                           self.q, self.U, self.sg, self.V, self.r_used, self.Qt, self.Pt, self.L,
+                           self.m, self.S, self.m, stream)
+        if evs:
+            evs[2].record(stream)
+
+    def timed(self, opts, steps, warmup):
+        torch = self.torch
+        stream = torch.cuda.current_stream()
+        for _ in range(warmup):
+            self.step(opts, stream)
+        torch.cuda.synchronize()
+        events = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(steps)]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for k in range(steps):
+            self.step(opts, stream, events[k])
+        torch.cuda.synchronize()
+        elapsed = time.perf_counter() - t0
+        filt_ms = float(np.mean([e[0].elapsed_time(e[1]) for e in events]))
+        recon_ms = float(np.mean([e[1].elapsed_time(e[2]) for e in events]))
+        K = np.abs(np.concatenate([self.kc.cpu().numpy(), self.kr.cpu().numpy()]).astype(np.int64))
+        unconv = int((np.concatenate([self.kc.cpu().numpy(), self.kr.cpu().numpy()]) < 0).sum())
+        return elapsed, filt_ms, recon_ms, K, unconv
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--seed", type=int, default=1)
+    ap.add_argument("--config", default="c2", choices=sorted(WORKLOADS))
+    ap.add_argument("--precision", type=int, default=None, help="0 = FP32, 1 = FP16 + refinement")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample", type=int, default=0,
-                    help="regressions in the CPU baseline sample (0 = all)")
+    ap.add_argument("--no-compare", action="store_true", help="skip timing the other precision form")
+    ap.add_argument("--cpu-sample", type=int, default=None,
+                    help="regressions in the CPU baseline sample (0 = all; default: all at c2, "
+                         "8000 at c3)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first run a plain 1 GiB device-to-device copy (for scaling the "
                          "FETCH_SIZE / WRITE_SIZE counters of a profiled run)")
@@ -78,103 +180,88 @@ def main():
 
     import torch
 
-    import synth
     import paper_1108_5359_amd.rpca as R
 
-    m = n = 10000
-    r = 20
-    p = q = 10 * r
-    log(f"bench: generating m=n={m} r={r} (seed {args.seed})")
-    pr = synth.config_problem("c2", seed=args.seed)
-    I, J = synth.seed_indices(m, n, p, q, seed=args.seed)
-    Ic = np.setdiff1d(np.arange(m), I)
-    Jc = np.setdiff1d(np.arange(n), J)
-    nc, mr = len(Jc), len(Ic)
-
-    dev = torch.device("cuda:0")
-    Md = torch.from_numpy(np.ascontiguousarray(pr.M.T)).to(dev)     # (n, m): column-major M
-    dI, dJ = torch.as_tensor(I).to(dev), torch.as_tensor(J).to(dev)
-    dIc, dJc = torch.as_tensor(Ic).to(dev), torch.as_tensor(Jc).to(dev)
-    U = torch.zeros((r, p), dtype=torch.float64, device=dev)
-    sg = torch.zeros(r, dtype=torch.float64, device=dev)
-    V = torch.zeros((r, q), dtype=torch.float64, device=dev)
-    Qt = torch.empty((nc, r), dtype=torch.float32, device=dev)
-    Pt = torch.empty((mr, r), dtype=torch.float32, device=dev)
-    kc = torch.empty(nc, dtype=torch.int32, device=dev)
-    kr = torch.empty(mr, dtype=torch.int32, device=dev)
-    L = torch.empty_like(Md)
-    S = torch.empty_like(Md)
-    opts = R.rpca_opts_default()
-    ctx = R.Context(0)
-
-    t0 = time.perf_counter()
-    st, r_used, seed_iters = R.rpca_seed(ctx, Md, m, n, m, dI, p, dJ, q, r, opts, U, sg, V)
-    torch.cuda.synchronize()
-    t_seed_ms = (time.perf_counter() - t0) * 1e3
-    log(f"bench: seed status={R.rpca_status_string(st)} r_used={r_used} iters={seed_iters} "
-        f"t={t_seed_ms:.1f} ms")
-    stream = torch.cuda.current_stream()
-
-    def step(evs=None):
-        if evs: evs[0].record(stream)
-        R.rpca_filter(ctx, Md, m, n, m, dI, p, dJ, q, dJc, nc, dIc, mr, U, V, r_used, opts,
-                      Qt, kc, Pt, kr, stream)
-        if evs: evs[1].record(stream)
-        R.rpca_reconstruct(ctx, Md, m, n, m, dI, p, dJ, q, U, sg, V, r_used, Qt, Pt, L, m, S, m,
-                           stream)
-        if evs: evs[2].record(stream)
+    wl = Workload(args.config, args.seed, R, torch)
+    wl.seed()
+    precision = WORKLOADS[args.config]["precision"] if args.precision is None else args.precision
+    opts = R.rpca_opts_default(precision=precision)
 
     if args.calibrate_copy:
-        src = torch.ones(1 << 28, dtype=torch.float32, device=dev)
+        src = torch.ones(1 << 28, dtype=torch.float32, device=wl.dev)
         dst = torch.empty_like(src)
         for _ in range(2):
             dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    events = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(args.steps)]
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for k in range(args.steps):
-        step(events[k])
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    filt_ms = float(np.mean([e[0].elapsed_time(e[1]) for e in events]))
-    recon_ms = float(np.mean([e[1].elapsed_time(e[2]) for e in events]))
-    ms_per_step = elapsed * 1e3 / args.steps
-    regs = nc + mr
-    value = regs * args.steps / elapsed
-    K = np.concatenate([kc.cpu().numpy(), kr.cpu().numpy()]).astype(np.int64)
-    Kabs = np.abs(K)
-    log(f"bench: {ms_per_step:.3f} ms/step  filter {filt_ms:.3f} ms  reconstruct {recon_ms:.3f} ms  "
-        f"K mean {Kabs.mean():.1f} max {Kabs.max()} unconverged {(K < 0).sum()}")
 
-    # Algorithmic work (per launch): the filter's two contractions per
-    # iteration (A^T g and A w: 4 p r flops), the completion's 12 bytes per
-    # element (read M, write L, write S).
-    filt_flops = float(4.0 * p * r_used * Kabs.sum())
-    recon_bytes = float(12.0 * m * n)
+    elapsed, filt_ms, recon_ms, K, unconv = wl.timed(opts, args.steps, args.warmup)
+    ms_per_step = elapsed * 1e3 / args.steps
+    regs = wl.nc + wl.mr
+    value = regs * args.steps / elapsed
+    log(f"bench: precision={precision} {ms_per_step:.3f} ms/step  filter {filt_ms:.3f} ms  "
+        f"reconstruct {recon_ms:.3f} ms  K mean {K.mean():.1f} max {K.max()} unconverged {unconv}")
+
+    # Algorithmic work per launch: the filter's two contractions per iteration
+    # (A^T g and A w: 4 p r flops per regression), the completion's 12 bytes
+    # per element (read M, write L, write S).
+    filt_flops = float(4.0 * wl.p * wl.r_used * K.sum())
+    recon_bytes = float(12.0 * wl.m * wl.n)
     filt_tflops = filt_flops / (filt_ms * 1e-3) / 1e12
     recon_gbs = recon_bytes / (recon_ms * 1e-3) / 1e9
     if filt_ms >= recon_ms:
-        digest = source_digest(["paper_1108_5359_amd/csrc/filter.hip"])
-        roofline = {"bound": "mfma", "kernel": "l1_filter_kernel (fp32 MFMA)",
-                    "achieved": round(filt_tflops, 3), "peak": PEAK_FP32_MFMA_TFLOPS,
-                    "unit": "TFLOP/s", "frac": round(filt_tflops / PEAK_FP32_MFMA_TFLOPS, 4),
-                    "traffic": counter_traffic("l1_filter_c2", digest)}
+        digest = source_digest(["paper_1108_5359_amd/csrc/filter_kernel.h"])
+        peak = PEAK_FP16_MFMA_TFLOPS if precision == 1 and wl.p >= 48 else PEAK_FP32_MFMA_TFLOPS
+        roofline = {"bound": "mfma",
+                    "kernel": "l1_filter_kernel_f16 (fp16 MFMA)" if peak > 1000 else
+                              "l1_filter_kernel (fp32 MFMA)",
+                    "achieved": round(filt_tflops, 3), "peak": peak, "unit": "TFLOP/s",
+                    "frac": round(filt_tflops / peak, 4),
+                    "traffic": counter_traffic(f"l1_filter_{args.config}", digest)}
     else:
         digest = source_digest(["paper_1108_5359_amd/csrc/reconstruct.hip"])
-        roofline = {"bound": "hbm", "kernel": "reconstruct (assemble + stream)",
+        roofline = {"bound": "hbm", "kernel": "reconstruct_kernel (+ assemble_factors)",
                     "achieved": round(recon_gbs, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
                     "frac": round(recon_gbs / PEAK_HBM_GBS, 4),
-                    "traffic": counter_traffic("reconstruct_c2", digest)}
+                    "traffic": counter_traffic(f"reconstruct_{args.config}", digest)}
+
+    detail = {"filter_ms": round(filt_ms, 4), "reconstruct_ms": round(recon_ms, 4),
+              "filter_tflops_contraction": round(filt_tflops, 3),
+              "reconstruct_gbs": round(recon_gbs, 1), "iters_mean": round(float(K.mean()), 2),
+              "iters_max": int(K.max()), "unconverged": unconv,
+              "t_seed_ms": round(wl.t_seed_ms, 1), "seed_iters": wl.seed_iters,
+              "r_used": wl.r_used, "precision": precision}
+
+    if not args.no_compare:
+        # the other precision form on the same matrix, and how far apart they are
+        Q0 = wl.Qt.clone()
+        P0 = wl.Pt.clone()
+        other = 1 - precision
+        key = "precision_form" if other == 1 else "plain_fp32_form"
+        try:
+            e2, f2, r2, K2, u2 = wl.timed(R.rpca_opts_default(precision=other), args.steps, 1)
+        except R.RpcaError as err:
+            detail[key] = {"unsupported": str(err)}
+            e2 = None
+    if not args.no_compare and e2 is not None:
+        Uh = wl.U.cpu().numpy()          # (r, p) = U^T
+        Vh = wl.V.cpu().numpy()
+        dq = np.linalg.norm((wl.Qt.double() - Q0.double()).cpu().numpy() @ Uh)
+        nq = np.linalg.norm(Q0.double().cpu().numpy() @ Uh)
+        dp = np.linalg.norm((wl.Pt.double() - P0.double()).cpu().numpy() @ Vh)
+        np_ = np.linalg.norm(P0.double().cpu().numpy() @ Vh)
+        detail[key] = {"value": round(regs * args.steps / e2, 1),
+                       "ms_per_step": round(e2 * 1e3 / args.steps, 4), "filter_ms": round(f2, 4),
+                       "reconstruct_ms": round(r2, 4), "iters_mean": round(float(K2.mean()), 2),
+                       "unconverged": u2,
+                       "relF_vs_headline_form": round(float(np.hypot(dq, dp) / np.hypot(nq, np_)), 10)}
+        log(f"bench: precision={other} {e2 * 1e3 / args.steps:.3f} ms/step  filter {f2:.3f} ms")
+        wl.timed(opts, 1, 0)        # leave the headline form's outputs in place
 
     cpu = None
     if not args.no_cpu_baseline:
-        cpu = cpu_baseline(pr, I, J, Ic, Jc, U.cpu().numpy().T, sg.cpu().numpy(),
-                           V.cpu().numpy().T, r_used, args.cpu_sample)
+        sample = args.cpu_sample if args.cpu_sample is not None else (0 if args.config == "c2" else 8000)
+        cpu = cpu_baseline(wl, sample)
 
     out = {
         "metric": "l1-filter solves/s (column + row l1 regressions, with completion of L and S)",
@@ -187,55 +274,63 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": "f32" if precision == 0 else "f16 contractions / f32 state",
         "data": "synthetic",
-        "config": {"workload": "plain form: m=n=10000, r=20, N(0,1e-4) factors, 10% +-1 "
-                               "corruptions, 200x200 seed, 9800 column + 9800 row regressions "
-                               "of length 200, L and S over all 1e8 entries",
-                   "m": m, "n": n, "r": r, "seed_block": [p, q], "regressions": regs},
+        "config": {"workload": WORKLOADS[args.config]["text"], "name": args.config,
+                   "m": wl.m, "n": wl.n, "r": wl.r, "seed_block": [wl.p, wl.q],
+                   "regressions": regs},
         "roofline": roofline,
         "cpu_baseline": cpu,
-        "detail": {"filter_ms": round(filt_ms, 4), "reconstruct_ms": round(recon_ms, 4),
-                   "filter_tflops_contraction": round(filt_tflops, 3),
-                   "reconstruct_gbs": round(recon_gbs, 1),
-                   "iters_mean": round(float(Kabs.mean()), 2), "iters_max": int(Kabs.max()),
-                   "unconverged": int((K < 0).sum()), "t_seed_ms": round(t_seed_ms, 1),
-                   "seed_iters": seed_iters, "r_used": r_used},
+        "detail": detail,
     }
     print(json.dumps(out), flush=True)
-    ctx.close()
+    wl.ctx.close()
 
 
-def cpu_baseline(pr, I, J, Ic, Jc, U, sigma, V, r, sample):
-    """The FP64 oracle as it stands on the host cores: Algorithm 1 on the
-    column and row regressions (OpenMP over regressions) and the four-block
-    completion with S = M - L, same seed factors as the GPU run."""
+def cpu_baseline(wl, sample):
+    """The FP64 oracle as it stands on the host cores: Algorithm 1 (literal
+    form, OpenMP over regressions) on a sample of the column and row
+    regressions of the same matrix with the same seed factors, plus (for the
+    full sample at m*n <= 1e8) the four-block completion and S = M - L."""
     import oracle
     oracle.build()
+    torch = wl.torch
     threads = oracle.num_threads(0)
-    nreg = len(Jc) + len(Ic)
+    nreg = wl.nc + wl.mr
     if sample and sample < nreg:
-        cols = Jc[: sample // 2]
-        rows = Ic[: sample - sample // 2]
-        frac = (len(cols) + len(rows)) / nreg
+        cols = wl.Jc[: sample // 2]
+        rows = wl.Ic[: sample - sample // 2]
     else:
-        cols, rows, frac = Jc, Ic, 1.0
+        cols, rows = wl.Jc, wl.Ic
+    U = wl.U.cpu().numpy().T
+    V = wl.V.cpu().numpy().T
+    sigma = wl.sg.cpu().numpy()
+    ru = wl.r_used
+    U, V, sigma = U[:, :ru], V[:, :ru], sigma[:ru]
+    # host copies of the regression inputs (column-major M: Md[j, i] = M[i, j])
+    Xc = wl.Md[torch.as_tensor(cols).to(wl.dev)][:, torch.as_tensor(wl.I).to(wl.dev)]
+    Xc = Xc.double().cpu().numpy().T                       # p x len(cols)
+    Xr = wl.Md[torch.as_tensor(wl.J).to(wl.dev)][:, torch.as_tensor(rows).to(wl.dev)]
+    Xr = Xr.double().cpu().numpy()                          # q x len(rows)
     t0 = time.perf_counter()
-    Qt, _ = oracle.filter_cols(pr.M, I, cols, U)
-    Pt, _ = oracle.filter_rows(pr.M, J, rows, V)
+    Qt, _ = oracle.alg1_batch(Xc, U)
+    Pt, _ = oracle.alg1_batch(Xr, V)
     t_f = time.perf_counter() - t0
-    # completion of the matching share of the matrix (all of it for the full sample)
-    t0 = time.perf_counter()
-    if frac == 1.0:
-        oracle.complete(pr.M, I, J, U, sigma, V, Qt, Pt)
-    t_c = time.perf_counter() - t0
+    t_c = 0.0
+    full = len(cols) == wl.nc and len(rows) == wl.mr and wl.m * wl.n <= 100_000_000
+    if full:
+        Mh = wl.Md.cpu().numpy().T
+        t0 = time.perf_counter()
+        oracle.complete(Mh, wl.I, wl.J, U, sigma, V, Qt, Pt)
+        t_c = time.perf_counter() - t0
     t = t_f + t_c
-    log(f"bench: cpu oracle {len(cols) + len(rows)} regressions in {t_f:.2f} s, "
-        f"completion {t_c:.2f} s, threads {threads}")
+    log(f"bench: cpu oracle {len(cols) + len(rows)} regressions in {t_f:.2f} s, completion "
+        f"{t_c:.2f} s, threads {threads}")
     return {"value": round((len(cols) + len(rows)) / t, 1), "unit": "regressions/s",
             "cores": threads, "kind": "oracle",
             "sample": f"{len(cols)} column + {len(rows)} row regressions of the same matrix "
-                      f"(FP64, Algorithm 1 literal form){' + completion of all 1e8 entries' if frac == 1.0 else ''}",
+                      f"(FP64, Algorithm 1 literal form)"
+                      f"{' + completion of all entries' if full else ' (no completion)'}",
             "seconds": round(t, 2)}
 
 

@@ -30,6 +30,8 @@ import numpy as np
 
 __all__ = [
     "Problem",
+    "lowrank_plus_sparse_device",
+    "hash_uniform_torch",
     "lowrank_plus_sparse",
     "seed_indices",
     "splitmix64",
@@ -170,3 +172,69 @@ def config_problem(name: str, seed: int = 1, **overrides) -> Problem:
     cfg = dict(CONFIGS[name])
     cfg.update(overrides)
     return lowrank_plus_sparse(seed=seed, **cfg)
+
+
+# ---------------------------------------------------------------------------
+# The same generator on a torch device, for matrices too large for the host
+# (m = n = 50000: 10 GB in FP32).  The factors are drawn on the host exactly
+# as above; the support and values use the same SplitMix64 counter hash
+# (int64 arithmetic wraps like uint64; right shifts are made logical).
+# ---------------------------------------------------------------------------
+def _i64(x: int) -> int:
+    x &= 0xFFFFFFFFFFFFFFFF
+    return x - (1 << 64) if x >= (1 << 63) else x
+
+
+def _lsr(z, k: int):
+    return (z >> k) & ((1 << (64 - k)) - 1)
+
+
+def _splitmix64_torch(x):
+    z = x + _i64(0x9E3779B97F4A7C15)
+    z = (z ^ _lsr(z, 30)) * _i64(0xBF58476D1CE4E5B9)
+    z = (z ^ _lsr(z, 27)) * _i64(0x94D049BB133111EB)
+    return z ^ _lsr(z, 31)
+
+
+def hash_uniform_torch(seed: int, stream: int, idx):
+    """torch version of :func:`hash_uniform` (idx: int64 tensor); equal bits."""
+    import torch
+    key = int(splitmix64(np.uint64((seed * 0x100000001B3 + stream) & 0xFFFFFFFFFFFFFFFF)))
+    h = _splitmix64_torch((idx * _i64(0x9E3779B97F4A7C15)) ^ _i64(key))
+    return _lsr(h, 11).to(torch.float64) * (1.0 / 9007199254740992.0)
+
+
+def lowrank_plus_sparse_device(m: int, n: int, r: int, *, factor_std: float, sparsity: float,
+                               values: str = "pm1", seed: int = 1, device="cuda",
+                               block_cols: int = 512):
+    """Bernoulli-support version of :func:`lowrank_plus_sparse` built on a
+    torch device.  Returns ``(Mt, A0, B0)``: ``Mt`` is the (n, m) row-major
+    FP32 tensor holding column-major M; ``A0``, ``B0`` are the host factors."""
+    import torch
+    rng = np.random.Generator(np.random.PCG64(seed))
+    A0 = rng.standard_normal((m, r)) * factor_std
+    B0 = rng.standard_normal((n, r)) * factor_std
+    Ad = torch.from_numpy(A0).to(device)
+    Bd = torch.from_numpy(B0).to(device)
+    Mt = torch.empty((n, m), dtype=torch.float32, device=device)
+    rows = torch.arange(m, dtype=torch.int64, device=device)
+    for j0 in range(0, n, block_cols):
+        j1 = min(n, j0 + block_cols)
+        lin = torch.arange(j0, j1, dtype=torch.int64, device=device)[:, None] * m + rows[None, :]
+        hit = hash_uniform_torch(seed, 1, lin) < sparsity
+        u = hash_uniform_torch(seed, 2, lin)
+        if values == "pm1":
+            vals = torch.where(u < 0.5, -1.0, 1.0)
+        elif values == "unif11":
+            vals = 2.0 * u - 1.0
+        elif values == "unif01":
+            vals = u
+        elif values == "unif500":
+            vals = 1000.0 * u - 500.0
+        else:
+            raise ValueError(values)
+        blk = Bd[j0:j1] @ Ad.T
+        blk += torch.where(hit, vals, torch.zeros_like(vals))
+        Mt[j0:j1] = blk.to(torch.float32)
+        del lin, hit, u, vals, blk
+    return Mt, A0, B0

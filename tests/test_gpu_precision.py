@@ -98,3 +98,55 @@ def test_precision_ragged(R, ctx, m, n, r):
     assert st >= 0, ctx.last_error()
     assert relF(host_matrix(L, m), res.L) <= REL_TOL
     assert relF(host_matrix(S, m), res.S) <= REL_TOL
+
+
+def test_precision_c3_full_size_sampled(R, ctx):
+    # m = n = 50000, r = 50, 5% U[-1,1] corruptions, 500 x 500 seed: the whole
+    # matrix is solved on the GPU (precision form); the oracle recomputes the
+    # seed and a sample of 300 column and 300 row regressions, and L, S are
+    # compared on the entries those determine (plus seed-block entries).
+    import torch
+    m = n = 50000
+    r, p = 50, 500
+    say("precision c3: generating 50000 x 50000 on the device")
+    Md, A0, B0 = synth.lowrank_plus_sparse_device(m, n, r, factor_std=np.sqrt(2e-5), sparsity=0.05,
+                                                  values="unif11", seed=1, device="cuda")
+    I, J = synth.seed_indices(m, n, p, p, seed=1)
+    L = torch.empty_like(Md)
+    S = torch.empty_like(Md)
+    say("precision c3: solve")
+    st, info = R.rpca_solve(ctx, Md, m, n, m, r, _opts(R), dev_i64(I), dev_i64(J), L, m, S, m)
+    torch.cuda.synchronize()
+    assert st == R.RPCA_OK, ctx.last_error()
+    assert info.r_used == r and info.filt_not_converged == 0
+    say(f"precision c3: t_seed {info.t_seed_ms:.0f} ms, filter {info.t_filter_ms:.3f} ms, "
+        f"completion {info.t_reconstruct_ms:.3f} ms")
+    dI, dJ = dev_i64(I), dev_i64(J)
+    Ms = Md[dJ][:, dI].double().cpu().numpy().T                 # M[I, J]
+    sd = oracle.seed_pcp(Ms)
+    assert sd.rank == r
+    rng = np.random.default_rng(3)
+    Ic, Jc = oracle.complement(I, m), oracle.complement(J, n)
+    cs = np.sort(rng.choice(len(Jc), 300, replace=False))
+    rs = np.sort(rng.choice(len(Ic), 300, replace=False))
+    Xc = Md[dev_i64(Jc[cs])][:, dI].double().cpu().numpy().T      # p x 300
+    Xr = Md[dJ][:, dev_i64(Ic[rs])].double().cpu().numpy()        # q x 300
+    Qs, kq = oracle.alg1_batch(Xc, sd.U)
+    Ps, kp = oracle.alg1_batch(Xr, sd.V)
+    Qt = np.zeros((r, len(Jc)))
+    Pt = np.zeros((r, len(Ic)))
+    Qt[:, cs] = Qs
+    Pt[:, rs] = Ps
+    rows = np.concatenate([rng.choice(Ic[rs], 3000), rng.choice(I, 500)])
+    cols = np.concatenate([rng.choice(Jc[cs], 2000), rng.choice(J, 1500)])
+    rng.shuffle(cols)
+    Lref = oracle.complete_entries(rows, cols, I, J, m, n, sd.U, sd.sigma, sd.V, Qt, Pt)
+    lin = torch.as_tensor(cols.astype(np.int64) * m + rows.astype(np.int64)).cuda()
+    Lg = L.reshape(-1)[lin].double().cpu().numpy()
+    Sg = S.reshape(-1)[lin].double().cpu().numpy()
+    Mv = Md.reshape(-1)[lin].double().cpu().numpy()
+    assert relF(Lg, Lref) <= REL_TOL
+    assert relF(Sg, Mv - Lref) <= REL_TOL
+    # exact recovery against the generating factors on the same entries
+    L0 = (A0[rows] * B0[cols]).sum(1)
+    assert relF(Lg, L0) <= 1e-5
