@@ -84,7 +84,8 @@ typedef struct {
     int32_t filt_max_iter;       /* (500)                                                   */
     int32_t filt_refresh;        /* recompute x - A z from x every this many steps (8)      */
     uint64_t rng_seed;           /* seed of rpca_sample_indices inside rpca_solve           */
-    int32_t precision;           /* 0 = FP32 throughout the filter (only value for now)     */
+    int32_t precision;           /* 0 = FP32 filter; 1 = FP16 MFMA contractions + FP32      */
+                                 /* refinement for regressions with p >= 48 (0)             */
 } rpca_opts;
 
 /* What rpca_solve reports. */
@@ -232,6 +233,93 @@ int rpca_solve(rpca_ctx_t ctx, const float *M, int64_t m, int64_t n, int64_t ldm
                const rpca_opts *opts, const int64_t *seed_rows, const int64_t *seed_cols,
                float *L, int64_t ldl, float *S, int64_t lds, rpca_info *info,
                hipStream_t stream);
+
+/* ------------------------------------------------------------------------
+ * Batched form: steps 2-5 of Algorithm 2 for many independent problems
+ * ("jobs") of uneven sizes.  The regressions of every job are independent
+ * (Sec. 3.3), so the column and row regressions of all jobs are served from
+ * one work queue by one persistent kernel, and the completions of all jobs
+ * by one launch; the launches of a run can be replayed from a HIP graph.
+ *
+ * Life cycle: rpca_batch_create (checks, workspace) -> rpca_batch_seed
+ * (step 2 for every job) -> rpca_batch_run (steps 3-5 for every job; may be
+ * called repeatedly, e.g. after the caller rewrites the M buffers in place)
+ * -> rpca_batch_destroy.  The batch keeps the job descriptors (pointers
+ * included): the caller's buffers must stay valid until destroy.
+ * ------------------------------------------------------------------------ */
+
+/* One problem of a batch.  All pointers are DEVICE pointers on the context's
+ * device; layouts as everywhere (column-major, explicit leading dims). */
+typedef struct {
+    const float *M;              /* m x n input, ld ldm >= m                                */
+    int64_t m, n, ldm;
+    int32_t r;                   /* target rank, 1 <= r <= min(p, q)                        */
+    const int64_t *seed_rows;    /* p sorted distinct row indices in [0, m)                 */
+    int64_t p;
+    const int64_t *seed_cols;    /* q sorted distinct column indices in [0, n)              */
+    int64_t q;
+    float *L;                    /* m x n output, ld ldl >= m                               */
+    int64_t ldl;
+    float *S;                    /* m x n output, ld lds >= m                               */
+    int64_t lds;
+} rpca_job;
+
+/* Launch-shape choices of a batch (what the autotuner searches over). */
+typedef struct {
+    int32_t lane_max_p;          /* regressions with p <= lane_max_p (<= 80) and r <= 8 use */
+    int32_t lane_max_r;          /* the lane form (one regression per lane, 4x4 MFMA);      */
+                                 /* others the 16-regression tile form (80, 8)              */
+    int32_t filter_waves_per_cu; /* persistent grid of the lane form (8)                    */
+    int32_t recon_cols_per_wave; /* columns streamed by one wave of the completion (32)     */
+    int32_t order;               /* work-queue order: 0 = costliest job sides first,        */
+                                 /* 1 = job order (0)                                       */
+    int32_t graph;               /* 1 = replay runs after the first from HIP graphs (1)     */
+} rpca_batch_tuning;
+
+typedef struct rpca_batch *rpca_batch_t;
+
+/* Fill *t with the defaults listed above. */
+void rpca_batch_tuning_default(rpca_batch_tuning *t);
+
+/*
+ * Check njobs jobs (host array `jobs`, copied) and allocate the batch's
+ * device workspace (complement indices, seed factors, filter outputs,
+ * completion factors, work queue).  opts as for rpca_solve (os_r, os_c and
+ * rng_seed unused: every job brings its seed indices); tuning may be NULL
+ * (defaults).  Synchronous.  Errors: RPCA_ERR_ARG (bad job: the message names
+ * it), RPCA_ERR_NOMEM, RPCA_ERR_UNSUPPORTED (a job outside every kernel class).
+ */
+int rpca_batch_create(rpca_ctx_t ctx, const rpca_job *jobs, int64_t njobs, const rpca_opts *opts,
+                      const rpca_batch_tuning *tuning, rpca_batch_t *batch);
+
+/*
+ * Step 2 (Sec. 3.1, eq. SPCP) for every job, as rpca_seed does for one, into
+ * the batch's workspace; then builds the work queue of steps 3-4 from the
+ * ranks found.  Synchronous.  Returns the most severe job status (the message
+ * names the first job with it); RPCA_ERR_SEED if a seed has rank 0.
+ */
+int rpca_batch_seed(rpca_batch_t batch);
+
+/*
+ * Steps 3-5 (Sec. 3.2-3.3, Algorithm 1 per regression; eqs. l1s, l1s') for
+ * every job: writes L and S of each job.  Requires a successful
+ * rpca_batch_seed.  Asynchronous on `stream`; with tuning.graph, the first
+ * run records the launches into two HIP graphs (filter, completion) that later
+ * runs replay.  The work queue lives in the batch: runs of one batch must not
+ * overlap (serialize them on one stream).
+ */
+int rpca_batch_run(rpca_batch_t batch, hipStream_t stream);
+
+/*
+ * Per-job summary of the last seed and run (host *info): rank used, seed
+ * iterations, filter iteration statistics; t_seed_ms is the job's seed wall
+ * time, t_filter_ms / t_reconstruct_ms the device time of the whole batch's
+ * filter / completion phase of the last run.  Synchronizes with the last run.
+ */
+int rpca_batch_job_info(rpca_batch_t batch, int64_t job, rpca_info *info);
+
+/* Free the batch's workspace and graphs (never caller memory). */
+int rpca_batch_destroy(rpca_batch_t batch);
 
 #ifdef __cplusplus
 }

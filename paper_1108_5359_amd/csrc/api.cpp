@@ -16,23 +16,6 @@ thread_local std::string g_create_error;
 
 bool finite_pos(double v) { return std::isfinite(v) && v > 0; }
 
-int check_opts(rpca_ctx *ctx, const rpca_opts &o)
-{
-    if (o.os_r < 1 || o.os_c < 1) return set_status(ctx, RPCA_ERR_ARG, "opts: oversampling must be >= 1");
-    if (!(o.filt_eps >= 0 && o.filt_eps < 1)) return set_status(ctx, RPCA_ERR_ARG, "opts: filt_eps must be in [0, 1)");
-    if (!(o.filt_rho >= 1) || !std::isfinite(o.filt_rho)) return set_status(ctx, RPCA_ERR_ARG, "opts: filt_rho must be >= 1");
-    if (!finite_pos(o.filt_beta0_scale) || !(o.filt_beta_max_scale >= 1) || !std::isfinite(o.filt_beta_max_scale))
-        return set_status(ctx, RPCA_ERR_ARG, "opts: bad beta scales");
-    if (o.filt_max_iter < 1) return set_status(ctx, RPCA_ERR_ARG, "opts: filt_max_iter must be >= 1");
-    if (o.filt_refresh < 0) return set_status(ctx, RPCA_ERR_ARG, "opts: filt_refresh must be >= 0");
-    if (!finite_pos(o.seed_tol) || !(o.seed_rho >= 1) || !finite_pos(o.seed_mu0_scale) ||
-        !(o.seed_mu_max_scale >= 1) || o.seed_max_iter < 1 || !(o.seed_rank_floor >= 0))
-        return set_status(ctx, RPCA_ERR_ARG, "opts: bad seed constants");
-    if (o.precision != 0 && o.precision != 1)
-        return set_status(ctx, RPCA_ERR_ARG, "opts: precision must be 0 (FP32) or 1 (FP16 + FP32 refinement)");
-    return RPCA_OK;
-}
-
 int check_matrix(rpca_ctx *ctx, const void *M, int64_t m, int64_t n, int64_t ld, const char *name)
 {
     if (!M) return set_status(ctx, RPCA_ERR_ARG, std::string(name) + " is NULL");
@@ -57,18 +40,6 @@ int check_sorted_indices(rpca_ctx *ctx, const int64_t *dev, int64_t count, int64
     return RPCA_OK;
 }
 
-FilterConsts consts_of(const rpca_opts &o)
-{
-    FilterConsts c;
-    c.eps = (float)o.filt_eps;
-    c.rho = (float)o.filt_rho;
-    c.beta0_scale = (float)o.filt_beta0_scale;
-    c.beta_max_scale = (float)o.filt_beta_max_scale;
-    c.max_iter = o.filt_max_iter;
-    c.refresh = o.filt_refresh;
-    c.precision = o.precision;
-    return c;
-}
 
 uint64_t splitmix64_next(uint64_t &state)
 {
@@ -125,6 +96,36 @@ std::vector<int64_t> complement_of(const std::vector<int64_t> &sorted_idx, int64
 }
 
 } // namespace
+
+int check_opts(rpca_ctx *ctx, const rpca_opts &o)
+{
+    if (o.os_r < 1 || o.os_c < 1) return set_status(ctx, RPCA_ERR_ARG, "opts: oversampling must be >= 1");
+    if (!(o.filt_eps >= 0 && o.filt_eps < 1)) return set_status(ctx, RPCA_ERR_ARG, "opts: filt_eps must be in [0, 1)");
+    if (!(o.filt_rho >= 1) || !std::isfinite(o.filt_rho)) return set_status(ctx, RPCA_ERR_ARG, "opts: filt_rho must be >= 1");
+    if (!finite_pos(o.filt_beta0_scale) || !(o.filt_beta_max_scale >= 1) || !std::isfinite(o.filt_beta_max_scale))
+        return set_status(ctx, RPCA_ERR_ARG, "opts: bad beta scales");
+    if (o.filt_max_iter < 1) return set_status(ctx, RPCA_ERR_ARG, "opts: filt_max_iter must be >= 1");
+    if (o.filt_refresh < 0) return set_status(ctx, RPCA_ERR_ARG, "opts: filt_refresh must be >= 0");
+    if (!finite_pos(o.seed_tol) || !(o.seed_rho >= 1) || !finite_pos(o.seed_mu0_scale) ||
+        !(o.seed_mu_max_scale >= 1) || o.seed_max_iter < 1 || !(o.seed_rank_floor >= 0))
+        return set_status(ctx, RPCA_ERR_ARG, "opts: bad seed constants");
+    if (o.precision != 0 && o.precision != 1)
+        return set_status(ctx, RPCA_ERR_ARG, "opts: precision must be 0 (FP32) or 1 (FP16 + FP32 refinement)");
+    return RPCA_OK;
+}
+
+FilterConsts consts_of(const rpca_opts &o)
+{
+    FilterConsts c;
+    c.eps = (float)o.filt_eps;
+    c.rho = (float)o.filt_rho;
+    c.beta0_scale = (float)o.filt_beta0_scale;
+    c.beta_max_scale = (float)o.filt_beta_max_scale;
+    c.max_iter = o.filt_max_iter;
+    c.refresh = o.filt_refresh;
+    c.precision = o.precision;
+    return c;
+}
 
 int set_status(rpca_ctx *ctx, int status, const std::string &msg)
 {

@@ -1,0 +1,455 @@
+// Batched form of steps 3-5 of Algorithm 2 over many independent problems.
+//
+// Filter, lane form.  For small seeds (p <= 80, r <= 8: e.g. the 10r x 10r
+// seeds of low-rank video backgrounds) a 16-regression tile wastes most of a
+// 16x16 MFMA on the rank axis.  Here every lane owns one regression and both
+// contractions of the clip form of Algorithm 1 (see filter_kernel.h)
+//     w = A^T g   and   v = A w
+// run on v_mfma_f32_4x4x1_16b_f32: 16 blocks of 4x4x1 per instruction, block
+// b serving lanes 4b..4b+3.  Measured lane layout: the A operand of row i of
+// block b comes from lane 4b+i, the B operand of column j from lane 4b+j, and
+// accumulator register i of lane 4b+j holds D_b[i][j].  So with the basis in
+// the A operand (identical in every block) and the lane's own vector in the
+// B operand, each lane receives its own product:
+//   * w:  K-step = element e, A = A[e][4 rb + i], B = g_lane[e]
+//         -> register i of lane l holds w_l[4 rb + i];
+//   * v:  K-step = rank k, A = A[4 t + i][k], B = w_l[k]
+//         -> register i of lane l holds v_l[4 t + i].
+// Nothing moves between lanes: u, y, g (p values each) and z (r values) are
+// per-lane registers, the stopping test needs no reduction, and a regression
+// of p elements costs ceil(r/4) p + ceil(p/4) r instructions of 8 cycles per
+// 64 regressions.
+//
+// Scheduling.  One persistent kernel serves a work queue of items (64
+// consecutive regressions of one side of one problem): each wave takes the
+// next item with an atomic add on the queue head, re-stages the basis in its
+// own LDS slice when the side changes, and leaves when the queue is empty,
+// so every wave reaches the exit.  The host orders the items (costliest sides
+// first by default) and resets the head with a kernel (graph-safe).
+//
+// Completion.  The factor assembly and the completion of every problem run as
+// one launch each, with a table giving each workgroup its problem.
+#include "recon_kernel.h"
+
+#include <climits>
+
+namespace batchk {
+
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ floatx4 mfma4x4(float a, float b, floatx4 c)
+{
+    return __builtin_amdgcn_mfma_f32_4x4x1f32(a, b, c, 0, 0, 0);
+}
+
+constexpr int kMaxP4 = kLaneMaxP / 4;   // 20 element quads
+constexpr int kMaxRB = kLaneMaxR / 4;   // 2 rank blocks
+constexpr int kWaves = 4;               // waves per workgroup
+constexpr int kVC = 4;                  // element quads per chunk of v = A w
+
+// Per-wave LDS slice: the basis in the two operand orders and the element
+// offsets.
+// a1[(4 rb + i) S1 + e] = A[e][4 rb + i] with an odd number S1/4 of float4 per
+// row (conflict-free ds_read_b128 of 4 rows); a2[e RR + k] = A[e][k] with
+// RR = 4 RB.
+struct WaveLds {
+    float a1[kMaxRB * 4 * 4 * (kMaxP4 | 1)];
+    float a2[kMaxP4 * 4 * 4 * kMaxRB];
+    int64_t eoff[kMaxP4 * 4];            // element offsets in M (floats), -1 = padding
+};
+
+// Built classes: P4 = ceil(p / 4) rounded up to one of these, RB = ceil(r / 4).
+constexpr int kP4[] = {1, 2, 3, 4, 5, 6, 8, 10, 13, 15, 18, 20};
+constexpr int kNumP4 = sizeof(kP4) / sizeof(kP4[0]);
+
+__device__ __forceinline__ void wave_lds_sync()
+{
+    // LDS operations of one wave complete in order; this keeps the compiler
+    // from moving LDS accesses across the re-staging of the slice.
+    asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+}
+
+// Element x_e of a lane's regression, 0 for padding elements, bad element
+// indices and invalid lanes.  The element's offset is wave-uniform: it is
+// read from LDS and moved to scalar registers, and the lane's regression
+// offset voff is a 32-bit byte offset, so the load is the scalar-base +
+// vector-offset form and every element shares one VGPR of address.  Masked
+// lanes read an in-bounds element and select 0 (no branch per element).
+__device__ __forceinline__ float load_x(const float *M, const int64_t *eoff, int e, uint32_t voff,
+                                        bool valid)
+{
+    const int64_t o = eoff[e];
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)o);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)((uint64_t)o >> 32));
+    const int64_t off = (int64_t)(((uint64_t)hi << 32) | lo);
+    const bool ok = off >= 0;
+    const char *base = reinterpret_cast<const char *>(M + (ok ? off : 0));
+    const float x = *reinterpret_cast<const float *>(base + voff);
+    return (ok && valid) ? x : 0.0f;
+}
+
+// One item: regressions first .. first + 63 of side s.  The state u, y (and g
+// when KEEP) of p values sits in VGPRs; x is re-read from M by the refresh.
+template <int P4, int RB, bool KEEP>
+__device__ __forceinline__ void lane_item(const LaneSide &s, int64_t first, int lane, WaveLds &w,
+                                          bool restage, const FilterConsts &C)
+{
+    constexpr int PP = 4 * P4;          // padded p
+    constexpr int S1 = 4 * (P4 | 1);    // a1 row stride
+    constexpr int RR = 4 * RB;          // padded r
+    constexpr int NCH = 4 / RB;         // accumulator chains per rank block of w
+    const int p = s.p, r = s.r;
+    const int q4 = lane & 3;
+
+    if (restage) {
+        wave_lds_sync();
+        for (int idx = lane; idx < RB * 4 * S1; idx += 64) {
+            const int k = idx / S1, e = idx - k * S1;
+            w.a1[idx] = (e < p && k < r) ? (float)s.A[e + (int64_t)k * s.lda] : 0.0f;
+        }
+        for (int idx = lane; idx < PP * RR; idx += 64) {
+            const int e = idx / RR, k = idx - e * RR;
+            w.a2[idx] = (e < p && k < r) ? (float)s.A[e + (int64_t)k * s.lda] : 0.0f;
+        }
+        for (int e = lane; e < PP; e += 64) {
+            int64_t off = -1;
+            if (e < p) {
+                const int64_t ei = s.elem_idx[e];
+                if (ei >= 0 && ei < s.elem_bound) off = ei * s.elem_stride;
+            }
+            w.eoff[e] = off;
+        }
+        wave_lds_sync();
+    }
+
+    // the host admits a side to the lane form only if every regression's
+    // offset reg_idx * reg_stride * 4 fits in 32 bits
+    const int64_t j = first + lane;
+    bool valid = j < s.nreg;
+    uint32_t voff = 0;
+    if (valid) {
+        const int64_t ri = s.reg_idx[j];
+        if (ri >= 0 && ri < s.reg_bound) voff = (uint32_t)(ri * s.reg_stride * 4);
+        else valid = false;
+    }
+
+    // ---- x, its norms, the starting state (u = x, y = 0, z = 0)
+    float u[P4][4], y[P4][4];
+    float gk[KEEP ? P4 : 1][4];
+    float xinf = 0.0f, xx = 0.0f;
+    const float *M = s.M;
+#pragma unroll
+    for (int t = 0; t < P4; ++t) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const float x = load_x(M, w.eoff, 4 * t + i, voff, valid);
+            u[t][i] = x;
+            y[t][i] = 0.0f;
+            xinf = fmaxf(xinf, fabsf(x));
+            xx = fmaf(x, x, xx);
+        }
+        __builtin_amdgcn_sched_barrier(0);
+    }
+    float beta = xx > 0.0f ? C.beta0_scale / sqrtf(xx) : 1.0f;
+    const float beta_bar = C.beta_max_scale * beta;
+    const float tol = C.eps * xinf;
+    bool done = !(valid && xinf > 0.0f);
+    int K = 0;
+    floatx4 z[RB];
+#pragma unroll
+    for (int rb = 0; rb < RB; ++rb) z[rb] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
+
+    const floatx4 *A1 = reinterpret_cast<const floatx4 *>(w.a1);
+    const floatx4 *A2 = reinterpret_cast<const floatx4 *>(w.a2);
+
+    for (int k = 0; k < C.max_iter; ++k) {
+        if (!__any(!done)) break;                                   // wave-uniform
+        asm volatile("" ::: "memory");   // the basis is re-read from LDS each step
+        // The lane's row offsets into the two fragment arrays, opaque to the
+        // optimizer: every fragment address is then formed inside the step
+        // (an immediate offset from these) instead of being hoisted out of
+        // the loop into one live VGPR per address.
+        uint32_t q1 = (uint32_t)(q4 * S1) / 4, q2 = (uint32_t)(q4 * RR) / 4;
+        asm volatile("" : "+v"(q1), "+v"(q2));
+        const floatx4 *F1 = A1 + q1;
+        const floatx4 *F2 = A2 + q2;
+
+        // ---- g = clip(beta u + y, -1, 1) and w = A^T g (NCH chains per rank block)
+        floatx4 acc[RB][NCH];
+#pragma unroll
+        for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+            for (int c = 0; c < NCH; ++c) acc[rb][c] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
+        // basis fragments one quad ahead; the scheduling barrier per quad keeps
+        // the compiler from hoisting every quad's loads (register pressure)
+        floatx4 an[RB];
+#pragma unroll
+        for (int rb = 0; rb < RB; ++rb) an[rb] = F1[(4 * rb * S1) / 4];
+#pragma unroll
+        for (int t = 0; t < P4; ++t) {
+            floatx4 a[RB];
+#pragma unroll
+            for (int rb = 0; rb < RB; ++rb) {
+                a[rb] = an[rb];
+                if (t + 1 < P4) an[rb] = F1[(4 * rb * S1 + 4 * (t + 1)) / 4];
+            }
+            float gt[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                gt[i] = __builtin_amdgcn_fmed3f(fmaf(beta, u[t][i], y[t][i]), -1.0f, 1.0f);
+                if constexpr (KEEP) gk[t][i] = gt[i];
+            }
+#pragma unroll
+            for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+                for (int i = 0; i < 4; ++i)
+                    acc[rb][i % NCH] = mfma4x4(a[rb][i], gt[i], acc[rb][i % NCH]);
+            __builtin_amdgcn_sched_barrier(0);
+        }
+        floatx4 W[RB];
+#pragma unroll
+        for (int rb = 0; rb < RB; ++rb) {
+            W[rb] = acc[rb][0];
+#pragma unroll
+            for (int c = 1; c < NCH; ++c) W[rb] += acc[rb][c];
+        }
+
+        // A converged regression keeps z and u frozen through a zero step size.
+        const float inv_beta = 1.0f / beta;
+        const float ib = done ? 0.0f : inv_beta;
+#pragma unroll
+        for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) z[rb][i] = fmaf(W[rb][i], ib, z[rb][i]);
+
+        // ---- v = A w in chunks of kVC quads, then the dual and residual update
+        float res = 0.0f;
+#pragma unroll
+        for (int t0 = 0; t0 < P4; t0 += kVC) {
+            floatx4 D[kVC];
+#pragma unroll
+            for (int c = 0; c < kVC; ++c) D[c] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+            for (int kb = 0; kb < RB; ++kb) {
+                floatx4 a[kVC];
+#pragma unroll
+                for (int c = 0; c < kVC; ++c)
+                    if (t0 + c < P4) a[c] = F2[(4 * (t0 + c) * RR + 4 * kb) / 4];
+                // ranks >= r have zero basis columns and zero w: the padded
+                // K-steps add exact zeros, and straight-line code keeps the
+                // register allocation in one block
+#pragma unroll
+                for (int kk = 0; kk < 4; ++kk)
+#pragma unroll
+                    for (int c = 0; c < kVC; ++c)
+                        if (t0 + c < P4) D[c] = mfma4x4(a[c][kk], W[kb][kk], D[c]);
+            }
+#pragma unroll
+            for (int c = 0; c < kVC; ++c) {
+                const int t = t0 + c;
+                if (t < P4) {
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) {
+                        float gg;
+                        if constexpr (KEEP) gg = gk[t][i];
+                        else gg = __builtin_amdgcn_fmed3f(fmaf(beta, u[t][i], y[t][i]), -1.0f, 1.0f);
+                        const float yn = gg - D[c][i];
+                        res = fmaxf(res, fabsf(yn - y[t][i]));
+                        u[t][i] = fmaf(-D[c][i], ib, u[t][i]);
+                        y[t][i] = yn;
+                    }
+                }
+            }
+            __builtin_amdgcn_sched_barrier(0);
+        }
+        if (!done) {
+            ++K;
+            if (!(res * inv_beta >= tol)) done = true;   // ||x-Az-e||_inf < eps ||x||_inf
+        }
+        beta = fminf(C.rho * beta, beta_bar);
+
+        // ---- periodic u = x - A z from the input, against FP32 drift
+        if (C.refresh > 0 && ((k + 1) % C.refresh) == 0) {
+            asm volatile("" ::: "memory");
+
+#pragma unroll
+            for (int t0 = 0; t0 < P4; t0 += kVC) {
+                floatx4 D[kVC];
+#pragma unroll
+                for (int c = 0; c < kVC; ++c) D[c] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+                for (int kb = 0; kb < RB; ++kb) {
+                    floatx4 a[kVC];
+#pragma unroll
+                    for (int c = 0; c < kVC; ++c)
+                        if (t0 + c < P4) a[c] = F2[(4 * (t0 + c) * RR + 4 * kb) / 4];
+#pragma unroll
+                    for (int kk = 0; kk < 4; ++kk)
+#pragma unroll
+                        for (int c = 0; c < kVC; ++c)
+                            if (t0 + c < P4) D[c] = mfma4x4(a[c][kk], z[kb][kk], D[c]);
+                }
+#pragma unroll
+                for (int c = 0; c < kVC; ++c) {
+                    const int t = t0 + c;
+                    if (t < P4) {
+#pragma unroll
+                        for (int i = 0; i < 4; ++i) {
+                            u[t][i] = load_x(M, w.eoff, 4 * t + i, voff, valid) - D[c][i];
+                        }
+                    }
+                }
+                __builtin_amdgcn_sched_barrier(0);
+            }
+        }
+    }
+
+    if (valid) {
+#pragma unroll
+        for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int kk = 4 * rb + i;
+                if (kk < r) s.Z[kk + j * s.ldz] = z[rb][i];
+            }
+    }
+    if (j < s.nreg && s.iters) s.iters[j] = !valid ? INT_MIN : (done ? K : -C.max_iter);
+}
+
+// Class groups: the state of P4 <= 10 quads (with g kept) and of 13..20
+// quads (g recomputed) need different register budgets, and a kernel's budget
+// is the largest of its branches, so each group is its own persistent kernel.
+constexpr int kSmallP4Classes = 8;   // kP4[0..8) = 1..10 quads
+#define LANE_CASE(i4, rb, keep)                                             \
+    case 2 * (i4) + (rb) - 1:                                               \
+        lane_item<kP4[i4], rb, keep>(s, first, lane, w, restage, C);        \
+        break;
+
+template <int GROUP>
+__global__ void __launch_bounds__(kWaves * 64) __attribute__((amdgpu_waves_per_eu(GROUP == 0 ? 2 : 1)))
+lane_filter_kernel(const LaneSide *__restrict__ sides, const int32_t *__restrict__ items,
+                   int32_t nitems, uint32_t *counter, FilterConsts C)
+{
+    __shared__ WaveLds lds[kWaves];
+    const int lane = threadIdx.x & 63;
+    WaveLds &w = lds[threadIdx.x >> 6];
+    int cached = -1;
+    for (;;) {
+        uint32_t it = 0;
+        if (lane == 0) it = atomicAdd(counter, 1u);
+        it = __builtin_amdgcn_readfirstlane(it);
+        if (it >= (uint32_t)nitems) break;               // every wave leaves here
+        const int sidx = items[2 * it];
+        const int64_t first = items[2 * it + 1];
+        const LaneSide &s = sides[sidx];
+        const bool restage = sidx != cached;
+        cached = sidx;
+        if constexpr (GROUP == 0) {
+            switch (s.cls) {
+                LANE_CASE(0, 1, true) LANE_CASE(0, 2, true) LANE_CASE(1, 1, true)
+                LANE_CASE(1, 2, true) LANE_CASE(2, 1, true) LANE_CASE(2, 2, true)
+                LANE_CASE(3, 1, true) LANE_CASE(3, 2, true) LANE_CASE(4, 1, true)
+                LANE_CASE(4, 2, true) LANE_CASE(5, 1, true) LANE_CASE(5, 2, true)
+                LANE_CASE(6, 1, true) LANE_CASE(6, 2, true) LANE_CASE(7, 1, true)
+                LANE_CASE(7, 2, true)
+            default: break;                              // other group: never queued here
+            }
+        } else {
+            switch (s.cls) {
+                LANE_CASE(8, 1, false) LANE_CASE(8, 2, false) LANE_CASE(9, 1, false)
+                LANE_CASE(9, 2, false) LANE_CASE(10, 1, false) LANE_CASE(10, 2, false)
+                LANE_CASE(11, 1, false) LANE_CASE(11, 2, false)
+            default: break;
+            }
+        }
+    }
+}
+#undef LANE_CASE
+static_assert(kNumP4 == 12 && kP4[kSmallP4Classes - 1] == 10, "class groups cover 12 quad classes");
+
+__global__ void reset_counters(uint32_t *counter)
+{
+    if (threadIdx.x < 2) counter[threadIdx.x] = 0u;
+}
+
+// ---------------------------------------------------------------- completion
+__global__ void __launch_bounds__(reconk::kAssembleThreads)
+batch_assemble(const ReconJob *__restrict__ jobs, const int32_t *__restrict__ block_job,
+               const int64_t *__restrict__ block_first)
+{
+    __shared__ int64_t sidx[reconk::kIdxLds];
+    const ReconJob &J = jobs[block_job[blockIdx.x]];
+    reconk::assemble_block(block_first[blockIdx.x], sidx, J.seed_rows, J.p, J.seed_cols, J.q, J.U,
+                           J.sigma, J.V, J.r, J.Qt, J.Pt, J.m, J.n, J.R4,
+                           const_cast<float *>(J.F), const_cast<float *>(J.G));
+}
+
+__global__ void __launch_bounds__(64)
+batch_reconstruct(const ReconJob *__restrict__ jobs, const int32_t *__restrict__ block_job,
+                  const uint32_t *__restrict__ block_local)
+{
+    const ReconJob &J = jobs[block_job[blockIdx.x]];
+    const uint32_t local = block_local[blockIdx.x];
+    const uint32_t bx = local % J.row_blocks, by = local / J.row_blocks;
+    const int lane = threadIdx.x;
+    if (J.R4 == 4) {
+        if (J.vec) reconk::recon_wave<4, true>(J.M, J.ldm, J.F, J.G, J.m, J.n, J.L, J.ldl, J.S, J.lds, bx, by, J.col_parts, lane);
+        else reconk::recon_wave<4, false>(J.M, J.ldm, J.F, J.G, J.m, J.n, J.L, J.ldl, J.S, J.lds, bx, by, J.col_parts, lane);
+    } else {
+        if (J.vec) reconk::recon_wave<8, true>(J.M, J.ldm, J.F, J.G, J.m, J.n, J.L, J.ldl, J.S, J.lds, bx, by, J.col_parts, lane);
+        else reconk::recon_wave<8, false>(J.M, J.ldm, J.F, J.G, J.m, J.n, J.L, J.ldl, J.S, J.lds, bx, by, J.col_parts, lane);
+    }
+}
+
+} // namespace batchk
+
+using namespace batchk;
+
+int lane_class(int p, int r)
+{
+    if (p < 1 || r < 1 || p > kLaneMaxP || r > kLaneMaxR) return -1;
+    const int need = (p + 3) / 4;
+    for (int i = 0; i < kNumP4; ++i)
+        if (kP4[i] >= need) return 2 * i + (r + 3) / 4 - 1;
+    return -1;
+}
+
+int lane_group(int cls) { return cls >= 0 && cls / 2 >= kSmallP4Classes ? 1 : 0; }
+
+int launch_lane_filter(rpca_ctx *ctx, const BatchTables &t, const FilterConsts &c,
+                       hipStream_t stream)
+{
+    hipLaunchKernelGGL(reset_counters, dim3(1), dim3(64), 0, stream, t.counter);
+    RPCA_HIP_TRY(ctx, hipGetLastError());
+    // large-state group first (its items are the costliest), then the small one
+    for (int g = 1; g >= 0; --g) {
+        const int32_t n = t.group_items[g];
+        if (n == 0) continue;
+        const int32_t *items = t.items + 2 * (g == 1 ? 0 : t.group_items[1]);
+        const int blocks = (t.grid_waves[g] + kWaves - 1) / kWaves;
+        if (g == 1)
+            hipLaunchKernelGGL(lane_filter_kernel<1>, dim3((unsigned)blocks), dim3(kWaves * 64), 0,
+                               stream, t.sides, items, n, t.counter + 1, c);
+        else
+            hipLaunchKernelGGL(lane_filter_kernel<0>, dim3((unsigned)blocks), dim3(kWaves * 64), 0,
+                               stream, t.sides, items, n, t.counter, c);
+        RPCA_HIP_TRY(ctx, hipGetLastError());
+    }
+    return RPCA_OK;
+}
+
+int launch_batch_reconstruct(rpca_ctx *ctx, const BatchTables &t, hipStream_t stream)
+{
+    if (t.asm_blocks > 0) {
+        hipLaunchKernelGGL(batch_assemble, dim3((unsigned)t.asm_blocks),
+                           dim3(reconk::kAssembleThreads), 0, stream, t.jobs, t.asm_block_job,
+                           t.asm_block_first);
+        RPCA_HIP_TRY(ctx, hipGetLastError());
+    }
+    if (t.rec_blocks > 0) {
+        hipLaunchKernelGGL(batch_reconstruct, dim3((unsigned)t.rec_blocks), dim3(64), 0, stream,
+                           t.jobs, t.rec_block_job, t.rec_block_local);
+        RPCA_HIP_TRY(ctx, hipGetLastError());
+    }
+    return RPCA_OK;
+}

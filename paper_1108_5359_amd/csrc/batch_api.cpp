@@ -1,0 +1,570 @@
+// Host runtime of the batched form: checks, workspace layout, the work queue
+// of the lane-form filter, the completion tables, and HIP graph replay.
+#include "rpca_internal.h"
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <numeric>
+#include <string>
+#include <vector>
+
+namespace {
+
+// Index checks and complements on host copies (as rpca_solve does).
+int fetch_sorted(rpca_ctx *ctx, const int64_t *dev, int64_t count, int64_t bound,
+                 const std::string &name, std::vector<int64_t> &out)
+{
+    out.resize((size_t)count);
+    RPCA_HIP_TRY(ctx, hipMemcpy(out.data(), dev, (size_t)count * sizeof(int64_t), hipMemcpyDeviceToHost));
+    for (int64_t i = 0; i < count; ++i) {
+        if (out[i] < 0 || out[i] >= bound) return set_status(ctx, RPCA_ERR_ARG, name + ": index out of range");
+        if (i > 0 && out[i] <= out[i - 1])
+            return set_status(ctx, RPCA_ERR_ARG, name + ": indices must be sorted and distinct");
+    }
+    return RPCA_OK;
+}
+
+std::vector<int64_t> complement_sorted(const std::vector<int64_t> &idx, int64_t bound)
+{
+    std::vector<int64_t> c;
+    c.reserve((size_t)(bound - (int64_t)idx.size()));
+    size_t a = 0;
+    for (int64_t i = 0; i < bound; ++i) {
+        if (a < idx.size() && idx[a] == i) ++a;
+        else c.push_back(i);
+    }
+    return c;
+}
+
+size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+// Per-iteration cost of one lane-form item (64 regressions), in SIMD cycles:
+// 6 VALU ops per element (4 cycles each per wave), ceil(r/4) 4x4x1 MFMAs per
+// element for w and r per element quad for v (8 cycles each).
+double lane_item_cost(int p, int r)
+{
+    const int P4 = (p + 3) / 4, RB = (r + 3) / 4;
+    return P4 * (96.0 + 32.0 * RB + 8.0 * r);
+}
+
+} // namespace
+
+struct BatchJobState {
+    int64_t mc = 0, nc = 0;        // complement sizes
+    int R4 = 4;                    // completion padding (from r)
+    bool lane_cols = false, lane_rows = false;
+    // byte offsets into the batch workspace
+    size_t o_Ic = 0, o_Jc = 0, o_U = 0, o_sig = 0, o_V = 0, o_Qt = 0, o_Pt = 0, o_it = 0, o_F = 0;
+    SeedOut so;
+    int seed_status = 0;
+    double t_seed_ms = 0;
+};
+
+struct rpca_batch {
+    rpca_ctx *ctx = nullptr;       // owner context (seed solver, BLAS handle)
+    rpca_ctx *wctx = nullptr;      // the batch's own workspace for tile-form / large-rank launches
+    std::vector<rpca_job> jobs;
+    std::vector<BatchJobState> js;
+    rpca_opts opts{};
+    rpca_batch_tuning tun{};
+    DevBuf ws;                     // per-job arrays
+    DevBuf tables;                 // queue, side and completion tables
+    BatchTables bt{};
+    bool seeded = false;
+    int64_t runs = 0;
+    hipStream_t bs = nullptr;
+    hipGraph_t graph[2] = {nullptr, nullptr};
+    hipGraphExec_t exec[2] = {nullptr, nullptr};
+    hipEvent_t ev[5] = {};
+    std::vector<FilterSide> tile_sides;   // sides in the tile form (one launch each)
+    std::vector<ReconArgs> single_recon;  // completions with R4 > 8 (one launch each)
+
+    char *at(size_t off) const { return static_cast<char *>(ws.ptr) + off; }
+};
+
+namespace {
+
+void drop_graphs(rpca_batch *b)
+{
+    for (int i = 0; i < 2; ++i) {
+        if (b->exec[i]) (void)hipGraphExecDestroy(b->exec[i]);
+        if (b->graph[i]) (void)hipGraphDestroy(b->graph[i]);
+        b->exec[i] = nullptr;
+        b->graph[i] = nullptr;
+    }
+}
+
+int fail(rpca_batch *b, int st)
+{
+    // errors of the batch's own workspace context are reported on the owner
+    if (b->wctx && !b->wctx->last_error.empty()) {
+        b->ctx->last_error = b->wctx->last_error;
+        b->wctx->last_error.clear();
+    }
+    return st;
+}
+
+int enqueue_filter(rpca_batch *b, hipStream_t s)
+{
+    const FilterConsts c = consts_of(b->opts);
+    int st = launch_lane_filter(b->wctx, b->bt, c, s);
+    if (st != RPCA_OK) return fail(b, st);
+    for (const FilterSide &fs : b->tile_sides)
+        if ((st = launch_filter(b->wctx, &fs, 1, c, s)) != RPCA_OK) return fail(b, st);
+    return RPCA_OK;
+}
+
+int enqueue_recon(rpca_batch *b, hipStream_t s)
+{
+    int st = launch_batch_reconstruct(b->wctx, b->bt, s);
+    if (st != RPCA_OK) return fail(b, st);
+    for (const ReconArgs &a : b->single_recon)
+        if ((st = launch_reconstruct(b->wctx, a, s)) != RPCA_OK) return fail(b, st);
+    return RPCA_OK;
+}
+
+// Build the device tables of the filter queue and of the batched completion
+// from the seed ranks.
+int build_tables(rpca_batch *b)
+{
+    rpca_ctx *ctx = b->ctx;
+    const int64_t nj = (int64_t)b->jobs.size();
+    std::vector<LaneSide> sides;
+    std::vector<double> side_cost;
+    b->tile_sides.clear();
+    b->single_recon.clear();
+    std::vector<ReconJob> rjobs;
+
+    for (int64_t j = 0; j < nj; ++j) {
+        const rpca_job &J = b->jobs[j];
+        BatchJobState &S = b->js[j];
+        const int ru = S.so.r_used;
+        const int64_t *dIc = reinterpret_cast<const int64_t *>(b->at(S.o_Ic));
+        const int64_t *dJc = reinterpret_cast<const int64_t *>(b->at(S.o_Jc));
+        const double *dU = reinterpret_cast<const double *>(b->at(S.o_U));
+        const double *dsig = reinterpret_cast<const double *>(b->at(S.o_sig));
+        const double *dV = reinterpret_cast<const double *>(b->at(S.o_V));
+        float *dQt = reinterpret_cast<float *>(b->at(S.o_Qt));
+        float *dPt = reinterpret_cast<float *>(b->at(S.o_Pt));
+        int32_t *dit = reinterpret_cast<int32_t *>(b->at(S.o_it));
+        // column side: elements = seed rows (p), regressions = J_c, basis U
+        if (S.nc > 0) {
+            if (S.lane_cols) {
+                LaneSide ls{J.M, J.seed_rows, dJc, 1, J.ldm, J.m, J.n, dU, S.nc, dQt, ru, dit,
+                            (int32_t)J.p, (int32_t)J.p, ru, lane_class((int)J.p, ru)};
+                sides.push_back(ls);
+                side_cost.push_back(lane_item_cost((int)J.p, ru));
+            } else {
+                b->tile_sides.push_back(FilterSide{J.M, J.seed_rows, dJc, 1, J.ldm, J.m, J.n, dU,
+                                                   (int32_t)J.p, (int32_t)J.p, ru, S.nc, dQt, ru,
+                                                   dit, nullptr});
+            }
+        }
+        // row side: elements = seed columns (q), regressions = I_c, basis V
+        if (S.mc > 0) {
+            if (S.lane_rows) {
+                LaneSide ls{J.M, J.seed_cols, dIc, J.ldm, 1, J.n, J.m, dV, S.mc, dPt, ru,
+                            dit + S.nc, (int32_t)J.q, (int32_t)J.q, ru, lane_class((int)J.q, ru)};
+                sides.push_back(ls);
+                side_cost.push_back(lane_item_cost((int)J.q, ru));
+            } else {
+                b->tile_sides.push_back(FilterSide{J.M, J.seed_cols, dIc, J.ldm, 1, J.n, J.m, dV,
+                                                   (int32_t)J.q, (int32_t)J.q, ru, S.mc, dPt, ru,
+                                                   dit + S.nc, nullptr});
+            }
+        }
+        ReconArgs a{J.M, J.m, J.n, J.ldm, J.seed_rows, J.p, J.seed_cols, J.q, dU, dsig, dV, ru,
+                    dQt, dPt, J.L, J.ldl, J.S, J.lds};
+        const int R4 = (ru + 3) / 4 * 4;   // <= S.R4, the class the workspace was laid out for
+        if (S.R4 <= 8) {
+            ReconJob rj{};
+            rj.M = J.M;
+            rj.L = J.L;
+            rj.S = J.S;
+            rj.F = reinterpret_cast<const float *>(b->at(S.o_F));
+            rj.G = rj.F + (size_t)J.m * R4;
+            rj.m = J.m;
+            rj.n = J.n;
+            rj.ldm = J.ldm;
+            rj.ldl = J.ldl;
+            rj.lds = J.lds;
+            rj.seed_rows = J.seed_rows;
+            rj.seed_cols = J.seed_cols;
+            rj.p = J.p;
+            rj.q = J.q;
+            rj.U = dU;
+            rj.sigma = dsig;
+            rj.V = dV;
+            rj.Qt = dQt;
+            rj.Pt = dPt;
+            rj.r = ru;
+            rj.R4 = R4;
+            rj.vec = (J.ldm % 4 == 0) && (J.ldl % 4 == 0) && (J.lds % 4 == 0) &&
+                     ((uintptr_t)J.M % 16 == 0) && ((uintptr_t)J.L % 16 == 0) &&
+                     ((uintptr_t)J.S % 16 == 0);
+            const int64_t cpw = std::max<int32_t>(1, b->tun.recon_cols_per_wave);
+            rj.row_blocks = (uint32_t)((J.m + 255) / 256);
+            rj.col_parts = (uint32_t)std::max<int64_t>(1, std::min<int64_t>(J.n, (J.n + cpw - 1) / cpw));
+            rjobs.push_back(rj);
+        } else {
+            b->single_recon.push_back(a);
+        }
+    }
+
+    // work queue: items of 64 regressions, costliest sides first (or job order)
+    std::vector<int32_t> order(sides.size());
+    std::iota(order.begin(), order.end(), 0);
+    if (b->tun.order == 0)
+        std::stable_sort(order.begin(), order.end(),
+                         [&](int32_t x, int32_t y) { return side_cost[x] > side_cost[y]; });
+    std::vector<int32_t> items;
+    int64_t group_items[2] = {0, 0};
+    for (int g = 1; g >= 0; --g) {      // group 1 (large state) first
+        for (int32_t sidx : order) {
+            if (lane_group(sides[sidx].cls) != g) continue;
+            const int64_t nreg = sides[sidx].nreg;
+            for (int64_t f = 0; f < nreg; f += 64) {
+                if (f > INT32_MAX) return set_status(ctx, RPCA_ERR_UNSUPPORTED, "batch: too many regressions in one side");
+                items.push_back(sidx);
+                items.push_back((int32_t)f);
+                ++group_items[g];
+            }
+        }
+    }
+    const int64_t nitems = (int64_t)items.size() / 2;
+    if (nitems > INT32_MAX) return set_status(ctx, RPCA_ERR_UNSUPPORTED, "batch: too many work items");
+
+    // completion tables
+    std::vector<int32_t> asm_job, rec_job;
+    std::vector<int64_t> asm_first;
+    std::vector<uint32_t> rec_local;
+    for (size_t k = 0; k < rjobs.size(); ++k) {
+        const ReconJob &rj = rjobs[k];
+        const int64_t threads = rj.m + rj.n;
+        for (int64_t f = 0; f < threads; f += 256) {
+            asm_job.push_back((int32_t)k);
+            asm_first.push_back(f);
+        }
+        const uint64_t waves = (uint64_t)rj.row_blocks * rj.col_parts;
+        if (waves > UINT32_MAX) return set_status(ctx, RPCA_ERR_UNSUPPORTED, "batch: completion grid too large");
+        for (uint64_t w = 0; w < waves; ++w) {
+            rec_job.push_back((int32_t)k);
+            rec_local.push_back((uint32_t)w);
+        }
+    }
+    if (asm_job.size() > (size_t)INT32_MAX || rec_job.size() > (size_t)INT32_MAX)
+        return set_status(ctx, RPCA_ERR_UNSUPPORTED, "batch: completion grid too large");
+
+    // one device buffer: sides | items | counter | jobs | asm tables | rec tables
+    size_t off = 0;
+    const size_t o_sides = off; off = align_up(off + sides.size() * sizeof(LaneSide), 256);
+    const size_t o_items = off; off = align_up(off + items.size() * sizeof(int32_t), 256);
+    const size_t o_ctr = off;   off = align_up(off + 256, 256);
+    const size_t o_jobs = off;  off = align_up(off + rjobs.size() * sizeof(ReconJob), 256);
+    const size_t o_aj = off;    off = align_up(off + asm_job.size() * sizeof(int32_t), 256);
+    const size_t o_af = off;    off = align_up(off + asm_first.size() * sizeof(int64_t), 256);
+    const size_t o_rj = off;    off = align_up(off + rec_job.size() * sizeof(int32_t), 256);
+    const size_t o_rl = off;    off = align_up(off + rec_local.size() * sizeof(uint32_t), 256);
+    int st = ensure_buf(ctx, b->tables, off);
+    if (st != RPCA_OK) return st;
+    char *base = static_cast<char *>(b->tables.ptr);
+    auto put = [&](size_t o, const void *src, size_t bytes) -> hipError_t {
+        return bytes ? hipMemcpy(base + o, src, bytes, hipMemcpyHostToDevice) : hipSuccess;
+    };
+    RPCA_HIP_TRY(ctx, put(o_sides, sides.data(), sides.size() * sizeof(LaneSide)));
+    RPCA_HIP_TRY(ctx, put(o_items, items.data(), items.size() * sizeof(int32_t)));
+    RPCA_HIP_TRY(ctx, put(o_jobs, rjobs.data(), rjobs.size() * sizeof(ReconJob)));
+    RPCA_HIP_TRY(ctx, put(o_aj, asm_job.data(), asm_job.size() * sizeof(int32_t)));
+    RPCA_HIP_TRY(ctx, put(o_af, asm_first.data(), asm_first.size() * sizeof(int64_t)));
+    RPCA_HIP_TRY(ctx, put(o_rj, rec_job.data(), rec_job.size() * sizeof(int32_t)));
+    RPCA_HIP_TRY(ctx, put(o_rl, rec_local.data(), rec_local.size() * sizeof(uint32_t)));
+
+    BatchTables &t = b->bt;
+    t.sides = reinterpret_cast<const LaneSide *>(base + o_sides);
+    t.items = reinterpret_cast<const int32_t *>(base + o_items);
+    t.counter = reinterpret_cast<uint32_t *>(base + o_ctr);
+    const int64_t wpc = b->tun.filter_waves_per_cu > 0 ? b->tun.filter_waves_per_cu : 8;
+    for (int g = 0; g < 2; ++g) {
+        // group 1 runs one wave per SIMD (its state needs the whole register file)
+        const int64_t per_cu = g == 0 ? wpc : std::min<int64_t>(wpc, 4);
+        t.group_items[g] = (int32_t)group_items[g];
+        t.grid_waves[g] = (int32_t)std::max<int64_t>(
+            1, std::min<int64_t>(group_items[g], per_cu * std::max(1, ctx->num_cu)));
+    }
+    t.jobs = reinterpret_cast<const ReconJob *>(base + o_jobs);
+    t.asm_block_job = reinterpret_cast<const int32_t *>(base + o_aj);
+    t.asm_block_first = reinterpret_cast<const int64_t *>(base + o_af);
+    t.asm_blocks = (int32_t)asm_job.size();
+    t.rec_block_job = reinterpret_cast<const int32_t *>(base + o_rj);
+    t.rec_block_local = reinterpret_cast<const uint32_t *>(base + o_rl);
+    t.rec_blocks = (int32_t)rec_job.size();
+    return RPCA_OK;
+}
+
+} // namespace
+
+extern "C" {
+
+void rpca_batch_tuning_default(rpca_batch_tuning *t)
+{
+    if (!t) return;
+    t->lane_max_p = kLaneMaxP;
+    t->lane_max_r = kLaneMaxR;
+    t->filter_waves_per_cu = 8;
+    t->recon_cols_per_wave = 32;
+    t->order = 0;
+    t->graph = 1;
+}
+
+int rpca_batch_create(rpca_ctx_t ctx, const rpca_job *jobs, int64_t njobs, const rpca_opts *opts,
+                      const rpca_batch_tuning *tuning, rpca_batch_t *out)
+{
+    if (!ctx) return RPCA_ERR_ARG;
+    ctx->last_error.clear();
+    if (!out) return set_status(ctx, RPCA_ERR_ARG, "batch: NULL output handle");
+    *out = nullptr;
+    if (!jobs || njobs < 1) return set_status(ctx, RPCA_ERR_ARG, "batch: need at least one job");
+    if (!opts) return set_status(ctx, RPCA_ERR_ARG, "batch: NULL opts");
+    const rpca_opts o = *opts;
+    int cst = check_opts(ctx, o);
+    if (cst != RPCA_OK) return cst;
+    rpca_batch_tuning tun;
+    rpca_batch_tuning_default(&tun);
+    if (tuning) tun = *tuning;
+    if (tun.lane_max_p < 0 || tun.lane_max_p > kLaneMaxP || tun.lane_max_r < 0 ||
+        tun.lane_max_r > kLaneMaxR || tun.filter_waves_per_cu < 0 || tun.filter_waves_per_cu > 64 ||
+        tun.recon_cols_per_wave < 1 || (tun.order != 0 && tun.order != 1) ||
+        (tun.graph != 0 && tun.graph != 1))
+        return set_status(ctx, RPCA_ERR_ARG, "batch: bad tuning");
+    RPCA_HIP_TRY(ctx, hipSetDevice(ctx->device));
+
+    rpca_batch *b = new rpca_batch();
+    b->ctx = ctx;
+    b->opts = o;
+    b->tun = tun;
+    b->jobs.assign(jobs, jobs + njobs);
+    b->js.resize((size_t)njobs);
+    auto bail = [&](int st) {
+        rpca_batch_destroy(b);
+        return st;
+    };
+
+    // checks and workspace layout
+    std::vector<std::vector<int64_t>> Ic((size_t)njobs), Jc((size_t)njobs);
+    size_t off = 0;
+    for (int64_t j = 0; j < njobs; ++j) {
+        const rpca_job &J = b->jobs[j];
+        BatchJobState &S = b->js[j];
+        const std::string nm = "batch job " + std::to_string(j);
+        if (!J.M || !J.L || !J.S || !J.seed_rows || !J.seed_cols)
+            return bail(set_status(ctx, RPCA_ERR_ARG, nm + ": NULL pointer"));
+        if (J.m < 1 || J.n < 1 || J.ldm < J.m || J.ldl < J.m || J.lds < J.m)
+            return bail(set_status(ctx, RPCA_ERR_ARG, nm + ": bad sizes or leading dimensions"));
+        if (J.r < 1 || J.p < 1 || J.q < 1 || J.p > J.m || J.q > J.n || J.r > std::min(J.p, J.q))
+            return bail(set_status(ctx, RPCA_ERR_ARG, nm + ": need 1 <= r <= min(p, q), p <= m, q <= n"));
+        if ((const void *)J.L == (const void *)J.S || (const void *)J.L == (const void *)J.M ||
+            (const void *)J.S == (const void *)J.M)
+            return bail(set_status(ctx, RPCA_ERR_ARG, nm + ": L, S and M must be distinct buffers"));
+        std::vector<int64_t> I, Jv;
+        int st = fetch_sorted(ctx, J.seed_rows, J.p, J.m, nm + " seed_rows", I);
+        if (st != RPCA_OK) return bail(st);
+        if ((st = fetch_sorted(ctx, J.seed_cols, J.q, J.n, nm + " seed_cols", Jv)) != RPCA_OK) return bail(st);
+        Ic[j] = complement_sorted(I, J.m);
+        Jc[j] = complement_sorted(Jv, J.n);
+        S.mc = (int64_t)Ic[j].size();
+        S.nc = (int64_t)Jc[j].size();
+        // filter form of each side; the completion's rank class
+        const bool lane_r = J.r <= tun.lane_max_r;
+        S.lane_cols = lane_r && J.p <= tun.lane_max_p && lane_class((int)J.p, J.r) >= 0;
+        S.lane_rows = lane_r && J.q <= tun.lane_max_p && lane_class((int)J.q, J.r) >= 0;
+        for (int rr = 1; rr <= J.r; ++rr) {   // any seed rank up to r must have a kernel
+            if ((!S.lane_cols && S.nc > 0 && !filter_supported(ctx, (int)J.p, rr, o.precision)) ||
+                (!S.lane_rows && S.mc > 0 && !filter_supported(ctx, (int)J.q, rr, o.precision)))
+                return bail(set_status(ctx, RPCA_ERR_UNSUPPORTED, nm + ": seed size outside the built kernel classes"));
+        }
+        S.R4 = (J.r + 3) / 4 * 4;
+        if (S.R4 > 64) return bail(set_status(ctx, RPCA_ERR_UNSUPPORTED, nm + ": rank above 64"));
+        S.o_Ic = off; off = align_up(off + (size_t)S.mc * 8, 256);
+        S.o_Jc = off; off = align_up(off + (size_t)S.nc * 8, 256);
+        S.o_U = off;  off = align_up(off + (size_t)J.p * J.r * 8, 256);
+        S.o_sig = off; off = align_up(off + (size_t)J.r * 8, 256);
+        S.o_V = off;  off = align_up(off + (size_t)J.q * J.r * 8, 256);
+        S.o_Qt = off; off = align_up(off + (size_t)S.nc * J.r * 4, 256);
+        S.o_Pt = off; off = align_up(off + (size_t)S.mc * J.r * 4, 256);
+        S.o_it = off; off = align_up(off + (size_t)(S.nc + S.mc) * 4, 256);
+        S.o_F = off;
+        if (S.R4 <= 8) off = align_up(off + (size_t)(J.m + J.n) * S.R4 * 4, 256);
+    }
+    int st = ensure_buf(ctx, b->ws, std::max<size_t>(off, 256));
+    if (st != RPCA_OK) return bail(st);
+    for (int64_t j = 0; j < njobs; ++j) {
+        const BatchJobState &S = b->js[j];
+        if (S.mc) RPCA_HIP_TRY(ctx, hipMemcpy(b->at(S.o_Ic), Ic[j].data(), S.mc * 8, hipMemcpyHostToDevice));
+        if (S.nc) RPCA_HIP_TRY(ctx, hipMemcpy(b->at(S.o_Jc), Jc[j].data(), S.nc * 8, hipMemcpyHostToDevice));
+    }
+
+    // the batch's own launch workspace, stream and events
+    b->wctx = new rpca_ctx();
+    b->wctx->device = ctx->device;
+    b->wctx->num_cu = ctx->num_cu;
+    b->wctx->max_lds = ctx->max_lds;
+    b->wctx->recon_waves_per_cu = ctx->recon_waves_per_cu;
+    if (hipStreamCreateWithFlags(&b->bs, hipStreamNonBlocking) != hipSuccess)
+        return bail(set_status(ctx, RPCA_ERR_DEVICE, "batch: hipStreamCreate failed"));
+    for (auto &e : b->ev)
+        if (hipEventCreate(&e) != hipSuccess)
+            return bail(set_status(ctx, RPCA_ERR_DEVICE, "batch: hipEventCreate failed"));
+    *out = b;
+    return RPCA_OK;
+}
+
+int rpca_batch_seed(rpca_batch_t b)
+{
+    if (!b) return RPCA_ERR_ARG;
+    rpca_ctx *ctx = b->ctx;
+    ctx->last_error.clear();
+    RPCA_HIP_TRY(ctx, hipSetDevice(ctx->device));
+    RPCA_HIP_TRY(ctx, hipStreamSynchronize(b->bs));
+    b->seeded = false;
+    drop_graphs(b);
+    int worst = RPCA_OK;
+    std::string worst_msg;
+    for (size_t j = 0; j < b->jobs.size(); ++j) {
+        const rpca_job &J = b->jobs[j];
+        BatchJobState &S = b->js[j];
+        const auto t0 = std::chrono::steady_clock::now();
+        S.so = SeedOut{};
+        S.seed_status = run_seed(ctx, J.M, J.ldm, J.seed_rows, J.p, J.seed_cols, J.q, J.r, b->opts,
+                                 reinterpret_cast<double *>(b->at(S.o_U)),
+                                 reinterpret_cast<double *>(b->at(S.o_sig)),
+                                 reinterpret_cast<double *>(b->at(S.o_V)), &S.so, nullptr);
+        S.t_seed_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+        if (S.seed_status < 0)
+            return set_status(ctx, S.seed_status, "batch job " + std::to_string(j) + ": " + ctx->last_error);
+        if (S.seed_status > 0 && worst == RPCA_OK) {
+            worst = S.seed_status;
+            worst_msg = "batch job " + std::to_string(j) + ": " + ctx->last_error;
+        }
+    }
+    RPCA_HIP_TRY(ctx, hipDeviceSynchronize());
+    int st = build_tables(b);
+    if (st != RPCA_OK) return st;
+    b->seeded = true;
+    b->runs = 0;
+    if (worst != RPCA_OK) return set_status(ctx, worst, worst_msg);
+    ctx->last_error.clear();
+    return RPCA_OK;
+}
+
+int rpca_batch_run(rpca_batch_t b, hipStream_t stream)
+{
+    if (!b) return RPCA_ERR_ARG;
+    rpca_ctx *ctx = b->ctx;
+    ctx->last_error.clear();
+    if (!b->seeded) return set_status(ctx, RPCA_ERR_ARG, "batch: run before a successful rpca_batch_seed");
+    RPCA_HIP_TRY(ctx, hipSetDevice(ctx->device));
+    // order after the caller's stream, run on the batch's stream, order back
+    RPCA_HIP_TRY(ctx, hipEventRecord(b->ev[3], stream));
+    RPCA_HIP_TRY(ctx, hipStreamWaitEvent(b->bs, b->ev[3], 0));
+    int st;
+    if (b->tun.graph && b->runs >= 1 && !b->exec[0]) {
+        // capture once the first (eager) run has sized every workspace
+        for (int g = 0; g < 2; ++g) {
+            RPCA_HIP_TRY(ctx, hipStreamBeginCapture(b->bs, hipStreamCaptureModeThreadLocal));
+            st = g == 0 ? enqueue_filter(b, b->bs) : enqueue_recon(b, b->bs);
+            hipGraph_t graph = nullptr;
+            const hipError_t e = hipStreamEndCapture(b->bs, &graph);
+            if (st != RPCA_OK) {
+                if (graph) (void)hipGraphDestroy(graph);
+                drop_graphs(b);
+                return st;
+            }
+            if (e != hipSuccess) {
+                drop_graphs(b);
+                return set_status(ctx, RPCA_ERR_DEVICE, std::string("batch: graph capture: ") + hipGetErrorString(e));
+            }
+            b->graph[g] = graph;
+            if (hipGraphInstantiate(&b->exec[g], graph, nullptr, nullptr, 0) != hipSuccess) {
+                drop_graphs(b);
+                return set_status(ctx, RPCA_ERR_DEVICE, "batch: hipGraphInstantiate failed");
+            }
+        }
+    }
+    RPCA_HIP_TRY(ctx, hipEventRecord(b->ev[0], b->bs));
+    if (b->exec[0]) {
+        RPCA_HIP_TRY(ctx, hipGraphLaunch(b->exec[0], b->bs));
+        RPCA_HIP_TRY(ctx, hipEventRecord(b->ev[1], b->bs));
+        RPCA_HIP_TRY(ctx, hipGraphLaunch(b->exec[1], b->bs));
+    } else {
+        if ((st = enqueue_filter(b, b->bs)) != RPCA_OK) return st;
+        RPCA_HIP_TRY(ctx, hipEventRecord(b->ev[1], b->bs));
+        if ((st = enqueue_recon(b, b->bs)) != RPCA_OK) return st;
+    }
+    RPCA_HIP_TRY(ctx, hipEventRecord(b->ev[2], b->bs));
+    RPCA_HIP_TRY(ctx, hipStreamWaitEvent(stream, b->ev[2], 0));
+    ++b->runs;
+    return RPCA_OK;
+}
+
+int rpca_batch_job_info(rpca_batch_t b, int64_t job, rpca_info *info)
+{
+    if (!b) return RPCA_ERR_ARG;
+    rpca_ctx *ctx = b->ctx;
+    ctx->last_error.clear();
+    if (!info || job < 0 || job >= (int64_t)b->jobs.size())
+        return set_status(ctx, RPCA_ERR_ARG, "batch: bad job index or NULL info");
+    RPCA_HIP_TRY(ctx, hipSetDevice(ctx->device));
+    RPCA_HIP_TRY(ctx, hipStreamSynchronize(b->bs));
+    const BatchJobState &S = b->js[job];
+    std::vector<int32_t> its((size_t)(S.nc + S.mc));
+    int64_t total = 0, bad = 0;
+    int32_t kmax = 0;
+    if (b->runs > 0 && !its.empty()) {
+        RPCA_HIP_TRY(ctx, hipMemcpy(its.data(), b->at(S.o_it), its.size() * 4, hipMemcpyDeviceToHost));
+        for (int32_t k : its) {
+            if (k < 0) ++bad;
+            const int32_t ak = k < 0 ? -k : k;
+            total += ak;
+            kmax = std::max(kmax, ak);
+        }
+    }
+    float tf = 0, tr = 0;
+    if (b->runs > 0) {
+        (void)hipEventElapsedTime(&tf, b->ev[0], b->ev[1]);
+        (void)hipEventElapsedTime(&tr, b->ev[1], b->ev[2]);
+    }
+    info->r_used = S.so.r_used;
+    info->seed_iters = S.so.iters;
+    info->seed_converged = S.so.converged;
+    info->filt_iters_max = kmax;
+    info->filt_iters_total = total;
+    info->filt_not_converged = bad;
+    info->t_seed_ms = S.t_seed_ms;
+    info->t_filter_ms = tf;
+    info->t_reconstruct_ms = tr;
+    return S.seed_status > 0 ? S.seed_status : (bad ? RPCA_WARN_NOT_CONVERGED : RPCA_OK);
+}
+
+int rpca_batch_destroy(rpca_batch_t b)
+{
+    if (!b) return RPCA_ERR_ARG;
+    (void)hipSetDevice(b->ctx->device);
+    if (b->bs) (void)hipStreamSynchronize(b->bs);
+    drop_graphs(b);
+    for (DevBuf *d : {&b->ws, &b->tables})
+        if (d->ptr) (void)hipFree(d->ptr);
+    if (b->wctx) {
+        for (DevBuf *d : {&b->wctx->factors, &b->wctx->xbuf_ws, &b->wctx->frag_ws, &b->wctx->scratch,
+                          &b->wctx->solve_ws, &b->wctx->seed_ws})
+            if (d->ptr) (void)hipFree(d->ptr);
+        delete b->wctx;
+    }
+    for (auto &e : b->ev)
+        if (e) (void)hipEventDestroy(e);
+    if (b->bs) (void)hipStreamDestroy(b->bs);
+    delete b;
+    return RPCA_OK;
+}
+
+} // extern "C"

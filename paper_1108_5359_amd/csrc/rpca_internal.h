@@ -38,6 +38,12 @@ int set_status(rpca_ctx *ctx, int status, const std::string &msg);
 // Make sure buf holds at least `bytes`; returns RPCA_OK or RPCA_ERR_NOMEM.
 int ensure_buf(rpca_ctx *ctx, DevBuf &buf, size_t bytes);
 
+struct FilterConsts;
+// Range checks of the options (RPCA_ERR_ARG with a message on failure).
+int check_opts(rpca_ctx *ctx, const rpca_opts &o);
+// The filter's constants in the precision the kernels use.
+FilterConsts consts_of(const rpca_opts &o);
+
 #define RPCA_HIP_TRY(ctx, expr)                                                        \
     do {                                                                               \
         hipError_t _e = (expr);                                                        \
@@ -116,3 +122,66 @@ struct SeedOut {
 int run_seed(rpca_ctx *ctx, const float *M, int64_t ldm, const int64_t *seed_rows, int64_t p,
              const int64_t *seed_cols, int64_t q, int32_t r, const rpca_opts &o, double *U,
              double *sigma, double *V, SeedOut *out, hipStream_t stream);
+
+// ---------------------------------------------------------------- batched form
+// One side (columns or rows) of one problem, filtered in the lane form: one
+// regression per lane, p <= kLaneMaxP, r <= kLaneMaxR.  Fields mean what
+// they mean in FilterSide; cls is the compiled (P4, RB) class index.
+constexpr int kLaneMaxP = 80;
+constexpr int kLaneMaxR = 8;
+
+struct LaneSide {
+    const float *M;
+    const int64_t *elem_idx;
+    const int64_t *reg_idx;
+    int64_t elem_stride, reg_stride;
+    int64_t elem_bound, reg_bound;
+    const double *A;
+    int64_t nreg;
+    float *Z;
+    int64_t ldz;
+    int32_t *iters;
+    int32_t lda, p, r, cls;
+};
+
+// Class index of (p, r) in the lane form, or -1 outside it, and the class
+// group (kernel) it runs in.
+int lane_class(int p, int r);
+int lane_group(int cls);
+
+// Completion of one problem inside the batched launch (R4 in {4, 8}).
+struct ReconJob {
+    const float *M;
+    float *L, *S;
+    const float *F, *G;          // assembled factors, m x R4 and n x R4 row-major
+    int64_t m, n, ldm, ldl, lds;
+    const int64_t *seed_rows, *seed_cols;
+    int64_t p, q;
+    const double *U, *sigma, *V;
+    const float *Qt, *Pt;
+    int32_t r, R4, vec;
+    uint32_t row_blocks, col_parts;   // completion waves of this problem: row_blocks x col_parts
+};
+
+// The device tables of a batched run.
+struct BatchTables {
+    const LaneSide *sides;
+    const int32_t *items;        // 2 per item: side index, first regression; group 1 first
+    int32_t group_items[2];      // items of class group 0 (P4 <= 10) and group 1
+    uint32_t *counter;           // two work-queue heads (reset by the launch itself)
+    int32_t grid_waves[2];       // persistent waves of each group's kernel
+    const ReconJob *jobs;
+    const int32_t *asm_block_job;    // job of each workgroup of the factor assembly
+    const int64_t *asm_block_first;  // the job's thread index of that workgroup's thread 0
+    int32_t asm_blocks;
+    const int32_t *rec_block_job;    // job of each completion wave
+    const uint32_t *rec_block_local; // its index among the job's waves
+    int32_t rec_blocks;
+};
+
+// Enqueue the lane-form filter over every item (queue reset included).
+int launch_lane_filter(rpca_ctx *ctx, const BatchTables &t, const FilterConsts &c,
+                       hipStream_t stream);
+
+// Enqueue factor assembly + completion of every job of the table.
+int launch_batch_reconstruct(rpca_ctx *ctx, const BatchTables &t, hipStream_t stream);

@@ -217,3 +217,104 @@ def rpca_solve(ctx: Context, M, m, n, ldm, r, opts, seed_rows, seed_cols, L, ldl
                                   _ptr(seed_rows), _ptr(seed_cols), _ptr(L), ldl, _ptr(S), lds,
                                   ctypes.byref(info), _stream(stream)))
     return st, info
+
+
+# ---------------------------------------------------------------- batched form
+class rpca_job(ctypes.Structure):
+    _fields_ = [
+        ("M", _vp), ("m", _i64), ("n", _i64), ("ldm", _i64), ("r", _i32),
+        ("seed_rows", _vp), ("p", _i64), ("seed_cols", _vp), ("q", _i64),
+        ("L", _vp), ("ldl", _i64), ("S", _vp), ("lds", _i64),
+    ]
+
+
+class rpca_batch_tuning(ctypes.Structure):
+    _fields_ = [
+        ("lane_max_p", _i32), ("lane_max_r", _i32), ("filter_waves_per_cu", _i32),
+        ("recon_cols_per_wave", _i32), ("order", _i32), ("graph", _i32),
+    ]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+lib.rpca_batch_tuning_default.argtypes = [ctypes.POINTER(rpca_batch_tuning)]
+lib.rpca_batch_tuning_default.restype = None
+lib.rpca_batch_create.argtypes = [_vp, ctypes.POINTER(rpca_job), _i64, ctypes.POINTER(rpca_opts),
+                                  ctypes.POINTER(rpca_batch_tuning), ctypes.POINTER(_vp)]
+lib.rpca_batch_seed.argtypes = [_vp]
+lib.rpca_batch_run.argtypes = [_vp, _vp]
+lib.rpca_batch_job_info.argtypes = [_vp, _i64, ctypes.POINTER(rpca_info)]
+lib.rpca_batch_destroy.argtypes = [_vp]
+for _f in ("rpca_batch_create", "rpca_batch_seed", "rpca_batch_run", "rpca_batch_job_info",
+           "rpca_batch_destroy"):
+    getattr(lib, _f).restype = ctypes.c_int
+
+
+def rpca_batch_tuning_default(**overrides) -> rpca_batch_tuning:
+    t = rpca_batch_tuning()
+    lib.rpca_batch_tuning_default(ctypes.byref(t))
+    for k, v in overrides.items():
+        if not hasattr(t, k):
+            raise AttributeError(k)
+        setattr(t, k, v)
+    return t
+
+
+def job(M, m, n, ldm, r, seed_rows, p, seed_cols, q, L, ldl, S, lds) -> rpca_job:
+    """One ``rpca_job`` from device tensors (kept alive by the caller)."""
+    return rpca_job(_ptr(M), m, n, ldm, r, _ptr(seed_rows), p, _ptr(seed_cols), q, _ptr(L), ldl,
+                    _ptr(S), lds)
+
+
+class Batch:
+    """Owns an ``rpca_batch_t``; errors are reported on the owner context."""
+
+    def __init__(self, ctx: Context, jobs, opts, tuning=None):
+        arr = (rpca_job * len(jobs))(*jobs)
+        h = _vp()
+        ctx.check(lib.rpca_batch_create(ctx.handle, arr, len(jobs), ctypes.byref(opts),
+                                        ctypes.byref(tuning) if tuning is not None else None,
+                                        ctypes.byref(h)))
+        self.ctx = ctx
+        self.handle = h
+        self.njobs = len(jobs)
+
+    def close(self):
+        if self.handle:
+            lib.rpca_batch_destroy(self.handle)
+            self.handle = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def rpca_batch_create(ctx: Context, jobs, opts, tuning=None) -> Batch:
+    return Batch(ctx, jobs, opts, tuning)
+
+
+def rpca_batch_seed(batch: Batch) -> int:
+    return batch.ctx.check(lib.rpca_batch_seed(batch.handle))
+
+
+def rpca_batch_run(batch: Batch, stream=None) -> int:
+    return batch.ctx.check(lib.rpca_batch_run(batch.handle, _stream(stream)))
+
+
+def rpca_batch_job_info(batch: Batch, job_index: int):
+    info = rpca_info()
+    st = batch.ctx.check(lib.rpca_batch_job_info(batch.handle, job_index, ctypes.byref(info)))
+    return st, info
+
+
+def rpca_batch_destroy(batch: Batch) -> None:
+    batch.close()

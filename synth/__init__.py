@@ -38,6 +38,13 @@ __all__ = [
     "hash_uniform",
     "CONFIGS",
     "config_problem",
+    "BATCH_C4",
+    "BatchJobSpec",
+    "batch_specs",
+    "block_rectangles",
+    "union_fraction",
+    "batch_job_host",
+    "batch_job_device",
 ]
 
 _GOLDEN = np.uint64(0x9E3779B97F4A7C15)
@@ -237,4 +244,127 @@ def lowrank_plus_sparse_device(m: int, n: int, r: int, *, factor_std: float, spa
         blk += torch.where(hit, vals, torch.zeros_like(vals))
         Mt[j0:j1] = blk.to(torch.float32)
         del lin, hit, u, vals, blk
+    return Mt, A0, B0
+
+
+# ---------------------------------------------------------------------------
+# Batches of independent problems shaped like video background modelling
+# (pixels x frames, low rank plus block-shaped foreground).  Each job draws
+# m, n, r, a corruption fraction rho and a list of rectangles on the host
+# (PCG64); the entries of M are then a pure function of the job's seed, so
+# the host and the device paint identical matrices.
+#
+# Corruptions (block reading): rectangles of height ~ U[m/50, m/10] and width
+# ~ U[n/20, n/5] at uniform positions are added until their union covers at
+# least rho of the matrix; every entry of the union gets a value U[0, 1]
+# keyed by the entry's column-major linear index.
+# ---------------------------------------------------------------------------
+BATCH_C4 = dict(njobs=256, m=(2048, 76800), n=(100, 1000), r=(1, 8), rho=(0.05, 0.15), os=10)
+
+
+@dataclasses.dataclass
+class BatchJobSpec:
+    m: int
+    n: int
+    r: int
+    rho: float
+    rects: list          # (i0, i1, j0, j1), half-open
+    seed: int            # factors, values and seed indices
+
+    @property
+    def p(self) -> int:
+        return BATCH_C4["os"] * self.r
+
+    @property
+    def q(self) -> int:
+        return BATCH_C4["os"] * self.r
+
+
+def union_fraction(rects, m: int, n: int) -> float:
+    """Exact area of the union of half-open rectangles, over m*n
+    (coordinate compression: the union is constant on the compressed cells)."""
+    if not rects:
+        return 0.0
+    ys = sorted({0, m, *[r[0] for r in rects], *[r[1] for r in rects]})
+    xs = sorted({0, n, *[r[2] for r in rects], *[r[3] for r in rects]})
+    yi = {v: k for k, v in enumerate(ys)}
+    xi = {v: k for k, v in enumerate(xs)}
+    cov = np.zeros((len(ys) - 1, len(xs) - 1), dtype=bool)
+    for i0, i1, j0, j1 in rects:
+        cov[yi[i0]:yi[i1], xi[j0]:xi[j1]] = True
+    h = np.diff(np.asarray(ys, dtype=np.float64))
+    w = np.diff(np.asarray(xs, dtype=np.float64))
+    return float((h[:, None] * w[None, :] * cov).sum() / (float(m) * n))
+
+
+def block_rectangles(rng: np.random.Generator, m: int, n: int, rho: float) -> list:
+    rects = []
+    hmin, hmax = max(1, -(-m // 50)), max(1, m // 10)
+    wmin, wmax = max(1, -(-n // 20)), max(1, n // 5)
+    while union_fraction(rects, m, n) < rho:
+        h = int(rng.integers(hmin, max(hmin, hmax) + 1))
+        w = int(rng.integers(wmin, max(wmin, wmax) + 1))
+        i0 = int(rng.integers(0, m - h + 1))
+        j0 = int(rng.integers(0, n - w + 1))
+        rects.append((i0, i0 + h, j0, j0 + w))
+    return rects
+
+
+def batch_specs(njobs: int = 256, seed: int = 1, m=(2048, 76800), n=(100, 1000), r=(1, 8),
+                rho=(0.05, 0.15)) -> list:
+    """Job shapes and corruption rectangles (uniform integer ranges, inclusive)."""
+    rng = np.random.Generator(np.random.PCG64([seed, 0xBA7C4]))
+    specs = []
+    for j in range(njobs):
+        mj = int(rng.integers(m[0], m[1] + 1))
+        nj = int(rng.integers(n[0], n[1] + 1))
+        rj = int(rng.integers(r[0], r[1] + 1))
+        rhoj = float(rng.uniform(rho[0], rho[1]))
+        rects = block_rectangles(rng, mj, nj, rhoj)
+        specs.append(BatchJobSpec(m=mj, n=nj, r=rj, rho=rhoj, rects=rects,
+                                  seed=(seed << 20) + j + 1))
+    return specs
+
+
+def _job_factors(spec: BatchJobSpec):
+    rng = np.random.Generator(np.random.PCG64(spec.seed))
+    std = np.sqrt(1.0 / spec.m)
+    return rng.standard_normal((spec.m, spec.r)) * std, rng.standard_normal((spec.n, spec.r)) * std
+
+
+def batch_job_host(spec: BatchJobSpec, keep_support: bool = True) -> Problem:
+    """M = fl32(A B^T + S0) of one job on the host (Fortran order)."""
+    A0, B0 = _job_factors(spec)
+    m, n = spec.m, spec.n
+    S0 = np.zeros((m, n), order="F")
+    support = np.zeros((m, n), dtype=bool, order="F")
+    for i0, i1, j0, j1 in spec.rects:
+        support[i0:i1, j0:j1] = True
+    jj, ii = np.nonzero(support.T)                     # column-major order
+    lin = jj.astype(np.uint64) * np.uint64(m) + ii.astype(np.uint64)
+    S0[ii, jj] = hash_uniform(spec.seed, 2, lin)
+    M = np.asfortranarray((A0 @ B0.T + S0).astype(np.float32))
+    return Problem(M=M, A0=A0, B0=B0, support=support if keep_support else None, m=m, n=n,
+                   r=spec.r, seed=spec.seed)
+
+
+def batch_job_device(spec: BatchJobSpec, device="cuda", out=None):
+    """The same matrix built on a torch device: returns ``(Mt, A0, B0)`` with
+    ``Mt`` the (n, m) FP32 tensor holding column-major M (or written into
+    ``out`` of that shape)."""
+    import torch
+    A0, B0 = _job_factors(spec)
+    m, n = spec.m, spec.n
+    Ad = torch.from_numpy(A0).to(device)
+    Bd = torch.from_numpy(B0).to(device)
+    L64 = Bd @ Ad.T                                       # (n, m) FP64, column-major M
+    mask = torch.zeros((n, m), dtype=torch.bool, device=device)
+    for i0, i1, j0, j1 in spec.rects:
+        mask[j0:j1, i0:i1] = True
+    lin = mask.view(-1).nonzero().squeeze(1)              # = j m + i, M's linear index
+    L64.view(-1)[lin] += hash_uniform_torch(spec.seed, 2, lin)
+    del mask, lin
+    Mt = out if out is not None else torch.empty((n, m), dtype=torch.float32, device=device)
+    Mt.copy_(L64)
+    del L64
     return Mt, A0, B0
