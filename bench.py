@@ -15,6 +15,12 @@ the FP32 result.
 ``--config c3``: m = n = 50000, r = 50, N(0, 2e-5) factors, 5% corruptions
 uniform in [-1, 1], 500 x 500 seed, precision form (M: 10 GB).
 
+``--config c4``: the batched form, 256 independent problems shaped like video
+background modelling (m ~ U{2048..76800} pixels, n ~ U{100..1000} frames,
+r ~ U{1..8}, N(0, 1/m) factors, 5-15% block foregrounds U[0, 1], 10r x 10r
+seeds; M: 22 GB).  One step is one ``rpca_batch_run``: every regression of
+every problem in the persistent filter kernels, then every completion.
+
 Prints ONE JSON line.  ``value`` = (column + row regressions) per second of
 step time.  ``roofline`` describes the dominant kernel: algorithmic bytes or
 flops per launch over its mean duration measured with HIP events on the launch
@@ -51,6 +57,12 @@ WORKLOADS = {
                     "500x500 seed (FP64), 49500 column + 49500 row regressions of length 500 with "
                     "FP16 MFMA contractions and FP32 refinement, L and S over all 2.5e9 entries"),
 }
+
+
+BATCH = {"c4": dict(njobs=256, precision=0,
+                   text="batched form: 256 problems, m ~ U{2048..76800}, n ~ U{100..1000}, "
+                        "r ~ U{1..8}, N(0,1/m) factors, 5-15% U[0,1] block foregrounds, 10r x 10r "
+                        "seeds; ~1.0e7 regressions of length 10-80; L and S over 5.6e9 entries")}
 
 
 def log(*a):
@@ -155,13 +167,166 @@ class Workload:
         return elapsed, filt_ms, recon_ms, K, unconv
 
 
+class BatchWorkload:
+    """Device-resident batch of independent problems (the c4 recipe)."""
+
+    def __init__(self, name, seed, R, torch, tuning=None):
+        import synth
+        w = BATCH[name]
+        self.name, self.R, self.torch = name, R, torch
+        dev = torch.device("cuda:0")
+        self.dev = dev
+        self.specs = synth.batch_specs(w["njobs"], seed)
+        log(f"bench: generating {name}: {len(self.specs)} problems")
+        self.keep, jobs = [], []
+        t0 = time.perf_counter()
+        for s in self.specs:
+            Md, _, _ = synth.batch_job_device(s, device=dev)
+            I, J = synth.seed_indices(s.m, s.n, s.p, s.q, seed=s.seed)
+            dI, dJ = torch.as_tensor(I).to(dev), torch.as_tensor(J).to(dev)
+            L = torch.empty_like(Md)
+            S = torch.empty_like(Md)
+            self.keep.append((Md, L, S, dI, dJ, I, J))
+            jobs.append(R.job(Md, s.m, s.n, s.m, s.r, dI, s.p, dJ, s.q, L, s.m, S, s.m))
+        torch.cuda.synchronize()
+        log(f"bench: generated in {time.perf_counter() - t0:.1f} s")
+        self.ctx = R.Context(0)
+        self.tuning = tuning if tuning is not None else R.rpca_batch_tuning_default()
+        self.batch = R.Batch(self.ctx, jobs, R.rpca_opts_default(precision=w["precision"]),
+                             self.tuning)
+        self.regs = sum((s.m - s.p) + (s.n - s.q) for s in self.specs)
+        self.elems = sum(s.m * s.n for s in self.specs)
+        self.filter_elems = sum((s.m - s.p) * s.q + (s.n - s.q) * s.p for s in self.specs)
+
+    def seed(self):
+        R = self.R
+        t0 = time.perf_counter()
+        st = R.rpca_batch_seed(self.batch)
+        self.t_seed_ms = (time.perf_counter() - t0) * 1e3
+        self.infos = [R.rpca_batch_job_info(self.batch, k)[1] for k in range(len(self.specs))]
+        ranks = [i.r_used for i in self.infos]
+        log(f"bench: batch seed status={R.rpca_status_string(st)} t={self.t_seed_ms:.0f} ms "
+            f"r_used mean {np.mean(ranks):.2f}")
+
+    def timed(self, steps, warmup):
+        torch, R = self.torch, self.R
+        stream = torch.cuda.current_stream()
+        for _ in range(warmup):
+            R.rpca_batch_run(self.batch, stream)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            R.rpca_batch_run(self.batch, stream)
+        torch.cuda.synchronize()
+        elapsed = time.perf_counter() - t0
+        # phase times (filter / completion) from the batch's own events, one
+        # synchronized run at a time
+        fs, rs = [], []
+        for _ in range(max(3, min(steps, 10))):
+            R.rpca_batch_run(self.batch, stream)
+            info = R.rpca_batch_job_info(self.batch, 0)[1]
+            fs.append(info.t_filter_ms)
+            rs.append(info.t_reconstruct_ms)
+        infos = [R.rpca_batch_job_info(self.batch, k)[1] for k in range(len(self.specs))]
+        return elapsed, float(np.mean(fs)), float(np.mean(rs)), infos
+
+
+def main_batch(args, R, torch):
+    wl = BatchWorkload(args.config, args.seed, R, torch)
+    wl.seed()
+    elapsed, filt_ms, recon_ms, infos = wl.timed(args.steps, args.warmup)
+    ms_per_step = elapsed * 1e3 / args.steps
+    value = wl.regs * args.steps / elapsed
+    iters_total = sum(i.filt_iters_total for i in infos)
+    unconv = sum(i.filt_not_converged for i in infos)
+    log(f"bench: {wl.name} {ms_per_step:.3f} ms/step  filter {filt_ms:.3f} ms  completion "
+        f"{recon_ms:.3f} ms  K mean {iters_total / wl.regs:.1f}  unconverged {unconv}")
+    recon_bytes = 12.0 * wl.elems
+    recon_gbs = recon_bytes / (recon_ms * 1e-3) / 1e9
+    # filter: algorithmic flops of both contractions per iteration (4 p r per
+    # regression); per-regression iteration counts are summed per side
+    filt_flops = 0.0
+    for s, i in zip(wl.specs, infos):
+        filt_flops += 4.0 * s.p * i.r_used * i.filt_iters_total
+    filt_tflops = filt_flops / (filt_ms * 1e-3) / 1e12
+    digest = source_digest(["paper_1108_5359_amd/csrc/recon_kernel.h",
+                            "paper_1108_5359_amd/csrc/batch.hip"])
+    if recon_ms >= filt_ms:
+        roofline = {"bound": "hbm", "kernel": "batch_reconstruct (+ batch_assemble)",
+                    "achieved": round(recon_gbs, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                    "frac": round(recon_gbs / PEAK_HBM_GBS, 4),
+                    "traffic": counter_traffic(f"batch_reconstruct_{args.config}", digest)}
+    else:
+        roofline = {"bound": "mfma", "kernel": "lane_filter_kernel (fp32 4x4x1 MFMA)",
+                    "achieved": round(filt_tflops, 3), "peak": PEAK_FP32_MFMA_TFLOPS,
+                    "unit": "TFLOP/s", "frac": round(filt_tflops / PEAK_FP32_MFMA_TFLOPS, 4),
+                    "traffic": counter_traffic(f"lane_filter_{args.config}", digest)}
+    detail = {"filter_ms": round(filt_ms, 4), "reconstruct_ms": round(recon_ms, 4),
+              "reconstruct_gbs": round(recon_gbs, 1),
+              "filter_tflops_contraction": round(filt_tflops, 3),
+              "iters_mean": round(iters_total / wl.regs, 2),
+              "iters_max": int(max(i.filt_iters_max for i in infos)), "unconverged": int(unconv),
+              "t_seed_ms": round(wl.t_seed_ms, 1), "jobs": len(wl.specs),
+              "tuning": wl.tuning.as_dict()}
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline_batch(wl, args.cpu_sample if args.cpu_sample is not None else 6)
+    out = {
+        "metric": "l1-filter solves/s (column + row l1 regressions, with completion of L and S)",
+        "value": round(value, 1),
+        "unit": "regressions/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": BATCH[args.config]["text"], "name": args.config,
+                   "problems": len(wl.specs), "regressions": wl.regs,
+                   "elements": wl.elems},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "detail": detail,
+    }
+    print(json.dumps(out), flush=True)
+    wl.batch.close()
+    wl.ctx.close()
+
+
+def cpu_baseline_batch(wl, njobs):
+    """The FP64 oracle as it stands on the host cores: Algorithm 2 (seed,
+    every column and row regression, completion) on the first ``njobs``
+    problems of the batch, from host copies of their M."""
+    import oracle
+    oracle.build()
+    threads = oracle.num_threads(0)
+    regs, t = 0, 0.0
+    for k in range(min(njobs, len(wl.specs))):
+        s = wl.specs[k]
+        Md, L, S, dI, dJ, I, J = wl.keep[k]
+        Mh = np.asfortranarray(Md.cpu().numpy().T)
+        t0 = time.perf_counter()
+        oracle.solve(Mh, s.r, I, J)
+        t += time.perf_counter() - t0
+        regs += (s.m - s.p) + (s.n - s.q)
+    log(f"bench: cpu oracle {regs} regressions ({njobs} problems) in {t:.2f} s, threads {threads}")
+    return {"value": round(regs / t, 1), "unit": "regressions/s", "cores": threads,
+            "kind": "oracle",
+            "sample": f"the first {njobs} problems of the batch, whole (seed, {regs} column + row "
+                      f"regressions, completion), FP64",
+            "seconds": round(t, 2)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--seed", type=int, default=1)
-    ap.add_argument("--config", default="c2", choices=sorted(WORKLOADS))
+    ap.add_argument("--config", default="c2", choices=sorted(WORKLOADS) + sorted(BATCH))
     ap.add_argument("--precision", type=int, default=None, help="0 = FP32, 1 = FP16 + refinement")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-compare", action="store_true", help="skip timing the other precision form")
@@ -182,6 +347,8 @@ def main():
 
     import paper_1108_5359_amd.rpca as R
 
+    if args.config in BATCH:
+        return main_batch(args, R, torch)
     wl = Workload(args.config, args.seed, R, torch)
     wl.seed()
     precision = WORKLOADS[args.config]["precision"] if args.precision is None else args.precision

@@ -267,8 +267,11 @@ typedef struct {
 /* Launch-shape choices of a batch (what the autotuner searches over). */
 typedef struct {
     int32_t lane_max_p;          /* regressions with p <= lane_max_p (<= 80) and r <= 8 use */
-    int32_t lane_max_r;          /* the lane form (one regression per lane, 4x4 MFMA);      */
-                                 /* others the 16-regression tile form (80, 8)              */
+    int32_t lane_max_r;          /* the lane form (one regression per 1, 2 or 4 lanes, 4x4  */
+                                 /* MFMA); others the 16-regression tile form (80, 8)       */
+    int32_t lane_split2_p;       /* lane form: p > this runs on 2 lanes per regression      */
+                                 /* (32; at most 32)                                        */
+    int32_t lane_split4_p;       /* ... and p > this on 4 lanes (64; split2 .. 64)          */
     int32_t filter_waves_per_cu; /* persistent grid of the lane form (8)                    */
     int32_t recon_cols_per_wave; /* columns streamed by one wave of the completion (32)     */
     int32_t order;               /* work-queue order: 0 = costliest job sides first,        */

@@ -58,9 +58,20 @@ struct WaveLds {
     int64_t eoff[kMaxP4 * 4];            // element offsets in M (floats), -1 = padding
 };
 
-// Built classes: P4 = ceil(p / 4) rounded up to one of these, RB = ceil(r / 4).
-constexpr int kP4[] = {1, 2, 3, 4, 5, 6, 8, 10, 13, 15, 18, 20};
-constexpr int kNumP4 = sizeof(kP4) / sizeof(kP4[0]);
+// Built classes (P4L element quads per lane, LPR lanes per regression); the
+// rank blocks RB = ceil(r / 4) in {1, 2} double the list.  A regression of p
+// elements runs in the smallest class of its LPR with 4 LPR P4L >= p.
+struct LaneClassDesc {
+    int p4l, lpr;
+};
+// At most 8 quads per lane: with every class in one kernel (whose register
+// budget is that of its largest branch) 10 quads spill at two waves per SIMD.
+constexpr LaneClassDesc kLaneCls[] = {
+    {1, 1}, {2, 1}, {3, 1}, {4, 1}, {5, 1}, {6, 1}, {8, 1},               // p <= 32
+    {2, 2}, {3, 2}, {4, 2}, {5, 2}, {6, 2}, {7, 2}, {8, 2},               // p <= 64
+    {1, 4}, {2, 4}, {3, 4}, {4, 4}, {5, 4},                               // p <= 80
+};
+constexpr int kNumLaneCls = sizeof(kLaneCls) / sizeof(kLaneCls[0]);
 
 __device__ __forceinline__ void wave_lds_sync()
 {
@@ -69,37 +80,66 @@ __device__ __forceinline__ void wave_lds_sync()
     asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
 }
 
+// Sum / max over the LPR lanes that share a regression (lanes reg, reg + 64/LPR, ...).
+template <int LPR>
+__device__ __forceinline__ float part_sum(float v)
+{
+    if constexpr (LPR >= 4) v += __shfl_xor(v, 16);
+    if constexpr (LPR >= 2) v += __shfl_xor(v, 32);
+    return v;
+}
+template <int LPR>
+__device__ __forceinline__ float part_max(float v)
+{
+    if constexpr (LPR >= 4) v = fmaxf(v, __shfl_xor(v, 16));
+    if constexpr (LPR >= 2) v = fmaxf(v, __shfl_xor(v, 32));
+    return v;
+}
+
 // Element x_e of a lane's regression, 0 for padding elements, bad element
 // indices and invalid lanes.  The element's offset is wave-uniform: it is
 // read from LDS and moved to scalar registers, and the lane's regression
 // offset voff is a 32-bit byte offset, so the load is the scalar-base +
 // vector-offset form and every element shares one VGPR of address.  Masked
 // lanes read an in-bounds element and select 0 (no branch per element).
+// With LPR > 1 the lanes of different parts read different elements: e is
+// then lane-dependent and the offset stays in VGPRs.
+template <bool UNIFORM>
 __device__ __forceinline__ float load_x(const float *M, const int64_t *eoff, int e, uint32_t voff,
                                         bool valid)
 {
-    const int64_t o = eoff[e];
-    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)o);
-    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)((uint64_t)o >> 32));
-    const int64_t off = (int64_t)(((uint64_t)hi << 32) | lo);
+    int64_t off = eoff[e];
+    if constexpr (UNIFORM) {
+        const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)off);
+        const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)((uint64_t)off >> 32));
+        off = (int64_t)(((uint64_t)hi << 32) | lo);
+    }
     const bool ok = off >= 0;
     const char *base = reinterpret_cast<const char *>(M + (ok ? off : 0));
     const float x = *reinterpret_cast<const float *>(base + voff);
     return (ok && valid) ? x : 0.0f;
 }
 
-// One item: regressions first .. first + 63 of side s.  The state u, y (and g
-// when KEEP) of p values sits in VGPRs; x is re-read from M by the refresh.
-template <int P4, int RB, bool KEEP>
+// One item: regressions first .. first + 64/LPR - 1 of side s.  Lane l serves
+// regression l mod (64/LPR) on its part l div (64/LPR) of the elements: 4 P4L
+// consecutive elements, whose u, y, g sit in VGPRs (x is re-read from M by the
+// refresh).  The lanes of one 4x4 MFMA block always belong to one part, so
+// the K-step element is common to the block; partial w and the residual are
+// summed / maxed over the parts with xor shuffles.
+template <int P4L, int RB, int LPR>
 __device__ __forceinline__ void lane_item(const LaneSide &s, int64_t first, int lane, WaveLds &w,
                                           bool restage, const FilterConsts &C)
 {
-    constexpr int PP = 4 * P4;          // padded p
-    constexpr int S1 = 4 * (P4 | 1);    // a1 row stride
+    constexpr int NR = 64 / LPR;        // regressions per item
+    constexpr int PL = 4 * P4L;         // elements per lane
+    constexpr int PP = LPR * PL;        // padded p
+    constexpr int S1 = 4 * ((PP / 4) | 1);   // a1 row stride
     constexpr int RR = 4 * RB;          // padded r
     constexpr int NCH = 4 / RB;         // accumulator chains per rank block of w
     const int p = s.p, r = s.r;
     const int q4 = lane & 3;
+    const int reg = lane % NR, part = lane / NR;
+    const int ebase = part * PL;
 
     if (restage) {
         wave_lds_sync();
@@ -124,7 +164,7 @@ __device__ __forceinline__ void lane_item(const LaneSide &s, int64_t first, int 
 
     // the host admits a side to the lane form only if every regression's
     // offset reg_idx * reg_stride * 4 fits in 32 bits
-    const int64_t j = first + lane;
+    const int64_t j = first + reg;
     bool valid = j < s.nreg;
     uint32_t voff = 0;
     if (valid) {
@@ -132,17 +172,17 @@ __device__ __forceinline__ void lane_item(const LaneSide &s, int64_t first, int 
         if (ri >= 0 && ri < s.reg_bound) voff = (uint32_t)(ri * s.reg_stride * 4);
         else valid = false;
     }
+    const float *M = s.M;
+    const int64_t *eoff = w.eoff + ebase;
 
     // ---- x, its norms, the starting state (u = x, y = 0, z = 0)
-    float u[P4][4], y[P4][4];
-    float gk[KEEP ? P4 : 1][4];
+    float u[P4L][4], y[P4L][4], gk[P4L][4];
     float xinf = 0.0f, xx = 0.0f;
-    const float *M = s.M;
 #pragma unroll
-    for (int t = 0; t < P4; ++t) {
+    for (int t = 0; t < P4L; ++t) {
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-            const float x = load_x(M, w.eoff, 4 * t + i, voff, valid);
+            const float x = load_x<LPR == 1>(M, eoff, 4 * t + i, voff, valid);
             u[t][i] = x;
             y[t][i] = 0.0f;
             xinf = fmaxf(xinf, fabsf(x));
@@ -150,6 +190,8 @@ __device__ __forceinline__ void lane_item(const LaneSide &s, int64_t first, int 
         }
         __builtin_amdgcn_sched_barrier(0);
     }
+    xinf = part_max<LPR>(xinf);
+    xx = part_sum<LPR>(xx);
     float beta = xx > 0.0f ? C.beta0_scale / sqrtf(xx) : 1.0f;
     const float beta_bar = C.beta_max_scale * beta;
     const float tol = C.eps * xinf;
@@ -165,16 +207,16 @@ __device__ __forceinline__ void lane_item(const LaneSide &s, int64_t first, int 
     for (int k = 0; k < C.max_iter; ++k) {
         if (!__any(!done)) break;                                   // wave-uniform
         asm volatile("" ::: "memory");   // the basis is re-read from LDS each step
-        // The lane's row offsets into the two fragment arrays, opaque to the
+        // The lane's offsets into the two fragment arrays, opaque to the
         // optimizer: every fragment address is then formed inside the step
         // (an immediate offset from these) instead of being hoisted out of
         // the loop into one live VGPR per address.
-        uint32_t q1 = (uint32_t)(q4 * S1) / 4, q2 = (uint32_t)(q4 * RR) / 4;
+        uint32_t q1 = (uint32_t)(q4 * S1 + ebase) / 4, q2 = (uint32_t)((ebase + q4) * RR) / 4;
         asm volatile("" : "+v"(q1), "+v"(q2));
         const floatx4 *F1 = A1 + q1;
         const floatx4 *F2 = A2 + q2;
 
-        // ---- g = clip(beta u + y, -1, 1) and w = A^T g (NCH chains per rank block)
+        // ---- g = clip(beta u + y, -1, 1) and the lane's part of w = A^T g
         floatx4 acc[RB][NCH];
 #pragma unroll
         for (int rb = 0; rb < RB; ++rb)
@@ -186,24 +228,21 @@ __device__ __forceinline__ void lane_item(const LaneSide &s, int64_t first, int 
 #pragma unroll
         for (int rb = 0; rb < RB; ++rb) an[rb] = F1[(4 * rb * S1) / 4];
 #pragma unroll
-        for (int t = 0; t < P4; ++t) {
+        for (int t = 0; t < P4L; ++t) {
             floatx4 a[RB];
 #pragma unroll
             for (int rb = 0; rb < RB; ++rb) {
                 a[rb] = an[rb];
-                if (t + 1 < P4) an[rb] = F1[(4 * rb * S1 + 4 * (t + 1)) / 4];
+                if (t + 1 < P4L) an[rb] = F1[(4 * rb * S1 + 4 * (t + 1)) / 4];
             }
-            float gt[4];
 #pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                gt[i] = __builtin_amdgcn_fmed3f(fmaf(beta, u[t][i], y[t][i]), -1.0f, 1.0f);
-                if constexpr (KEEP) gk[t][i] = gt[i];
-            }
+            for (int i = 0; i < 4; ++i)
+                gk[t][i] = __builtin_amdgcn_fmed3f(fmaf(beta, u[t][i], y[t][i]), -1.0f, 1.0f);
 #pragma unroll
             for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
                 for (int i = 0; i < 4; ++i)
-                    acc[rb][i % NCH] = mfma4x4(a[rb][i], gt[i], acc[rb][i % NCH]);
+                    acc[rb][i % NCH] = mfma4x4(a[rb][i], gk[t][i], acc[rb][i % NCH]);
             __builtin_amdgcn_sched_barrier(0);
         }
         floatx4 W[RB];
@@ -212,6 +251,8 @@ __device__ __forceinline__ void lane_item(const LaneSide &s, int64_t first, int 
             W[rb] = acc[rb][0];
 #pragma unroll
             for (int c = 1; c < NCH; ++c) W[rb] += acc[rb][c];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) W[rb][i] = part_sum<LPR>(W[rb][i]);
         }
 
         // A converged regression keeps z and u frozen through a zero step size.
@@ -222,10 +263,11 @@ __device__ __forceinline__ void lane_item(const LaneSide &s, int64_t first, int 
 #pragma unroll
             for (int i = 0; i < 4; ++i) z[rb][i] = fmaf(W[rb][i], ib, z[rb][i]);
 
-        // ---- v = A w in chunks of kVC quads, then the dual and residual update
+        // ---- v = A w on the lane's elements in chunks of kVC quads, then the
+        // dual and residual update
         float res = 0.0f;
 #pragma unroll
-        for (int t0 = 0; t0 < P4; t0 += kVC) {
+        for (int t0 = 0; t0 < P4L; t0 += kVC) {
             floatx4 D[kVC];
 #pragma unroll
             for (int c = 0; c < kVC; ++c) D[c] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
@@ -234,7 +276,7 @@ __device__ __forceinline__ void lane_item(const LaneSide &s, int64_t first, int 
                 floatx4 a[kVC];
 #pragma unroll
                 for (int c = 0; c < kVC; ++c)
-                    if (t0 + c < P4) a[c] = F2[(4 * (t0 + c) * RR + 4 * kb) / 4];
+                    if (t0 + c < P4L) a[c] = F2[(4 * (t0 + c) * RR + 4 * kb) / 4];
                 // ranks >= r have zero basis columns and zero w: the padded
                 // K-steps add exact zeros, and straight-line code keeps the
                 // register allocation in one block
@@ -242,18 +284,15 @@ __device__ __forceinline__ void lane_item(const LaneSide &s, int64_t first, int 
                 for (int kk = 0; kk < 4; ++kk)
 #pragma unroll
                     for (int c = 0; c < kVC; ++c)
-                        if (t0 + c < P4) D[c] = mfma4x4(a[c][kk], W[kb][kk], D[c]);
+                        if (t0 + c < P4L) D[c] = mfma4x4(a[c][kk], W[kb][kk], D[c]);
             }
 #pragma unroll
             for (int c = 0; c < kVC; ++c) {
                 const int t = t0 + c;
-                if (t < P4) {
+                if (t < P4L) {
 #pragma unroll
                     for (int i = 0; i < 4; ++i) {
-                        float gg;
-                        if constexpr (KEEP) gg = gk[t][i];
-                        else gg = __builtin_amdgcn_fmed3f(fmaf(beta, u[t][i], y[t][i]), -1.0f, 1.0f);
-                        const float yn = gg - D[c][i];
+                        const float yn = gk[t][i] - D[c][i];
                         res = fmaxf(res, fabsf(yn - y[t][i]));
                         u[t][i] = fmaf(-D[c][i], ib, u[t][i]);
                         y[t][i] = yn;
@@ -262,6 +301,7 @@ __device__ __forceinline__ void lane_item(const LaneSide &s, int64_t first, int 
             }
             __builtin_amdgcn_sched_barrier(0);
         }
+        res = part_max<LPR>(res);
         if (!done) {
             ++K;
             if (!(res * inv_beta >= tol)) done = true;   // ||x-Az-e||_inf < eps ||x||_inf
@@ -271,9 +311,8 @@ __device__ __forceinline__ void lane_item(const LaneSide &s, int64_t first, int 
         // ---- periodic u = x - A z from the input, against FP32 drift
         if (C.refresh > 0 && ((k + 1) % C.refresh) == 0) {
             asm volatile("" ::: "memory");
-
 #pragma unroll
-            for (int t0 = 0; t0 < P4; t0 += kVC) {
+            for (int t0 = 0; t0 < P4L; t0 += kVC) {
                 floatx4 D[kVC];
 #pragma unroll
                 for (int c = 0; c < kVC; ++c) D[c] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
@@ -282,21 +321,20 @@ __device__ __forceinline__ void lane_item(const LaneSide &s, int64_t first, int 
                     floatx4 a[kVC];
 #pragma unroll
                     for (int c = 0; c < kVC; ++c)
-                        if (t0 + c < P4) a[c] = F2[(4 * (t0 + c) * RR + 4 * kb) / 4];
+                        if (t0 + c < P4L) a[c] = F2[(4 * (t0 + c) * RR + 4 * kb) / 4];
 #pragma unroll
                     for (int kk = 0; kk < 4; ++kk)
 #pragma unroll
                         for (int c = 0; c < kVC; ++c)
-                            if (t0 + c < P4) D[c] = mfma4x4(a[c][kk], z[kb][kk], D[c]);
+                            if (t0 + c < P4L) D[c] = mfma4x4(a[c][kk], z[kb][kk], D[c]);
                 }
 #pragma unroll
                 for (int c = 0; c < kVC; ++c) {
                     const int t = t0 + c;
-                    if (t < P4) {
+                    if (t < P4L) {
 #pragma unroll
-                        for (int i = 0; i < 4; ++i) {
-                            u[t][i] = load_x(M, w.eoff, 4 * t + i, voff, valid) - D[c][i];
-                        }
+                        for (int i = 0; i < 4; ++i)
+                            u[t][i] = load_x<LPR == 1>(M, eoff, 4 * t + i, voff, valid) - D[c][i];
                     }
                 }
                 __builtin_amdgcn_sched_barrier(0);
@@ -304,29 +342,27 @@ __device__ __forceinline__ void lane_item(const LaneSide &s, int64_t first, int 
         }
     }
 
-    if (valid) {
+    if (part == 0) {
+        if (valid) {
 #pragma unroll
-        for (int rb = 0; rb < RB; ++rb)
+            for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const int kk = 4 * rb + i;
-                if (kk < r) s.Z[kk + j * s.ldz] = z[rb][i];
-            }
+                for (int i = 0; i < 4; ++i) {
+                    const int kk = 4 * rb + i;
+                    if (kk < r) s.Z[kk + j * s.ldz] = z[rb][i];
+                }
+        }
+        if (j < s.nreg && s.iters) s.iters[j] = !valid ? INT_MIN : (done ? K : -C.max_iter);
     }
-    if (j < s.nreg && s.iters) s.iters[j] = !valid ? INT_MIN : (done ? K : -C.max_iter);
 }
 
-// Class groups: the state of P4 <= 10 quads (with g kept) and of 13..20
-// quads (g recomputed) need different register budgets, and a kernel's budget
-// is the largest of its branches, so each group is its own persistent kernel.
-constexpr int kSmallP4Classes = 8;   // kP4[0..8) = 1..10 quads
-#define LANE_CASE(i4, rb, keep)                                             \
-    case 2 * (i4) + (rb) - 1:                                               \
-        lane_item<kP4[i4], rb, keep>(s, first, lane, w, restage, C);        \
+#define LANE_CASE(ci, rb)                                                              \
+    case 2 * (ci) + (rb) - 1:                                                          \
+        lane_item<kLaneCls[ci].p4l, rb, kLaneCls[ci].lpr>(s, first, lane, w, restage, C); \
         break;
+#define LANE_CASES(ci) LANE_CASE(ci, 1) LANE_CASE(ci, 2)
 
-template <int GROUP>
-__global__ void __launch_bounds__(kWaves * 64) __attribute__((amdgpu_waves_per_eu(GROUP == 0 ? 2 : 1)))
+__global__ void __launch_bounds__(kWaves * 64) __attribute__((amdgpu_waves_per_eu(2)))
 lane_filter_kernel(const LaneSide *__restrict__ sides, const int32_t *__restrict__ items,
                    int32_t nitems, uint32_t *counter, FilterConsts C)
 {
@@ -344,32 +380,22 @@ lane_filter_kernel(const LaneSide *__restrict__ sides, const int32_t *__restrict
         const LaneSide &s = sides[sidx];
         const bool restage = sidx != cached;
         cached = sidx;
-        if constexpr (GROUP == 0) {
-            switch (s.cls) {
-                LANE_CASE(0, 1, true) LANE_CASE(0, 2, true) LANE_CASE(1, 1, true)
-                LANE_CASE(1, 2, true) LANE_CASE(2, 1, true) LANE_CASE(2, 2, true)
-                LANE_CASE(3, 1, true) LANE_CASE(3, 2, true) LANE_CASE(4, 1, true)
-                LANE_CASE(4, 2, true) LANE_CASE(5, 1, true) LANE_CASE(5, 2, true)
-                LANE_CASE(6, 1, true) LANE_CASE(6, 2, true) LANE_CASE(7, 1, true)
-                LANE_CASE(7, 2, true)
-            default: break;                              // other group: never queued here
-            }
-        } else {
-            switch (s.cls) {
-                LANE_CASE(8, 1, false) LANE_CASE(8, 2, false) LANE_CASE(9, 1, false)
-                LANE_CASE(9, 2, false) LANE_CASE(10, 1, false) LANE_CASE(10, 2, false)
-                LANE_CASE(11, 1, false) LANE_CASE(11, 2, false)
-            default: break;
-            }
+        switch (s.cls) {
+            LANE_CASES(0) LANE_CASES(1) LANE_CASES(2) LANE_CASES(3) LANE_CASES(4) LANE_CASES(5)
+            LANE_CASES(6) LANE_CASES(7) LANE_CASES(8) LANE_CASES(9) LANE_CASES(10) LANE_CASES(11)
+            LANE_CASES(12) LANE_CASES(13) LANE_CASES(14) LANE_CASES(15) LANE_CASES(16)
+            LANE_CASES(17) LANE_CASES(18)
+        default: break;                                  // rejected on the host
         }
     }
 }
+#undef LANE_CASES
 #undef LANE_CASE
-static_assert(kNumP4 == 12 && kP4[kSmallP4Classes - 1] == 10, "class groups cover 12 quad classes");
+static_assert(kNumLaneCls == 19, "LANE_CASES list covers every class");
 
 __global__ void reset_counters(uint32_t *counter)
 {
-    if (threadIdx.x < 2) counter[threadIdx.x] = 0u;
+    if (threadIdx.x == 0) counter[0] = 0u;
 }
 
 // ---------------------------------------------------------------- completion
@@ -405,36 +431,27 @@ batch_reconstruct(const ReconJob *__restrict__ jobs, const int32_t *__restrict__
 
 using namespace batchk;
 
-int lane_class(int p, int r)
+int lane_class(int p, int r, int lpr)
 {
     if (p < 1 || r < 1 || p > kLaneMaxP || r > kLaneMaxR) return -1;
-    const int need = (p + 3) / 4;
-    for (int i = 0; i < kNumP4; ++i)
-        if (kP4[i] >= need) return 2 * i + (r + 3) / 4 - 1;
+    for (int i = 0; i < kNumLaneCls; ++i)
+        if (kLaneCls[i].lpr == lpr && 4 * kLaneCls[i].lpr * kLaneCls[i].p4l >= p)
+            return 2 * i + (r + 3) / 4 - 1;
     return -1;
 }
 
-int lane_group(int cls) { return cls >= 0 && cls / 2 >= kSmallP4Classes ? 1 : 0; }
+int lane_regs_per_item(int cls) { return 64 / kLaneCls[cls / 2].lpr; }
 
 int launch_lane_filter(rpca_ctx *ctx, const BatchTables &t, const FilterConsts &c,
                        hipStream_t stream)
 {
     hipLaunchKernelGGL(reset_counters, dim3(1), dim3(64), 0, stream, t.counter);
     RPCA_HIP_TRY(ctx, hipGetLastError());
-    // large-state group first (its items are the costliest), then the small one
-    for (int g = 1; g >= 0; --g) {
-        const int32_t n = t.group_items[g];
-        if (n == 0) continue;
-        const int32_t *items = t.items + 2 * (g == 1 ? 0 : t.group_items[1]);
-        const int blocks = (t.grid_waves[g] + kWaves - 1) / kWaves;
-        if (g == 1)
-            hipLaunchKernelGGL(lane_filter_kernel<1>, dim3((unsigned)blocks), dim3(kWaves * 64), 0,
-                               stream, t.sides, items, n, t.counter + 1, c);
-        else
-            hipLaunchKernelGGL(lane_filter_kernel<0>, dim3((unsigned)blocks), dim3(kWaves * 64), 0,
-                               stream, t.sides, items, n, t.counter, c);
-        RPCA_HIP_TRY(ctx, hipGetLastError());
-    }
+    if (t.nitems == 0) return RPCA_OK;
+    const int blocks = (t.grid_waves + kWaves - 1) / kWaves;
+    hipLaunchKernelGGL(lane_filter_kernel, dim3((unsigned)blocks), dim3(kWaves * 64), 0, stream,
+                       t.sides, t.items, t.nitems, t.counter, c);
+    RPCA_HIP_TRY(ctx, hipGetLastError());
     return RPCA_OK;
 }
 

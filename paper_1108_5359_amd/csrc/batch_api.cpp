@@ -39,13 +39,20 @@ std::vector<int64_t> complement_sorted(const std::vector<int64_t> &idx, int64_t 
 
 size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
-// Per-iteration cost of one lane-form item (64 regressions), in SIMD cycles:
-// 6 VALU ops per element (4 cycles each per wave), ceil(r/4) 4x4x1 MFMAs per
-// element for w and r per element quad for v (8 cycles each).
-double lane_item_cost(int p, int r)
+// Relative per-iteration cost of one lane-form regression, in SIMD cycles:
+// 6 VALU ops per element (4 cycles each per 64 lanes), ceil(r/4) 4x4x1 MFMAs
+// per element for w and 4 ceil(r/4) per element quad for v (8 cycles each
+// per 64 lanes).  Used to order the work queue (costliest sides first).
+double lane_reg_cost(int p, int r)
 {
     const int P4 = (p + 3) / 4, RB = (r + 3) / 4;
-    return P4 * (96.0 + 32.0 * RB + 8.0 * r);
+    return P4 * (96.0 + 64.0 * RB) / 64.0;
+}
+
+// Lanes per regression of a lane-form side with p elements.
+int lane_lpr(const rpca_batch_tuning &t, int64_t p)
+{
+    return p > t.lane_split4_p ? 4 : (p > t.lane_split2_p ? 2 : 1);
 }
 
 } // namespace
@@ -152,9 +159,10 @@ int build_tables(rpca_batch *b)
         if (S.nc > 0) {
             if (S.lane_cols) {
                 LaneSide ls{J.M, J.seed_rows, dJc, 1, J.ldm, J.m, J.n, dU, S.nc, dQt, ru, dit,
-                            (int32_t)J.p, (int32_t)J.p, ru, lane_class((int)J.p, ru)};
+                            (int32_t)J.p, (int32_t)J.p, ru,
+                            lane_class((int)J.p, ru, lane_lpr(b->tun, J.p))};
                 sides.push_back(ls);
-                side_cost.push_back(lane_item_cost((int)J.p, ru));
+                side_cost.push_back(lane_reg_cost((int)J.p, ru));
             } else {
                 b->tile_sides.push_back(FilterSide{J.M, J.seed_rows, dJc, 1, J.ldm, J.m, J.n, dU,
                                                    (int32_t)J.p, (int32_t)J.p, ru, S.nc, dQt, ru,
@@ -165,9 +173,10 @@ int build_tables(rpca_batch *b)
         if (S.mc > 0) {
             if (S.lane_rows) {
                 LaneSide ls{J.M, J.seed_cols, dIc, J.ldm, 1, J.n, J.m, dV, S.mc, dPt, ru,
-                            dit + S.nc, (int32_t)J.q, (int32_t)J.q, ru, lane_class((int)J.q, ru)};
+                            dit + S.nc, (int32_t)J.q, (int32_t)J.q, ru,
+                            lane_class((int)J.q, ru, lane_lpr(b->tun, J.q))};
                 sides.push_back(ls);
-                side_cost.push_back(lane_item_cost((int)J.q, ru));
+                side_cost.push_back(lane_reg_cost((int)J.q, ru));
             } else {
                 b->tile_sides.push_back(FilterSide{J.M, J.seed_cols, dIc, J.ldm, 1, J.n, J.m, dV,
                                                    (int32_t)J.q, (int32_t)J.q, ru, S.mc, dPt, ru,
@@ -212,24 +221,20 @@ int build_tables(rpca_batch *b)
         }
     }
 
-    // work queue: items of 64 regressions, costliest sides first (or job order)
+    // work queue: items of 64 / LPR regressions, costliest sides first (or job order)
     std::vector<int32_t> order(sides.size());
     std::iota(order.begin(), order.end(), 0);
     if (b->tun.order == 0)
         std::stable_sort(order.begin(), order.end(),
                          [&](int32_t x, int32_t y) { return side_cost[x] > side_cost[y]; });
     std::vector<int32_t> items;
-    int64_t group_items[2] = {0, 0};
-    for (int g = 1; g >= 0; --g) {      // group 1 (large state) first
-        for (int32_t sidx : order) {
-            if (lane_group(sides[sidx].cls) != g) continue;
-            const int64_t nreg = sides[sidx].nreg;
-            for (int64_t f = 0; f < nreg; f += 64) {
-                if (f > INT32_MAX) return set_status(ctx, RPCA_ERR_UNSUPPORTED, "batch: too many regressions in one side");
-                items.push_back(sidx);
-                items.push_back((int32_t)f);
-                ++group_items[g];
-            }
+    for (int32_t sidx : order) {
+        const int64_t nreg = sides[sidx].nreg;
+        const int64_t per = lane_regs_per_item(sides[sidx].cls);
+        for (int64_t f = 0; f < nreg; f += per) {
+            if (f > INT32_MAX) return set_status(ctx, RPCA_ERR_UNSUPPORTED, "batch: too many regressions in one side");
+            items.push_back(sidx);
+            items.push_back((int32_t)f);
         }
     }
     const int64_t nitems = (int64_t)items.size() / 2;
@@ -283,15 +288,10 @@ int build_tables(rpca_batch *b)
     BatchTables &t = b->bt;
     t.sides = reinterpret_cast<const LaneSide *>(base + o_sides);
     t.items = reinterpret_cast<const int32_t *>(base + o_items);
+    t.nitems = (int32_t)nitems;
     t.counter = reinterpret_cast<uint32_t *>(base + o_ctr);
     const int64_t wpc = b->tun.filter_waves_per_cu > 0 ? b->tun.filter_waves_per_cu : 8;
-    for (int g = 0; g < 2; ++g) {
-        // group 1 runs one wave per SIMD (its state needs the whole register file)
-        const int64_t per_cu = g == 0 ? wpc : std::min<int64_t>(wpc, 4);
-        t.group_items[g] = (int32_t)group_items[g];
-        t.grid_waves[g] = (int32_t)std::max<int64_t>(
-            1, std::min<int64_t>(group_items[g], per_cu * std::max(1, ctx->num_cu)));
-    }
+    t.grid_waves = (int32_t)std::max<int64_t>(1, std::min<int64_t>(nitems, wpc * std::max(1, ctx->num_cu)));
     t.jobs = reinterpret_cast<const ReconJob *>(base + o_jobs);
     t.asm_block_job = reinterpret_cast<const int32_t *>(base + o_aj);
     t.asm_block_first = reinterpret_cast<const int64_t *>(base + o_af);
@@ -311,6 +311,8 @@ void rpca_batch_tuning_default(rpca_batch_tuning *t)
     if (!t) return;
     t->lane_max_p = kLaneMaxP;
     t->lane_max_r = kLaneMaxR;
+    t->lane_split2_p = 32;
+    t->lane_split4_p = 64;
     t->filter_waves_per_cu = 8;
     t->recon_cols_per_wave = 32;
     t->order = 0;
@@ -333,7 +335,9 @@ int rpca_batch_create(rpca_ctx_t ctx, const rpca_job *jobs, int64_t njobs, const
     rpca_batch_tuning_default(&tun);
     if (tuning) tun = *tuning;
     if (tun.lane_max_p < 0 || tun.lane_max_p > kLaneMaxP || tun.lane_max_r < 0 ||
-        tun.lane_max_r > kLaneMaxR || tun.filter_waves_per_cu < 0 || tun.filter_waves_per_cu > 64 ||
+        tun.lane_max_r > kLaneMaxR || tun.lane_split2_p < 0 || tun.lane_split2_p > 32 ||
+        tun.lane_split4_p < tun.lane_split2_p || tun.lane_split4_p > 64 ||
+        tun.filter_waves_per_cu < 0 || tun.filter_waves_per_cu > 64 ||
         tun.recon_cols_per_wave < 1 || (tun.order != 0 && tun.order != 1) ||
         (tun.graph != 0 && tun.graph != 1))
         return set_status(ctx, RPCA_ERR_ARG, "batch: bad tuning");
@@ -375,9 +379,15 @@ int rpca_batch_create(rpca_ctx_t ctx, const rpca_job *jobs, int64_t njobs, const
         S.mc = (int64_t)Ic[j].size();
         S.nc = (int64_t)Jc[j].size();
         // filter form of each side; the completion's rank class
+        // lane form: small seeds, and regression offsets (column j: j ldm, row
+        // i: i) that fit 32-bit byte offsets
         const bool lane_r = J.r <= tun.lane_max_r;
-        S.lane_cols = lane_r && J.p <= tun.lane_max_p && lane_class((int)J.p, J.r) >= 0;
-        S.lane_rows = lane_r && J.q <= tun.lane_max_p && lane_class((int)J.q, J.r) >= 0;
+        const bool cols32 = (J.n - 1) * J.ldm * 4 + 4 <= (int64_t)UINT32_MAX;
+        const bool rows32 = (J.m - 1) * 4 + 4 <= (int64_t)UINT32_MAX;
+        S.lane_cols = lane_r && cols32 && J.p <= tun.lane_max_p &&
+                      lane_class((int)J.p, J.r, lane_lpr(tun, J.p)) >= 0;
+        S.lane_rows = lane_r && rows32 && J.q <= tun.lane_max_p &&
+                      lane_class((int)J.q, J.r, lane_lpr(tun, J.q)) >= 0;
         for (int rr = 1; rr <= J.r; ++rr) {   // any seed rank up to r must have a kernel
             if ((!S.lane_cols && S.nc > 0 && !filter_supported(ctx, (int)J.p, rr, o.precision)) ||
                 (!S.lane_rows && S.mc > 0 && !filter_supported(ctx, (int)J.q, rr, o.precision)))

@@ -99,7 +99,10 @@ constexpr int kColBatch = 4;    // columns whose loads are in flight together
 
 // One wave of the completion: rows [256 bx, 256 bx + 256) and the column
 // range [n by / gy, n (by + 1) / gy), so the gy waves sharing a row block
-// stream the same number of bytes.
+// stream the same number of bytes.  VEC (16-byte aligned columns): lane l
+// owns rows 4l .. 4l+3 of the block and moves float4s; otherwise lane l owns
+// rows l, l+64, l+128, l+192, so each load and store instruction of the wave
+// is one contiguous 256-byte run whatever the alignment of the column.
 template <int R4, bool VEC>
 __device__ __forceinline__ void recon_wave(const float *__restrict__ M, int64_t ldm,
                                            const float *__restrict__ F,
@@ -108,14 +111,18 @@ __device__ __forceinline__ void recon_wave(const float *__restrict__ M, int64_t 
                                            float *__restrict__ So, int64_t lds, uint32_t bx,
                                            uint32_t by, uint32_t gy, int lane)
 {
-    const int64_t i0 = (int64_t)bx * kRowsPerWave + lane * kRowsPerLane;
+    const int64_t blk = (int64_t)bx * kRowsPerWave;
     const int64_t j0 = n * (int64_t)by / gy;
     const int64_t jend = n * ((int64_t)by + 1) / gy;
+    // row of register rr of this lane
+    auto row = [&](int rr) -> int64_t {
+        return VEC ? blk + lane * kRowsPerLane + rr : blk + lane + 64 * rr;
+    };
 
     float f[kRowsPerLane][R4];
 #pragma unroll
     for (int rr = 0; rr < kRowsPerLane; ++rr) {
-        const int64_t i = i0 + rr;
+        const int64_t i = row(rr);
 #pragma unroll
         for (int k = 0; k < R4; k += 4) {
             floatx4 v = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
@@ -126,17 +133,24 @@ __device__ __forceinline__ void recon_wave(const float *__restrict__ M, int64_t 
             f[rr][k + 3] = v[3];
         }
     }
-    const bool full_rows = i0 + kRowsPerLane <= m;
+    const bool full_rows = blk + kRowsPerWave <= m;
     int64_t j = j0;
-    if (VEC && full_rows) {
+    if (full_rows) {
         // batches of kColBatch columns, loads issued first
 #pragma unroll 1
         for (; j + kColBatch <= jend; j += kColBatch) {
             floatx4 mv[kColBatch];
 #pragma unroll
-            for (int cb = 0; cb < kColBatch; ++cb)
-                mv[cb] = __builtin_nontemporal_load(
-                    reinterpret_cast<const floatx4 *>(M + (j + cb) * ldm + i0));
+            for (int cb = 0; cb < kColBatch; ++cb) {
+                if constexpr (VEC) {
+                    mv[cb] = __builtin_nontemporal_load(
+                        reinterpret_cast<const floatx4 *>(M + (j + cb) * ldm + row(0)));
+                } else {
+#pragma unroll
+                    for (int rr = 0; rr < kRowsPerLane; ++rr)
+                        mv[cb][rr] = __builtin_nontemporal_load(M + (j + cb) * ldm + row(rr));
+                }
+            }
 #pragma unroll
             for (int cb = 0; cb < kColBatch; ++cb) {
                 const float *gj = G + (j + cb) * R4;     // uniform across the wave
@@ -147,9 +161,17 @@ __device__ __forceinline__ void recon_wave(const float *__restrict__ M, int64_t 
 #pragma unroll
                     for (int rr = 0; rr < kRowsPerLane; ++rr) lv[rr] = fmaf(f[rr][k], gk, lv[rr]);
                 }
-                __builtin_nontemporal_store(lv, reinterpret_cast<floatx4 *>(Lo + (j + cb) * ldl + i0));
-                __builtin_nontemporal_store(mv[cb] - lv,
-                                            reinterpret_cast<floatx4 *>(So + (j + cb) * lds + i0));
+                const floatx4 sv = mv[cb] - lv;
+                if constexpr (VEC) {
+                    __builtin_nontemporal_store(lv, reinterpret_cast<floatx4 *>(Lo + (j + cb) * ldl + row(0)));
+                    __builtin_nontemporal_store(sv, reinterpret_cast<floatx4 *>(So + (j + cb) * lds + row(0)));
+                } else {
+#pragma unroll
+                    for (int rr = 0; rr < kRowsPerLane; ++rr) {
+                        __builtin_nontemporal_store(lv[rr], Lo + (j + cb) * ldl + row(rr));
+                        __builtin_nontemporal_store(sv[rr], So + (j + cb) * lds + row(rr));
+                    }
+                }
             }
         }
     }
@@ -164,14 +186,14 @@ __device__ __forceinline__ void recon_wave(const float *__restrict__ M, int64_t 
         }
         if (VEC && full_rows) {
             const floatx4 mv = __builtin_nontemporal_load(
-                reinterpret_cast<const floatx4 *>(M + j * ldm + i0));
+                reinterpret_cast<const floatx4 *>(M + j * ldm + row(0)));
             const floatx4 lv = floatx4{acc[0], acc[1], acc[2], acc[3]};
-            __builtin_nontemporal_store(lv, reinterpret_cast<floatx4 *>(Lo + j * ldl + i0));
-            __builtin_nontemporal_store(mv - lv, reinterpret_cast<floatx4 *>(So + j * lds + i0));
+            __builtin_nontemporal_store(lv, reinterpret_cast<floatx4 *>(Lo + j * ldl + row(0)));
+            __builtin_nontemporal_store(mv - lv, reinterpret_cast<floatx4 *>(So + j * lds + row(0)));
         } else {
 #pragma unroll
             for (int rr = 0; rr < kRowsPerLane; ++rr) {
-                const int64_t i = i0 + rr;
+                const int64_t i = row(rr);
                 if (i < m) {
                     const float mv = M[j * ldm + i];
                     Lo[j * ldl + i] = acc[rr];

@@ -144,10 +144,10 @@ struct LaneSide {
     int32_t lda, p, r, cls;
 };
 
-// Class index of (p, r) in the lane form, or -1 outside it, and the class
-// group (kernel) it runs in.
-int lane_class(int p, int r);
-int lane_group(int cls);
+// Class index of (p, r) in the lane form with lpr lanes per regression (1, 2
+// or 4), or -1 outside it; and the regressions one work item of a class covers.
+int lane_class(int p, int r, int lpr);
+int lane_regs_per_item(int cls);
 
 // Completion of one problem inside the batched launch (R4 in {4, 8}).
 struct ReconJob {
@@ -166,10 +166,10 @@ struct ReconJob {
 // The device tables of a batched run.
 struct BatchTables {
     const LaneSide *sides;
-    const int32_t *items;        // 2 per item: side index, first regression; group 1 first
-    int32_t group_items[2];      // items of class group 0 (P4 <= 10) and group 1
-    uint32_t *counter;           // two work-queue heads (reset by the launch itself)
-    int32_t grid_waves[2];       // persistent waves of each group's kernel
+    const int32_t *items;        // 2 per item: side index, first regression
+    int32_t nitems;
+    uint32_t *counter;           // work-queue head (reset by the launch itself)
+    int32_t grid_waves;          // persistent waves of the lane filter
     const ReconJob *jobs;
     const int32_t *asm_block_job;    // job of each workgroup of the factor assembly
     const int64_t *asm_block_first;  // the job's thread index of that workgroup's thread 0

@@ -151,7 +151,10 @@ def test_batch_graph_replays_are_bitwise_equal(R, ctx):
 
 
 @pytest.mark.parametrize("tuning", [dict(order=1), dict(filter_waves_per_cu=1, recon_cols_per_wave=3),
-                                    dict(lane_max_p=0), dict(lane_max_r=4, graph=0)])
+                                    dict(lane_max_p=0), dict(lane_max_r=4, graph=0),
+                                    dict(lane_split2_p=0, lane_split4_p=0),
+                                    dict(lane_split2_p=32, lane_split4_p=32),
+                                    dict(lane_split2_p=8, lane_split4_p=64)])
 def test_batch_tunings_agree(R, ctx, tuning):
     # every launch shape and form choice gives the oracle's answer
     import torch
@@ -195,7 +198,9 @@ def test_batch_argument_errors(R, ctx):
     with pytest.raises(R.RpcaError):
         R.rpca_batch_job_info(b, 5)
     b.close()
-    with pytest.raises(R.RpcaError) as e:
-        R.Batch(ctx, [R.job(Md, P.m, P.n, ldm, spec.r, dI, p, dJ, q, L, ldl, S, ldl)], o,
-                R.rpca_batch_tuning_default(lane_max_p=81))
-    assert e.value.status == R.RPCA_ERR_ARG
+    for bad in (dict(lane_max_p=81), dict(lane_split2_p=33), dict(lane_split2_p=20, lane_split4_p=10),
+                dict(lane_split4_p=65), dict(order=2)):
+        with pytest.raises(R.RpcaError) as e:
+            R.Batch(ctx, [R.job(Md, P.m, P.n, ldm, spec.r, dI, p, dJ, q, L, ldl, S, ldl)], o,
+                    R.rpca_batch_tuning_default(**bad))
+        assert e.value.status == R.RPCA_ERR_ARG, bad
