@@ -277,6 +277,8 @@ typedef struct {
     int32_t order;               /* work-queue order: 0 = costliest job sides first,        */
                                  /* 1 = job order (0)                                       */
     int32_t graph;               /* 1 = replay runs after the first from HIP graphs (1)     */
+    int32_t seed_batched;        /* 1 = seed blocks that fit in LDS are solved together, one */
+                                 /* workgroup each (Jacobi SVD); 0 = one by one (1)         */
 } rpca_batch_tuning;
 
 typedef struct rpca_batch *rpca_batch_t;
@@ -320,6 +322,14 @@ int rpca_batch_run(rpca_batch_t batch, hipStream_t stream);
  * filter / completion phase of the last run.  Synchronizes with the last run.
  */
 int rpca_batch_job_info(rpca_batch_t batch, int64_t job, rpca_info *info);
+
+/*
+ * The seed factors of `job` after rpca_batch_seed (Sec. 3.2: L^s = U Sigma
+ * V^T), copied into caller DEVICE buffers: U (p x r, ld p), sigma (r), V
+ * (q x r, ld q), FP64, columns beyond the rank used zero.  Synchronous.
+ * Errors: RPCA_ERR_ARG (bad job, NULL buffer, batch not seeded).
+ */
+int rpca_batch_job_factors(rpca_batch_t batch, int64_t job, double *U, double *sigma, double *V);
 
 /* Free the batch's workspace and graphs (never caller memory). */
 int rpca_batch_destroy(rpca_batch_t batch);

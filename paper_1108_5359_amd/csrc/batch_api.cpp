@@ -77,6 +77,7 @@ struct rpca_batch {
     rpca_batch_tuning tun{};
     DevBuf ws;                     // per-job arrays
     DevBuf tables;                 // queue, side and completion tables
+    DevBuf seed_ws;                // batched seed solver
     BatchTables bt{};
     bool seeded = false;
     int64_t runs = 0;
@@ -317,6 +318,7 @@ void rpca_batch_tuning_default(rpca_batch_tuning *t)
     t->recon_cols_per_wave = 32;
     t->order = 0;
     t->graph = 1;
+    t->seed_batched = 1;
 }
 
 int rpca_batch_create(rpca_ctx_t ctx, const rpca_job *jobs, int64_t njobs, const rpca_opts *opts,
@@ -339,7 +341,7 @@ int rpca_batch_create(rpca_ctx_t ctx, const rpca_job *jobs, int64_t njobs, const
         tun.lane_split4_p < tun.lane_split2_p || tun.lane_split4_p > 64 ||
         tun.filter_waves_per_cu < 0 || tun.filter_waves_per_cu > 64 ||
         tun.recon_cols_per_wave < 1 || (tun.order != 0 && tun.order != 1) ||
-        (tun.graph != 0 && tun.graph != 1))
+        (tun.graph != 0 && tun.graph != 1) || (tun.seed_batched != 0 && tun.seed_batched != 1))
         return set_status(ctx, RPCA_ERR_ARG, "batch: bad tuning");
     RPCA_HIP_TRY(ctx, hipSetDevice(ctx->device));
 
@@ -440,22 +442,67 @@ int rpca_batch_seed(rpca_batch_t b)
     drop_graphs(b);
     int worst = RPCA_OK;
     std::string worst_msg;
+    auto note = [&](size_t j, int st, const std::string &msg) -> int {
+        if (st < 0) return set_status(ctx, st, "batch job " + std::to_string(j) + ": " + msg);
+        if (st > 0 && worst == RPCA_OK) {
+            worst = st;
+            worst_msg = "batch job " + std::to_string(j) + ": " + msg;
+        }
+        return RPCA_OK;
+    };
+    auto dU = [&](size_t j) { return reinterpret_cast<double *>(b->at(b->js[j].o_U)); };
+    auto dsig = [&](size_t j) { return reinterpret_cast<double *>(b->at(b->js[j].o_sig)); };
+    auto dV = [&](size_t j) { return reinterpret_cast<double *>(b->at(b->js[j].o_V)); };
+
+    // small seed blocks: all in one launch of the batched solver
+    std::vector<size_t> small;
+    std::vector<SmallSeedArgs> args;
     for (size_t j = 0; j < b->jobs.size(); ++j) {
+        const rpca_job &J = b->jobs[j];
+        if (!b->tun.seed_batched || !seed_small_fits(ctx, J.p, J.q)) continue;
+        small.push_back(j);
+        args.push_back(SmallSeedArgs{J.M, J.ldm, J.seed_rows, J.seed_cols, J.p, J.q, J.r, dU(j),
+                                     dsig(j), dV(j)});
+    }
+    if (!small.empty()) {
+        const auto t0 = std::chrono::steady_clock::now();
+        int st = ensure_buf(ctx, b->seed_ws, seed_small_workspace(args.data(), (int)args.size()));
+        if (st != RPCA_OK) return st;
+        std::vector<SeedOut> outs(small.size());
+        std::vector<int> sts(small.size());
+        st = run_seed_small(ctx, args.data(), (int)args.size(), b->opts, b->seed_ws.ptr, outs.data(),
+                            sts.data(), nullptr);
+        if (st != RPCA_OK) return st;
+        const double ms =
+            std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+        for (size_t k = 0; k < small.size(); ++k) {
+            BatchJobState &S = b->js[small[k]];
+            S.so = outs[k];
+            S.seed_status = sts[k];
+            S.t_seed_ms = ms;              // one launch serves them all
+            const char *what = sts[k] == RPCA_ERR_SEED ? "the recovered seed has rank 0"
+                             : sts[k] == RPCA_ERR_NUMERIC ? "non-finite entry in the seed block"
+                             : sts[k] == RPCA_WARN_RANK ? "rank of L^s differs from the target"
+                             : "seed tolerance not met";
+            if ((st = note(small[k], sts[k], what)) != RPCA_OK) return st;
+        }
+    }
+    // the others one at a time (rocSOLVER route)
+    size_t next_small = 0;
+    for (size_t j = 0; j < b->jobs.size(); ++j) {
+        if (next_small < small.size() && small[next_small] == j) {
+            ++next_small;
+            continue;
+        }
         const rpca_job &J = b->jobs[j];
         BatchJobState &S = b->js[j];
         const auto t0 = std::chrono::steady_clock::now();
         S.so = SeedOut{};
         S.seed_status = run_seed(ctx, J.M, J.ldm, J.seed_rows, J.p, J.seed_cols, J.q, J.r, b->opts,
-                                 reinterpret_cast<double *>(b->at(S.o_U)),
-                                 reinterpret_cast<double *>(b->at(S.o_sig)),
-                                 reinterpret_cast<double *>(b->at(S.o_V)), &S.so, nullptr);
+                                 dU(j), dsig(j), dV(j), &S.so, nullptr);
         S.t_seed_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
-        if (S.seed_status < 0)
-            return set_status(ctx, S.seed_status, "batch job " + std::to_string(j) + ": " + ctx->last_error);
-        if (S.seed_status > 0 && worst == RPCA_OK) {
-            worst = S.seed_status;
-            worst_msg = "batch job " + std::to_string(j) + ": " + ctx->last_error;
-        }
+        int st = note(j, S.seed_status, ctx->last_error);
+        if (st != RPCA_OK) return st;
     }
     RPCA_HIP_TRY(ctx, hipDeviceSynchronize());
     int st = build_tables(b);
@@ -556,13 +603,30 @@ int rpca_batch_job_info(rpca_batch_t b, int64_t job, rpca_info *info)
     return S.seed_status > 0 ? S.seed_status : (bad ? RPCA_WARN_NOT_CONVERGED : RPCA_OK);
 }
 
+int rpca_batch_job_factors(rpca_batch_t b, int64_t job, double *U, double *sigma, double *V)
+{
+    if (!b) return RPCA_ERR_ARG;
+    rpca_ctx *ctx = b->ctx;
+    ctx->last_error.clear();
+    if (job < 0 || job >= (int64_t)b->jobs.size() || !U || !sigma || !V)
+        return set_status(ctx, RPCA_ERR_ARG, "batch: bad job index or NULL buffer");
+    if (!b->seeded) return set_status(ctx, RPCA_ERR_ARG, "batch: factors before a successful rpca_batch_seed");
+    RPCA_HIP_TRY(ctx, hipSetDevice(ctx->device));
+    const rpca_job &J = b->jobs[job];
+    const BatchJobState &S = b->js[job];
+    RPCA_HIP_TRY(ctx, hipMemcpy(U, b->at(S.o_U), (size_t)J.p * J.r * 8, hipMemcpyDeviceToDevice));
+    RPCA_HIP_TRY(ctx, hipMemcpy(sigma, b->at(S.o_sig), (size_t)J.r * 8, hipMemcpyDeviceToDevice));
+    RPCA_HIP_TRY(ctx, hipMemcpy(V, b->at(S.o_V), (size_t)J.q * J.r * 8, hipMemcpyDeviceToDevice));
+    return RPCA_OK;
+}
+
 int rpca_batch_destroy(rpca_batch_t b)
 {
     if (!b) return RPCA_ERR_ARG;
     (void)hipSetDevice(b->ctx->device);
     if (b->bs) (void)hipStreamSynchronize(b->bs);
     drop_graphs(b);
-    for (DevBuf *d : {&b->ws, &b->tables})
+    for (DevBuf *d : {&b->ws, &b->tables, &b->seed_ws})
         if (d->ptr) (void)hipFree(d->ptr);
     if (b->wctx) {
         for (DevBuf *d : {&b->wctx->factors, &b->wctx->xbuf_ws, &b->wctx->frag_ws, &b->wctx->scratch,

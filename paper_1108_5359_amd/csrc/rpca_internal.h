@@ -123,6 +123,23 @@ int run_seed(rpca_ctx *ctx, const float *M, int64_t ldm, const int64_t *seed_row
              const int64_t *seed_cols, int64_t q, int32_t r, const rpca_opts &o, double *U,
              double *sigma, double *V, SeedOut *out, hipStream_t stream);
 
+// Many small seed blocks in one launch (one workgroup each, Jacobi SVD in LDS).
+struct SmallSeedArgs {
+    const float *M;
+    int64_t ldm;
+    const int64_t *rows, *cols;
+    int64_t p, q;
+    int32_t r;
+    double *U, *sigma, *V;
+};
+// Whether a p x q seed block fits the batched solver's LDS budget.
+bool seed_small_fits(rpca_ctx *ctx, int64_t p, int64_t q);
+// Device workspace (bytes) run_seed_small needs for these problems.
+size_t seed_small_workspace(const SmallSeedArgs *args, int n);
+// Solve them; per problem, the status of run_seed and its SeedOut.  Synchronous.
+int run_seed_small(rpca_ctx *ctx, const SmallSeedArgs *args, int n, const rpca_opts &o, void *ws,
+                   SeedOut *outs, int *statuses, hipStream_t stream);
+
 // ---------------------------------------------------------------- batched form
 // One side (columns or rows) of one problem, filtered in the lane form: one
 // regression per lane, p <= kLaneMaxP, r <= kLaneMaxR.  Fields mean what

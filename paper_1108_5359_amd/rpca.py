@@ -232,7 +232,7 @@ class rpca_batch_tuning(ctypes.Structure):
     _fields_ = [
         ("lane_max_p", _i32), ("lane_max_r", _i32), ("lane_split2_p", _i32),
         ("lane_split4_p", _i32), ("filter_waves_per_cu", _i32),
-        ("recon_cols_per_wave", _i32), ("order", _i32), ("graph", _i32),
+        ("recon_cols_per_wave", _i32), ("order", _i32), ("graph", _i32), ("seed_batched", _i32),
     ]
 
     def as_dict(self):
@@ -247,8 +247,9 @@ lib.rpca_batch_seed.argtypes = [_vp]
 lib.rpca_batch_run.argtypes = [_vp, _vp]
 lib.rpca_batch_job_info.argtypes = [_vp, _i64, ctypes.POINTER(rpca_info)]
 lib.rpca_batch_destroy.argtypes = [_vp]
+lib.rpca_batch_job_factors.argtypes = [_vp, _i64, _vp, _vp, _vp]
 for _f in ("rpca_batch_create", "rpca_batch_seed", "rpca_batch_run", "rpca_batch_job_info",
-           "rpca_batch_destroy"):
+           "rpca_batch_destroy", "rpca_batch_job_factors"):
     getattr(lib, _f).restype = ctypes.c_int
 
 
@@ -319,3 +320,9 @@ def rpca_batch_job_info(batch: Batch, job_index: int):
 
 def rpca_batch_destroy(batch: Batch) -> None:
     batch.close()
+
+
+def rpca_batch_job_factors(batch: Batch, job_index: int, U, sigma, V) -> int:
+    """U: (r, p) FP64 tensor (column-major p x r), sigma: (r,), V: (r, q)."""
+    return batch.ctx.check(lib.rpca_batch_job_factors(batch.handle, job_index, _ptr(U), _ptr(sigma),
+                                                      _ptr(V)))

@@ -204,3 +204,43 @@ def test_batch_argument_errors(R, ctx):
             R.Batch(ctx, [R.job(Md, P.m, P.n, ldm, spec.r, dI, p, dJ, q, L, ldl, S, ldl)], o,
                     R.rpca_batch_tuning_default(**bad))
         assert e.value.status == R.RPCA_ERR_ARG, bad
+
+
+@pytest.mark.parametrize("m,n,r,p,q,seed", [(600, 500, 3, 30, 30, 1), (700, 900, 5, 50, 70, 2),
+                                           (800, 400, 8, 80, 64, 3), (500, 700, 2, 40, 20, 4)])
+def test_batched_seed_solver_matches_oracle(R, ctx, m, n, r, p, q, seed):
+    # Well-conditioned seed blocks (Bernoulli +-1 corruptions, default
+    # tolerances): the batched seed solver (one workgroup per problem, Jacobi
+    # SVD) reaches the oracle's rank, iteration count and L^s; the one-by-one
+    # route on the same batch agrees too.
+    import torch
+    pr = synth.lowrank_plus_sparse(m, n, r, factor_std=np.sqrt(1.0 / max(m, n)), sparsity=0.1,
+                                   values="pm1", seed=seed)
+    I, J = synth.seed_indices(m, n, p, q, seed=seed)
+    sd = oracle.seed_pcp(pr.M[np.ix_(I, J)].astype(np.float64))
+    kk = min(sd.rank, r)
+    Ls_ref = (sd.U[:, :kk] * sd.sigma[:kk]) @ sd.V[:, :kk].T
+    Md = _upload(pr, m)
+    L = torch.empty_like(Md)
+    S = torch.empty_like(Md)
+    dI, dJ = dev_i64(I), dev_i64(J)
+    for batched in (1, 0):
+        say(f"seed solver m={m} n={n} r={r} p={p} q={q} batched={batched}")
+        b = R.Batch(ctx, [R.job(Md, m, n, m, r, dI, p, dJ, q, L, m, S, m)], R.rpca_opts_default(),
+                    R.rpca_batch_tuning_default(seed_batched=batched))
+        st = R.rpca_batch_seed(b)
+        st, info = R.rpca_batch_job_info(b, 0)
+        assert info.r_used == kk and info.seed_iters == sd.iters, (info.r_used, info.seed_iters, sd.iters)
+        U = torch.zeros((r, p), dtype=torch.float64, device="cuda")
+        sg = torch.zeros(r, dtype=torch.float64, device="cuda")
+        V = torch.zeros((r, q), dtype=torch.float64, device="cuda")
+        R.rpca_batch_job_factors(b, 0, U, sg, V)
+        Uh, sh, Vh = U.cpu().numpy().T, sg.cpu().numpy(), V.cpu().numpy().T
+        Ls = (Uh * sh) @ Vh.T
+        # the one-by-one route takes singular vectors from the eigenvectors of
+        # the Gram matrix, which squares the spectrum (measured: up to 2e-8)
+        assert relF(Ls, Ls_ref) <= (1e-9 if batched else 1e-7), relF(Ls, Ls_ref)
+        assert np.allclose(Uh.T @ Uh, np.diag((sh > 0).astype(float)), atol=1e-12)
+        assert np.allclose(Vh.T @ Vh, np.diag((sh > 0).astype(float)), atol=1e-12)
+        assert np.all(np.diff(sh[:kk]) <= 0)
+        b.close()
