@@ -291,8 +291,10 @@ void rpca_batch_tuning_default(rpca_batch_tuning *t);
  * device workspace (complement indices, seed factors, filter outputs,
  * completion factors, work queue).  opts as for rpca_solve (os_r, os_c and
  * rng_seed unused: every job brings its seed indices); tuning may be NULL
- * (defaults).  Synchronous.  Errors: RPCA_ERR_ARG (bad job: the message names
- * it), RPCA_ERR_NOMEM, RPCA_ERR_UNSUPPORTED (a job outside every kernel class).
+ * (defaults).  The seed index arrays are read after the work enqueued on the
+ * default (NULL) stream.  Synchronous.  Errors: RPCA_ERR_ARG (bad job: the
+ * message names it), RPCA_ERR_NOMEM, RPCA_ERR_UNSUPPORTED (a job outside
+ * every kernel class).
  */
 int rpca_batch_create(rpca_ctx_t ctx, const rpca_job *jobs, int64_t njobs, const rpca_opts *opts,
                       const rpca_batch_tuning *tuning, rpca_batch_t *batch);
@@ -300,10 +302,13 @@ int rpca_batch_create(rpca_ctx_t ctx, const rpca_job *jobs, int64_t njobs, const
 /*
  * Step 2 (Sec. 3.1, eq. SPCP) for every job, as rpca_seed does for one, into
  * the batch's workspace; then builds the work queue of steps 3-4 from the
- * ranks found.  Synchronous.  Returns the most severe job status (the message
- * names the first job with it); RPCA_ERR_SEED if a seed has rank 0.
+ * ranks found.  Seed blocks that fit in LDS are solved together by one launch
+ * (one workgroup each, Jacobi SVD), the others one at a time (rocSOLVER).
+ * The M buffers are read after the work enqueued on `stream`.  Synchronous.
+ * Returns the most severe job status (the message names the first job with
+ * it); RPCA_ERR_SEED if a seed has rank 0.
  */
-int rpca_batch_seed(rpca_batch_t batch);
+int rpca_batch_seed(rpca_batch_t batch, hipStream_t stream);
 
 /*
  * Steps 3-5 (Sec. 3.2-3.3, Algorithm 1 per regression; eqs. l1s, l1s') for
@@ -333,6 +338,77 @@ int rpca_batch_job_factors(rpca_batch_t batch, int64_t job, double *U, double *s
 
 /* Free the batch's workspace and graphs (never caller memory). */
 int rpca_batch_destroy(rpca_batch_t batch);
+
+/* ------------------------------------------------------------------------
+ * Served form: a request loop over the batched form.  Requests (one rpca_job
+ * each) queue in arrival order; `workers` host threads each take requests
+ * from the head of the queue while the device memory of all admitted,
+ * unfinished requests stays within hbm_budget_bytes (a request larger than
+ * the budget is admitted alone), up to max_batch at a time, and run steps 2-5
+ * for them as one batch on their own stream, so batches of different workers
+ * overlap on the device and requests that arrive meanwhile join the next
+ * batch.  A batch that fails as a whole is retried request by request.
+ * ------------------------------------------------------------------------ */
+typedef struct {
+    double hbm_budget_bytes;     /* admission budget: M, L, S and workspace of the admitted */
+                                 /* unfinished requests (200e9)                             */
+    int32_t workers;             /* concurrent batches, 1..16 (3)                           */
+    int32_t max_batch;           /* requests per batch (64)                                 */
+} rpca_server_opts;
+
+/* What a finished request reports (times: host clock, ms since creation). */
+typedef struct {
+    int32_t status;              /* the request's status (as rpca_solve's)                  */
+    int32_t batch_size;          /* requests in the batch it ran in                         */
+    rpca_info info;              /* rank, iterations; phase times of its batch              */
+    double t_submit_ms, t_admit_ms, t_done_ms;
+} rpca_request_info;
+
+typedef struct {
+    int64_t submitted, completed, failed, batches, queued;
+    double peak_inflight_bytes;  /* largest admitted footprint seen                         */
+    double inflight_bytes;       /* admitted footprint now                                  */
+} rpca_server_stats;
+
+typedef struct rpca_server *rpca_server_t;
+
+/* Fill *o with the defaults listed above. */
+void rpca_server_opts_default(rpca_server_opts *o);
+
+/*
+ * Start a request loop on HIP device `device` with the method's options
+ * (opts, as for rpca_solve), the launch shapes of its batches (tuning, may be
+ * NULL; graph replay is off: every batch runs once) and the server options
+ * (sopts, may be NULL).  Errors: RPCA_ERR_ARG, RPCA_ERR_DEVICE; the message
+ * is rpca_server_error(NULL).
+ */
+int rpca_server_create(int device, const rpca_opts *opts, const rpca_batch_tuning *tuning,
+                       const rpca_server_opts *sopts, rpca_server_t *server);
+
+/*
+ * Queue one request (host *job, copied; its device buffers belong to the
+ * caller and must stay valid and untouched until the request is done; M is
+ * read after the work enqueued on the default stream when its batch starts).
+ * *ticket receives its handle.  Errors: RPCA_ERR_ARG (NULL, sizes, rank).
+ */
+int rpca_server_submit(rpca_server_t server, const rpca_job *job, int64_t *ticket);
+
+/* Block until the request is done, fill *info (may be NULL) and forget the
+ * ticket.  Returns the request's status when negative, else RPCA_OK. */
+int rpca_server_wait(rpca_server_t server, int64_t ticket, rpca_request_info *info);
+
+/* *done = 1 if the request is done (the ticket stays valid until waited). */
+int rpca_server_poll(rpca_server_t server, int64_t ticket, int32_t *done);
+
+/* Counters of the loop. */
+int rpca_server_get_stats(rpca_server_t server, rpca_server_stats *stats);
+
+/* Text of the last error of the server (NULL: of the last failed create). */
+const char *rpca_server_error(rpca_server_t server);
+
+/* Finish every queued request, stop the workers, free everything the server
+ * owns. */
+int rpca_server_destroy(rpca_server_t server);
 
 #ifdef __cplusplus
 }

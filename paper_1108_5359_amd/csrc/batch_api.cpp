@@ -13,10 +13,12 @@ namespace {
 
 // Index checks and complements on host copies (as rpca_solve does).
 int fetch_sorted(rpca_ctx *ctx, const int64_t *dev, int64_t count, int64_t bound,
-                 const std::string &name, std::vector<int64_t> &out)
+                 const std::string &name, std::vector<int64_t> &out, hipStream_t stream)
 {
     out.resize((size_t)count);
-    RPCA_HIP_TRY(ctx, hipMemcpy(out.data(), dev, (size_t)count * sizeof(int64_t), hipMemcpyDeviceToHost));
+    RPCA_HIP_TRY(ctx, hipMemcpyAsync(out.data(), dev, (size_t)count * sizeof(int64_t),
+                                     hipMemcpyDeviceToHost, stream));
+    RPCA_HIP_TRY(ctx, hipStreamSynchronize(stream));
     for (int64_t i = 0; i < count; ++i) {
         if (out[i] < 0 || out[i] >= bound) return set_status(ctx, RPCA_ERR_ARG, name + ": index out of range");
         if (i > 0 && out[i] <= out[i - 1])
@@ -276,7 +278,7 @@ int build_tables(rpca_batch *b)
     if (st != RPCA_OK) return st;
     char *base = static_cast<char *>(b->tables.ptr);
     auto put = [&](size_t o, const void *src, size_t bytes) -> hipError_t {
-        return bytes ? hipMemcpy(base + o, src, bytes, hipMemcpyHostToDevice) : hipSuccess;
+        return bytes ? hipMemcpyAsync(base + o, src, bytes, hipMemcpyHostToDevice, b->bs) : hipSuccess;
     };
     RPCA_HIP_TRY(ctx, put(o_sides, sides.data(), sides.size() * sizeof(LaneSide)));
     RPCA_HIP_TRY(ctx, put(o_items, items.data(), items.size() * sizeof(int32_t)));
@@ -285,6 +287,7 @@ int build_tables(rpca_batch *b)
     RPCA_HIP_TRY(ctx, put(o_af, asm_first.data(), asm_first.size() * sizeof(int64_t)));
     RPCA_HIP_TRY(ctx, put(o_rj, rec_job.data(), rec_job.size() * sizeof(int32_t)));
     RPCA_HIP_TRY(ctx, put(o_rl, rec_local.data(), rec_local.size() * sizeof(uint32_t)));
+    RPCA_HIP_TRY(ctx, hipStreamSynchronize(b->bs));     // the host vectors die here
 
     BatchTables &t = b->bt;
     t.sides = reinterpret_cast<const LaneSide *>(base + o_sides);
@@ -304,6 +307,136 @@ int build_tables(rpca_batch *b)
 }
 
 } // namespace
+
+int batch_check_tuning(rpca_ctx *ctx, const rpca_batch_tuning &tun)
+{
+    if (tun.lane_max_p < 0 || tun.lane_max_p > kLaneMaxP || tun.lane_max_r < 0 ||
+        tun.lane_max_r > kLaneMaxR || tun.lane_split2_p < 0 || tun.lane_split2_p > 32 ||
+        tun.lane_split4_p < tun.lane_split2_p || tun.lane_split4_p > 64 ||
+        tun.filter_waves_per_cu < 0 || tun.filter_waves_per_cu > 64 ||
+        tun.recon_cols_per_wave < 1 || (tun.order != 0 && tun.order != 1) ||
+        (tun.graph != 0 && tun.graph != 1) || (tun.seed_batched != 0 && tun.seed_batched != 1))
+        return set_status(ctx, RPCA_ERR_ARG, "batch: bad tuning");
+    return RPCA_OK;
+}
+
+rpca_batch *batch_new(rpca_ctx *ctx, const rpca_opts &o, const rpca_batch_tuning &tun, int *status)
+{
+    *status = check_opts(ctx, o);
+    if (*status != RPCA_OK) return nullptr;
+    if ((*status = batch_check_tuning(ctx, tun)) != RPCA_OK) return nullptr;
+    if (hipSetDevice(ctx->device) != hipSuccess) {
+        *status = set_status(ctx, RPCA_ERR_DEVICE, "batch: hipSetDevice failed");
+        return nullptr;
+    }
+    rpca_batch *b = new rpca_batch();
+    b->ctx = ctx;
+    b->opts = o;
+    b->tun = tun;
+    // the batch's own launch workspace, stream and events
+    b->wctx = new rpca_ctx();
+    b->wctx->device = ctx->device;
+    b->wctx->num_cu = ctx->num_cu;
+    b->wctx->max_lds = ctx->max_lds;
+    b->wctx->recon_waves_per_cu = ctx->recon_waves_per_cu;
+    bool ok = hipStreamCreateWithFlags(&b->bs, hipStreamNonBlocking) == hipSuccess;
+    for (auto &e : b->ev) ok = ok && hipEventCreate(&e) == hipSuccess;
+    if (!ok) {
+        *status = set_status(ctx, RPCA_ERR_DEVICE, "batch: stream or event creation failed");
+        rpca_batch_destroy(b);
+        return nullptr;
+    }
+    *status = RPCA_OK;
+    return b;
+}
+
+hipStream_t batch_stream(rpca_batch *b) { return b->bs; }
+
+// Order the batch stream after the work already enqueued on `stream`.
+int order_after(rpca_batch *b, hipStream_t stream)
+{
+    RPCA_HIP_TRY(b->ctx, hipEventRecord(b->ev[4], stream));
+    RPCA_HIP_TRY(b->ctx, hipStreamWaitEvent(b->bs, b->ev[4], 0));
+    return RPCA_OK;
+}
+
+int batch_plan(rpca_batch *b, const rpca_job *jobs, int64_t njobs, hipStream_t stream)
+{
+    rpca_ctx *ctx = b->ctx;
+    const rpca_batch_tuning &tun = b->tun;
+    const rpca_opts &o = b->opts;
+    if (!jobs || njobs < 1) return set_status(ctx, RPCA_ERR_ARG, "batch: need at least one job");
+    RPCA_HIP_TRY(ctx, hipStreamSynchronize(b->bs));
+    int ost = order_after(b, stream);      // the index arrays may still be in flight there
+    if (ost != RPCA_OK) return ost;
+    drop_graphs(b);
+    b->seeded = false;
+    b->runs = 0;
+    b->jobs.assign(jobs, jobs + njobs);
+    b->js.assign((size_t)njobs, BatchJobState{});
+
+    // checks and workspace layout
+    std::vector<std::vector<int64_t>> Ic((size_t)njobs), Jc((size_t)njobs);
+    size_t off = 0;
+    for (int64_t j = 0; j < njobs; ++j) {
+        const rpca_job &J = b->jobs[j];
+        BatchJobState &S = b->js[j];
+        const std::string nm = "batch job " + std::to_string(j);
+        if (!J.M || !J.L || !J.S || !J.seed_rows || !J.seed_cols)
+            return set_status(ctx, RPCA_ERR_ARG, nm + ": NULL pointer");
+        if (J.m < 1 || J.n < 1 || J.ldm < J.m || J.ldl < J.m || J.lds < J.m)
+            return set_status(ctx, RPCA_ERR_ARG, nm + ": bad sizes or leading dimensions");
+        if (J.r < 1 || J.p < 1 || J.q < 1 || J.p > J.m || J.q > J.n || J.r > std::min(J.p, J.q))
+            return set_status(ctx, RPCA_ERR_ARG, nm + ": need 1 <= r <= min(p, q), p <= m, q <= n");
+        if ((const void *)J.L == (const void *)J.S || (const void *)J.L == (const void *)J.M ||
+            (const void *)J.S == (const void *)J.M)
+            return set_status(ctx, RPCA_ERR_ARG, nm + ": L, S and M must be distinct buffers");
+        std::vector<int64_t> I, Jv;
+        int st = fetch_sorted(ctx, J.seed_rows, J.p, J.m, nm + " seed_rows", I, b->bs);
+        if (st != RPCA_OK) return st;
+        if ((st = fetch_sorted(ctx, J.seed_cols, J.q, J.n, nm + " seed_cols", Jv, b->bs)) != RPCA_OK) return st;
+        Ic[j] = complement_sorted(I, J.m);
+        Jc[j] = complement_sorted(Jv, J.n);
+        S.mc = (int64_t)Ic[j].size();
+        S.nc = (int64_t)Jc[j].size();
+        // filter form of each side; the completion's rank class
+        // lane form: small seeds, and regression offsets (column j: j ldm, row
+        // i: i) that fit 32-bit byte offsets
+        const bool lane_r = J.r <= tun.lane_max_r;
+        const bool cols32 = (J.n - 1) * J.ldm * 4 + 4 <= (int64_t)UINT32_MAX;
+        const bool rows32 = (J.m - 1) * 4 + 4 <= (int64_t)UINT32_MAX;
+        S.lane_cols = lane_r && cols32 && J.p <= tun.lane_max_p &&
+                      lane_class((int)J.p, J.r, lane_lpr(tun, J.p)) >= 0;
+        S.lane_rows = lane_r && rows32 && J.q <= tun.lane_max_p &&
+                      lane_class((int)J.q, J.r, lane_lpr(tun, J.q)) >= 0;
+        for (int rr = 1; rr <= J.r; ++rr) {   // any seed rank up to r must have a kernel
+            if ((!S.lane_cols && S.nc > 0 && !filter_supported(ctx, (int)J.p, rr, o.precision)) ||
+                (!S.lane_rows && S.mc > 0 && !filter_supported(ctx, (int)J.q, rr, o.precision)))
+                return set_status(ctx, RPCA_ERR_UNSUPPORTED, nm + ": seed size outside the built kernel classes");
+        }
+        S.R4 = (J.r + 3) / 4 * 4;
+        if (S.R4 > 64) return set_status(ctx, RPCA_ERR_UNSUPPORTED, nm + ": rank above 64");
+        S.o_Ic = off; off = align_up(off + (size_t)S.mc * 8, 256);
+        S.o_Jc = off; off = align_up(off + (size_t)S.nc * 8, 256);
+        S.o_U = off;  off = align_up(off + (size_t)J.p * J.r * 8, 256);
+        S.o_sig = off; off = align_up(off + (size_t)J.r * 8, 256);
+        S.o_V = off;  off = align_up(off + (size_t)J.q * J.r * 8, 256);
+        S.o_Qt = off; off = align_up(off + (size_t)S.nc * J.r * 4, 256);
+        S.o_Pt = off; off = align_up(off + (size_t)S.mc * J.r * 4, 256);
+        S.o_it = off; off = align_up(off + (size_t)(S.nc + S.mc) * 4, 256);
+        S.o_F = off;
+        if (S.R4 <= 8) off = align_up(off + (size_t)(J.m + J.n) * S.R4 * 4, 256);
+    }
+    int st = ensure_buf(ctx, b->ws, std::max<size_t>(off, 256));
+    if (st != RPCA_OK) return st;
+    for (int64_t j = 0; j < njobs; ++j) {
+        const BatchJobState &S = b->js[j];
+        if (S.mc) RPCA_HIP_TRY(ctx, hipMemcpyAsync(b->at(S.o_Ic), Ic[j].data(), S.mc * 8, hipMemcpyHostToDevice, b->bs));
+        if (S.nc) RPCA_HIP_TRY(ctx, hipMemcpyAsync(b->at(S.o_Jc), Jc[j].data(), S.nc * 8, hipMemcpyHostToDevice, b->bs));
+    }
+    RPCA_HIP_TRY(ctx, hipStreamSynchronize(b->bs));
+    return RPCA_OK;
+}
 
 extern "C" {
 
@@ -330,114 +463,29 @@ int rpca_batch_create(rpca_ctx_t ctx, const rpca_job *jobs, int64_t njobs, const
     *out = nullptr;
     if (!jobs || njobs < 1) return set_status(ctx, RPCA_ERR_ARG, "batch: need at least one job");
     if (!opts) return set_status(ctx, RPCA_ERR_ARG, "batch: NULL opts");
-    const rpca_opts o = *opts;
-    int cst = check_opts(ctx, o);
-    if (cst != RPCA_OK) return cst;
     rpca_batch_tuning tun;
     rpca_batch_tuning_default(&tun);
     if (tuning) tun = *tuning;
-    if (tun.lane_max_p < 0 || tun.lane_max_p > kLaneMaxP || tun.lane_max_r < 0 ||
-        tun.lane_max_r > kLaneMaxR || tun.lane_split2_p < 0 || tun.lane_split2_p > 32 ||
-        tun.lane_split4_p < tun.lane_split2_p || tun.lane_split4_p > 64 ||
-        tun.filter_waves_per_cu < 0 || tun.filter_waves_per_cu > 64 ||
-        tun.recon_cols_per_wave < 1 || (tun.order != 0 && tun.order != 1) ||
-        (tun.graph != 0 && tun.graph != 1) || (tun.seed_batched != 0 && tun.seed_batched != 1))
-        return set_status(ctx, RPCA_ERR_ARG, "batch: bad tuning");
-    RPCA_HIP_TRY(ctx, hipSetDevice(ctx->device));
-
-    rpca_batch *b = new rpca_batch();
-    b->ctx = ctx;
-    b->opts = o;
-    b->tun = tun;
-    b->jobs.assign(jobs, jobs + njobs);
-    b->js.resize((size_t)njobs);
-    auto bail = [&](int st) {
+    int st = RPCA_OK;
+    rpca_batch *b = batch_new(ctx, *opts, tun, &st);
+    if (!b) return st;
+    if ((st = batch_plan(b, jobs, njobs, nullptr)) != RPCA_OK) {
         rpca_batch_destroy(b);
         return st;
-    };
-
-    // checks and workspace layout
-    std::vector<std::vector<int64_t>> Ic((size_t)njobs), Jc((size_t)njobs);
-    size_t off = 0;
-    for (int64_t j = 0; j < njobs; ++j) {
-        const rpca_job &J = b->jobs[j];
-        BatchJobState &S = b->js[j];
-        const std::string nm = "batch job " + std::to_string(j);
-        if (!J.M || !J.L || !J.S || !J.seed_rows || !J.seed_cols)
-            return bail(set_status(ctx, RPCA_ERR_ARG, nm + ": NULL pointer"));
-        if (J.m < 1 || J.n < 1 || J.ldm < J.m || J.ldl < J.m || J.lds < J.m)
-            return bail(set_status(ctx, RPCA_ERR_ARG, nm + ": bad sizes or leading dimensions"));
-        if (J.r < 1 || J.p < 1 || J.q < 1 || J.p > J.m || J.q > J.n || J.r > std::min(J.p, J.q))
-            return bail(set_status(ctx, RPCA_ERR_ARG, nm + ": need 1 <= r <= min(p, q), p <= m, q <= n"));
-        if ((const void *)J.L == (const void *)J.S || (const void *)J.L == (const void *)J.M ||
-            (const void *)J.S == (const void *)J.M)
-            return bail(set_status(ctx, RPCA_ERR_ARG, nm + ": L, S and M must be distinct buffers"));
-        std::vector<int64_t> I, Jv;
-        int st = fetch_sorted(ctx, J.seed_rows, J.p, J.m, nm + " seed_rows", I);
-        if (st != RPCA_OK) return bail(st);
-        if ((st = fetch_sorted(ctx, J.seed_cols, J.q, J.n, nm + " seed_cols", Jv)) != RPCA_OK) return bail(st);
-        Ic[j] = complement_sorted(I, J.m);
-        Jc[j] = complement_sorted(Jv, J.n);
-        S.mc = (int64_t)Ic[j].size();
-        S.nc = (int64_t)Jc[j].size();
-        // filter form of each side; the completion's rank class
-        // lane form: small seeds, and regression offsets (column j: j ldm, row
-        // i: i) that fit 32-bit byte offsets
-        const bool lane_r = J.r <= tun.lane_max_r;
-        const bool cols32 = (J.n - 1) * J.ldm * 4 + 4 <= (int64_t)UINT32_MAX;
-        const bool rows32 = (J.m - 1) * 4 + 4 <= (int64_t)UINT32_MAX;
-        S.lane_cols = lane_r && cols32 && J.p <= tun.lane_max_p &&
-                      lane_class((int)J.p, J.r, lane_lpr(tun, J.p)) >= 0;
-        S.lane_rows = lane_r && rows32 && J.q <= tun.lane_max_p &&
-                      lane_class((int)J.q, J.r, lane_lpr(tun, J.q)) >= 0;
-        for (int rr = 1; rr <= J.r; ++rr) {   // any seed rank up to r must have a kernel
-            if ((!S.lane_cols && S.nc > 0 && !filter_supported(ctx, (int)J.p, rr, o.precision)) ||
-                (!S.lane_rows && S.mc > 0 && !filter_supported(ctx, (int)J.q, rr, o.precision)))
-                return bail(set_status(ctx, RPCA_ERR_UNSUPPORTED, nm + ": seed size outside the built kernel classes"));
-        }
-        S.R4 = (J.r + 3) / 4 * 4;
-        if (S.R4 > 64) return bail(set_status(ctx, RPCA_ERR_UNSUPPORTED, nm + ": rank above 64"));
-        S.o_Ic = off; off = align_up(off + (size_t)S.mc * 8, 256);
-        S.o_Jc = off; off = align_up(off + (size_t)S.nc * 8, 256);
-        S.o_U = off;  off = align_up(off + (size_t)J.p * J.r * 8, 256);
-        S.o_sig = off; off = align_up(off + (size_t)J.r * 8, 256);
-        S.o_V = off;  off = align_up(off + (size_t)J.q * J.r * 8, 256);
-        S.o_Qt = off; off = align_up(off + (size_t)S.nc * J.r * 4, 256);
-        S.o_Pt = off; off = align_up(off + (size_t)S.mc * J.r * 4, 256);
-        S.o_it = off; off = align_up(off + (size_t)(S.nc + S.mc) * 4, 256);
-        S.o_F = off;
-        if (S.R4 <= 8) off = align_up(off + (size_t)(J.m + J.n) * S.R4 * 4, 256);
     }
-    int st = ensure_buf(ctx, b->ws, std::max<size_t>(off, 256));
-    if (st != RPCA_OK) return bail(st);
-    for (int64_t j = 0; j < njobs; ++j) {
-        const BatchJobState &S = b->js[j];
-        if (S.mc) RPCA_HIP_TRY(ctx, hipMemcpy(b->at(S.o_Ic), Ic[j].data(), S.mc * 8, hipMemcpyHostToDevice));
-        if (S.nc) RPCA_HIP_TRY(ctx, hipMemcpy(b->at(S.o_Jc), Jc[j].data(), S.nc * 8, hipMemcpyHostToDevice));
-    }
-
-    // the batch's own launch workspace, stream and events
-    b->wctx = new rpca_ctx();
-    b->wctx->device = ctx->device;
-    b->wctx->num_cu = ctx->num_cu;
-    b->wctx->max_lds = ctx->max_lds;
-    b->wctx->recon_waves_per_cu = ctx->recon_waves_per_cu;
-    if (hipStreamCreateWithFlags(&b->bs, hipStreamNonBlocking) != hipSuccess)
-        return bail(set_status(ctx, RPCA_ERR_DEVICE, "batch: hipStreamCreate failed"));
-    for (auto &e : b->ev)
-        if (hipEventCreate(&e) != hipSuccess)
-            return bail(set_status(ctx, RPCA_ERR_DEVICE, "batch: hipEventCreate failed"));
     *out = b;
     return RPCA_OK;
 }
 
-int rpca_batch_seed(rpca_batch_t b)
+int rpca_batch_seed(rpca_batch_t b, hipStream_t stream)
 {
     if (!b) return RPCA_ERR_ARG;
     rpca_ctx *ctx = b->ctx;
     ctx->last_error.clear();
     RPCA_HIP_TRY(ctx, hipSetDevice(ctx->device));
     RPCA_HIP_TRY(ctx, hipStreamSynchronize(b->bs));
+    int ost = order_after(b, stream);      // M may still be in flight there
+    if (ost != RPCA_OK) return ost;
     b->seeded = false;
     drop_graphs(b);
     int worst = RPCA_OK;
@@ -471,7 +519,7 @@ int rpca_batch_seed(rpca_batch_t b)
         std::vector<SeedOut> outs(small.size());
         std::vector<int> sts(small.size());
         st = run_seed_small(ctx, args.data(), (int)args.size(), b->opts, b->seed_ws.ptr, outs.data(),
-                            sts.data(), nullptr);
+                            sts.data(), b->bs);
         if (st != RPCA_OK) return st;
         const double ms =
             std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
@@ -499,12 +547,12 @@ int rpca_batch_seed(rpca_batch_t b)
         const auto t0 = std::chrono::steady_clock::now();
         S.so = SeedOut{};
         S.seed_status = run_seed(ctx, J.M, J.ldm, J.seed_rows, J.p, J.seed_cols, J.q, J.r, b->opts,
-                                 dU(j), dsig(j), dV(j), &S.so, nullptr);
+                                 dU(j), dsig(j), dV(j), &S.so, b->bs);
         S.t_seed_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
         int st = note(j, S.seed_status, ctx->last_error);
         if (st != RPCA_OK) return st;
     }
-    RPCA_HIP_TRY(ctx, hipDeviceSynchronize());
+    RPCA_HIP_TRY(ctx, hipStreamSynchronize(b->bs));
     int st = build_tables(b);
     if (st != RPCA_OK) return st;
     b->seeded = true;
@@ -578,7 +626,8 @@ int rpca_batch_job_info(rpca_batch_t b, int64_t job, rpca_info *info)
     int64_t total = 0, bad = 0;
     int32_t kmax = 0;
     if (b->runs > 0 && !its.empty()) {
-        RPCA_HIP_TRY(ctx, hipMemcpy(its.data(), b->at(S.o_it), its.size() * 4, hipMemcpyDeviceToHost));
+        RPCA_HIP_TRY(ctx, hipMemcpyAsync(its.data(), b->at(S.o_it), its.size() * 4, hipMemcpyDeviceToHost, b->bs));
+        RPCA_HIP_TRY(ctx, hipStreamSynchronize(b->bs));
         for (int32_t k : its) {
             if (k < 0) ++bad;
             const int32_t ak = k < 0 ? -k : k;
@@ -614,9 +663,10 @@ int rpca_batch_job_factors(rpca_batch_t b, int64_t job, double *U, double *sigma
     RPCA_HIP_TRY(ctx, hipSetDevice(ctx->device));
     const rpca_job &J = b->jobs[job];
     const BatchJobState &S = b->js[job];
-    RPCA_HIP_TRY(ctx, hipMemcpy(U, b->at(S.o_U), (size_t)J.p * J.r * 8, hipMemcpyDeviceToDevice));
-    RPCA_HIP_TRY(ctx, hipMemcpy(sigma, b->at(S.o_sig), (size_t)J.r * 8, hipMemcpyDeviceToDevice));
-    RPCA_HIP_TRY(ctx, hipMemcpy(V, b->at(S.o_V), (size_t)J.q * J.r * 8, hipMemcpyDeviceToDevice));
+    RPCA_HIP_TRY(ctx, hipMemcpyAsync(U, b->at(S.o_U), (size_t)J.p * J.r * 8, hipMemcpyDeviceToDevice, b->bs));
+    RPCA_HIP_TRY(ctx, hipMemcpyAsync(sigma, b->at(S.o_sig), (size_t)J.r * 8, hipMemcpyDeviceToDevice, b->bs));
+    RPCA_HIP_TRY(ctx, hipMemcpyAsync(V, b->at(S.o_V), (size_t)J.q * J.r * 8, hipMemcpyDeviceToDevice, b->bs));
+    RPCA_HIP_TRY(ctx, hipStreamSynchronize(b->bs));
     return RPCA_OK;
 }
 

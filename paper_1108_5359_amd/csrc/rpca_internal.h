@@ -202,3 +202,13 @@ int launch_lane_filter(rpca_ctx *ctx, const BatchTables &t, const FilterConsts &
 
 // Enqueue factor assembly + completion of every job of the table.
 int launch_batch_reconstruct(rpca_ctx *ctx, const BatchTables &t, hipStream_t stream);
+
+// The batch plan, reusable (the request loop re-plans one object per batch so
+// that its device buffers only grow).
+struct rpca_batch;
+int batch_check_tuning(rpca_ctx *ctx, const rpca_batch_tuning &tun);
+rpca_batch *batch_new(rpca_ctx *ctx, const rpca_opts &o, const rpca_batch_tuning &tun, int *status);
+// Lay out and check a new set of jobs; the index arrays are read after the
+// work enqueued on `stream`.
+int batch_plan(rpca_batch *b, const rpca_job *jobs, int64_t njobs, hipStream_t stream);
+hipStream_t batch_stream(rpca_batch *b);

@@ -243,7 +243,7 @@ lib.rpca_batch_tuning_default.argtypes = [ctypes.POINTER(rpca_batch_tuning)]
 lib.rpca_batch_tuning_default.restype = None
 lib.rpca_batch_create.argtypes = [_vp, ctypes.POINTER(rpca_job), _i64, ctypes.POINTER(rpca_opts),
                                   ctypes.POINTER(rpca_batch_tuning), ctypes.POINTER(_vp)]
-lib.rpca_batch_seed.argtypes = [_vp]
+lib.rpca_batch_seed.argtypes = [_vp, _vp]
 lib.rpca_batch_run.argtypes = [_vp, _vp]
 lib.rpca_batch_job_info.argtypes = [_vp, _i64, ctypes.POINTER(rpca_info)]
 lib.rpca_batch_destroy.argtypes = [_vp]
@@ -304,8 +304,8 @@ def rpca_batch_create(ctx: Context, jobs, opts, tuning=None) -> Batch:
     return Batch(ctx, jobs, opts, tuning)
 
 
-def rpca_batch_seed(batch: Batch) -> int:
-    return batch.ctx.check(lib.rpca_batch_seed(batch.handle))
+def rpca_batch_seed(batch: Batch, stream=None) -> int:
+    return batch.ctx.check(lib.rpca_batch_seed(batch.handle, _stream(stream)))
 
 
 def rpca_batch_run(batch: Batch, stream=None) -> int:
@@ -326,3 +326,108 @@ def rpca_batch_job_factors(batch: Batch, job_index: int, U, sigma, V) -> int:
     """U: (r, p) FP64 tensor (column-major p x r), sigma: (r,), V: (r, q)."""
     return batch.ctx.check(lib.rpca_batch_job_factors(batch.handle, job_index, _ptr(U), _ptr(sigma),
                                                       _ptr(V)))
+
+
+# ---------------------------------------------------------------- served form
+class rpca_server_opts(ctypes.Structure):
+    _fields_ = [("hbm_budget_bytes", ctypes.c_double), ("workers", _i32), ("max_batch", _i32)]
+
+
+class rpca_request_info(ctypes.Structure):
+    _fields_ = [("status", _i32), ("batch_size", _i32), ("info", rpca_info),
+                ("t_submit_ms", ctypes.c_double), ("t_admit_ms", ctypes.c_double),
+                ("t_done_ms", ctypes.c_double)]
+
+
+class rpca_server_stats(ctypes.Structure):
+    _fields_ = [("submitted", _i64), ("completed", _i64), ("failed", _i64), ("batches", _i64),
+                ("queued", _i64), ("peak_inflight_bytes", ctypes.c_double),
+                ("inflight_bytes", ctypes.c_double)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+lib.rpca_server_opts_default.argtypes = [ctypes.POINTER(rpca_server_opts)]
+lib.rpca_server_opts_default.restype = None
+lib.rpca_server_create.argtypes = [ctypes.c_int, ctypes.POINTER(rpca_opts),
+                                   ctypes.POINTER(rpca_batch_tuning),
+                                   ctypes.POINTER(rpca_server_opts), ctypes.POINTER(_vp)]
+lib.rpca_server_submit.argtypes = [_vp, ctypes.POINTER(rpca_job), ctypes.POINTER(_i64)]
+lib.rpca_server_wait.argtypes = [_vp, _i64, ctypes.POINTER(rpca_request_info)]
+lib.rpca_server_poll.argtypes = [_vp, _i64, ctypes.POINTER(_i32)]
+lib.rpca_server_get_stats.argtypes = [_vp, ctypes.POINTER(rpca_server_stats)]
+lib.rpca_server_error.argtypes = [_vp]
+lib.rpca_server_error.restype = ctypes.c_char_p
+lib.rpca_server_destroy.argtypes = [_vp]
+for _f in ("rpca_server_create", "rpca_server_submit", "rpca_server_wait", "rpca_server_poll",
+           "rpca_server_get_stats", "rpca_server_destroy"):
+    getattr(lib, _f).restype = ctypes.c_int
+
+
+def rpca_server_opts_default(**overrides) -> rpca_server_opts:
+    o = rpca_server_opts()
+    lib.rpca_server_opts_default(ctypes.byref(o))
+    for k, v in overrides.items():
+        if not hasattr(o, k):
+            raise AttributeError(k)
+        setattr(o, k, v)
+    return o
+
+
+class Server:
+    """Owns an ``rpca_server_t``: submit() queues a job, wait() returns its
+    ``rpca_request_info`` (raising RpcaError for a failed request)."""
+
+    def __init__(self, opts, tuning=None, server_opts=None, device: int = 0):
+        h = _vp()
+        st = lib.rpca_server_create(device, ctypes.byref(opts),
+                                    ctypes.byref(tuning) if tuning is not None else None,
+                                    ctypes.byref(server_opts) if server_opts is not None else None,
+                                    ctypes.byref(h))
+        if st != RPCA_OK:
+            raise RpcaError(st, lib.rpca_server_error(None).decode())
+        self.handle = h
+
+    def submit(self, job: rpca_job) -> int:
+        t = _i64(0)
+        st = lib.rpca_server_submit(self.handle, ctypes.byref(job), ctypes.byref(t))
+        if st != RPCA_OK:
+            raise RpcaError(st, lib.rpca_server_error(self.handle).decode())
+        return t.value
+
+    def wait(self, ticket: int, check: bool = True) -> rpca_request_info:
+        info = rpca_request_info()
+        st = lib.rpca_server_wait(self.handle, ticket, ctypes.byref(info))
+        if st < 0 and check:
+            raise RpcaError(st, f"request {ticket} failed")
+        return info
+
+    def poll(self, ticket: int) -> bool:
+        d = _i32(0)
+        st = lib.rpca_server_poll(self.handle, ticket, ctypes.byref(d))
+        if st != RPCA_OK:
+            raise RpcaError(st, lib.rpca_server_error(self.handle).decode())
+        return bool(d.value)
+
+    def stats(self) -> rpca_server_stats:
+        s = rpca_server_stats()
+        lib.rpca_server_get_stats(self.handle, ctypes.byref(s))
+        return s
+
+    def close(self):
+        if self.handle:
+            lib.rpca_server_destroy(self.handle)
+            self.handle = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
