@@ -15,6 +15,16 @@ the FP32 result.
 ``--config c3``: m = n = 50000, r = 50, N(0, 2e-5) factors, 5% corruptions
 uniform in [-1, 1], 500 x 500 seed, precision form (M: 10 GB).
 
+``--config c5``: the served form.  A Poisson stream of requests drawn from a
+mix (60% m = n = 2000, r = 5; 30% m = 20000 x n = 500, r = 10; 10% m = n =
+20000, r = 30; N(0, 1/max(m, n)) factors, 10% +-1 corruptions, 10r x 10r
+seeds, precision form) goes through the request loop (rpca_server_*, HBM
+budget 200 GB).  Inputs are synthesised on the device before the clock runs
+(a pool of instances per class that requests reuse).  Reported: the plain
+GPU form's rate (rpca_solve on one request after another), the server's
+rate at saturation (``value``), and p50 / p99 latency at 50%, 80%, 100% and
+200% of the plain rate.
+
 ``--config c4``: the batched form, 256 independent problems shaped like video
 background modelling (m ~ U{2048..76800} pixels, n ~ U{100..1000} frames,
 r ~ U{1..8}, N(0, 1/m) factors, 5-15% block foregrounds U[0, 1], 10r x 10r
@@ -63,6 +73,14 @@ BATCH = {"c4": dict(njobs=256, precision=0,
                    text="batched form: 256 problems, m ~ U{2048..76800}, n ~ U{100..1000}, "
                         "r ~ U{1..8}, N(0,1/m) factors, 5-15% U[0,1] block foregrounds, 10r x 10r "
                         "seeds; ~1.0e7 regressions of length 10-80; L and S over 5.6e9 entries")}
+
+
+SERVE = {"c5": dict(classes=[("A", 2000, 2000, 5, 0.6, 6), ("B", 20000, 500, 10, 0.3, 4),
+                            ("C", 20000, 20000, 30, 0.1, 2)],
+                   sparsity=0.10, values="pm1", budget=200e9, precision=1,
+                   text="served form: Poisson requests, 60% 2000x2000 r=5, 30% 20000x500 r=10, "
+                        "10% 20000x20000 r=30, N(0,1/max(m,n)) factors, 10% +-1 corruptions, 10r x 10r "
+                        "seeds, precision form, HBM budget 200 GB")}
 
 
 def log(*a):
@@ -320,13 +338,188 @@ def cpu_baseline_batch(wl, njobs):
             "seconds": round(t, 2)}
 
 
+def main_serve(args, R, torch):
+    import threading
+    import synth
+    w = SERVE[args.config]
+    dev = torch.device("cuda:0")
+    rng = np.random.Generator(np.random.PCG64([args.seed, 0xC5]))
+    # a pool of device-resident instances per class
+    pool = {}
+    t0 = time.perf_counter()
+    for name, m, n, r, frac, count in w["classes"]:
+        pool[name] = []
+        for k in range(count):
+            s = 1000 * args.seed + 10 * len(pool) + k
+            Md, _, _ = synth.lowrank_plus_sparse_device(m, n, r, factor_std=np.sqrt(1.0 / max(m, n)),
+                                                        sparsity=w["sparsity"], values=w["values"],
+                                                        seed=s, device=dev)
+            I, J = synth.seed_indices(m, n, 10 * r, 10 * r, seed=s)
+            pool[name].append((Md, m, n, r, torch.as_tensor(I).to(dev), torch.as_tensor(J).to(dev)))
+    torch.cuda.synchronize()
+    log(f"bench: generated the request pool in {time.perf_counter() - t0:.1f} s")
+    names = [c[0] for c in w["classes"]]
+    fracs = np.array([c[4] for c in w["classes"]])
+    counters = {nm: 0 for nm in names}
+
+    def draw(nreq):
+        reqs = []
+        for _ in range(nreq):
+            nm = names[int(rng.choice(len(names), p=fracs))]
+            inst = pool[nm][counters[nm] % len(pool[nm])]
+            counters[nm] += 1
+            reqs.append((nm, inst))
+        return reqs
+
+    opts = R.rpca_opts_default(precision=w["precision"])
+    # plain GPU form: rpca_solve on one request after another
+    ctx = R.Context(0)
+    plain_reqs = draw(args.plain_requests)
+    lat_plain = {nm: [] for nm in names}
+    for nm, (Md, m, n, r, dI, dJ) in plain_reqs[:3]:           # warm-up
+        L = torch.empty_like(Md)
+        S = torch.empty_like(Md)
+        R.rpca_solve(ctx, Md, m, n, m, r, opts, dI, dJ, L, m, S, m)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for nm, (Md, m, n, r, dI, dJ) in plain_reqs:
+        t1 = time.perf_counter()
+        L = torch.empty_like(Md)
+        S = torch.empty_like(Md)
+        R.rpca_solve(ctx, Md, m, n, m, r, opts, dI, dJ, L, m, S, m)
+        lat_plain[nm].append((time.perf_counter() - t1) * 1e3)
+        del L, S
+    plain_s = time.perf_counter() - t0
+    plain_rate = len(plain_reqs) / plain_s
+    log(f"bench: plain form {plain_rate:.2f} solves/s over {len(plain_reqs)} requests")
+
+    srv = R.Server(opts, None, R.rpca_server_opts_default(hbm_budget_bytes=w["budget"],
+                                                          workers=args.workers,
+                                                          max_batch=args.max_batch))
+
+    def run_stream(reqs, qps):
+        """Submit at Poisson arrival times (qps = None: all at once); wait for all."""
+        gaps = rng.exponential(1.0 / qps, len(reqs)) if qps else np.zeros(len(reqs))
+        arrivals = np.cumsum(gaps)
+        tickets, bufs = [None] * len(reqs), [None] * len(reqs)
+        infos = [None] * len(reqs)
+        done = threading.Event()
+
+        def waiter():
+            for k in range(len(reqs)):
+                while tickets[k] is None:
+                    time.sleep(0.0002)
+                infos[k] = srv.wait(tickets[k], check=False)
+                bufs[k] = None                                   # outputs no longer needed
+            done.set()
+
+        th = threading.Thread(target=waiter)
+        th.start()
+        t_start = time.perf_counter()
+        for k, (nm, (Md, m, n, r, dI, dJ)) in enumerate(reqs):
+            delay = t_start + arrivals[k] - time.perf_counter()
+            if delay > 0:
+                time.sleep(delay)
+            L = torch.empty_like(Md)
+            S = torch.empty_like(Md)
+            bufs[k] = (L, S)
+            tickets[k] = srv.submit(R.job(Md, m, n, m, r, dI, 10 * r, dJ, 10 * r, L, m, S, m))
+        done.wait()
+        th.join()
+        lat = np.array([i.t_done_ms - i.t_submit_ms for i in infos])
+        span = (max(i.t_done_ms for i in infos) - min(i.t_submit_ms for i in infos)) / 1e3
+        by_class = {}
+        for nm in names:
+            sel = [x for (c, _), x in zip(reqs, lat) if c == nm]
+            if sel:
+                by_class[nm] = {"n": len(sel), "p50_ms": round(float(np.percentile(sel, 50)), 2),
+                                "p99_ms": round(float(np.percentile(sel, 99)), 2)}
+        failed = sum(1 for i in infos if i.status < 0)
+        return {"offered_qps": round(qps, 3) if qps else None,
+                "achieved_solves_per_s": round(len(reqs) / span, 3),
+                "p50_ms": round(float(np.percentile(lat, 50)), 2),
+                "p99_ms": round(float(np.percentile(lat, 99)), 2),
+                "mean_batch": round(float(np.mean([i.batch_size for i in infos])), 2),
+                "failed": failed, "by_class": by_class}, infos, reqs
+
+    run_stream(draw(6), None)                                      # warm-up of the workers
+    sat, sat_infos, sat_reqs = run_stream(draw(args.requests), None)
+    log(f"bench: server at saturation {sat['achieved_solves_per_s']:.2f} solves/s "
+        f"(mean batch {sat['mean_batch']})")
+    levels = []
+    for f in (0.5, 0.8, 1.0, 2.0):
+        res, _, _ = run_stream(draw(args.requests), f * plain_rate)
+        res["load"] = f"{int(f * 100)}% of the plain rate"
+        levels.append(res)
+        log(f"bench: {res['load']}: {res['achieved_solves_per_s']:.2f} solves/s, p50 "
+            f"{res['p50_ms']:.1f} ms, p99 {res['p99_ms']:.1f} ms, mean batch {res['mean_batch']}")
+    st = srv.stats()
+    srv.close()
+
+    # roofline of the completion over the saturation run's batches (one record
+    # per batch: requests of a batch finish at the same instant)
+    batches = {}
+    for (nm, (Md, m, n, r, dI, dJ)), i in zip(sat_reqs, sat_infos):
+        b = batches.setdefault(round(i.t_done_ms, 6), [0.0, i.info.t_reconstruct_ms])
+        b[0] += 12.0 * m * n
+    rb = sum(v[0] for v in batches.values())
+    rt = sum(v[1] for v in batches.values()) * 1e-3
+    recon_gbs = rb / rt / 1e9 if rt > 0 else 0.0
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+        oracle.build()
+        Md, m, n, r, dI, dJ = pool["A"][0]
+        Mh = np.asfortranarray(Md.cpu().numpy().T)
+        I, J = dI.cpu().numpy(), dJ.cpu().numpy()
+        t0 = time.perf_counter()
+        for _ in range(3):
+            oracle.solve(Mh, r, I, J)
+        tc = time.perf_counter() - t0
+        cpu = {"value": round(3 / tc, 3), "unit": "solves/s", "cores": oracle.num_threads(0),
+               "kind": "oracle",
+               "sample": "3 solves of a class-A request (2000 x 2000, r = 5): seed, every column "
+                         "and row regression, completion, FP64", "seconds": round(tc, 2)}
+    out = {
+        "metric": "served PCP solves/s (request mix, p50/p99 latency)",
+        "value": sat["achieved_solves_per_s"],
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": args.requests,
+        "warmup": 6,
+        "ms_per_step": round(1e3 / sat["achieved_solves_per_s"], 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32 data, f16 contractions / f32 state (p >= 48), f64 seed",
+        "data": "synthetic",
+        "config": {"workload": w["text"], "name": args.config, "workers": args.workers,
+                   "max_batch": args.max_batch, "requests_per_level": args.requests},
+        "roofline": {"bound": "hbm", "kernel": "completion of the served batches",
+                     "achieved": round(recon_gbs, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                     "frac": round(recon_gbs / PEAK_HBM_GBS, 4), "traffic": None},
+        "cpu_baseline": cpu,
+        "detail": {"plain_solves_per_s": round(plain_rate, 3),
+                   "served_vs_plain": round(sat["achieved_solves_per_s"] / plain_rate, 3),
+                   "plain_latency_ms": {nm: round(float(np.median(v)), 2) for nm, v in lat_plain.items() if v},
+                   "saturation": sat, "levels": levels, "server": st.as_dict()},
+    }
+    print(json.dumps(out), flush=True)
+    ctx.close()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--seed", type=int, default=1)
-    ap.add_argument("--config", default="c2", choices=sorted(WORKLOADS) + sorted(BATCH))
+    ap.add_argument("--config", default="c2", choices=sorted(WORKLOADS) + sorted(BATCH) + sorted(SERVE))
+    ap.add_argument("--requests", type=int, default=60, help="served form: requests per load level")
+    ap.add_argument("--plain-requests", type=int, default=20,
+                    help="served form: requests of the plain-rate measurement")
+    ap.add_argument("--workers", type=int, default=3, help="served form: worker threads")
+    ap.add_argument("--max-batch", type=int, default=64, help="served form: requests per batch")
     ap.add_argument("--precision", type=int, default=None, help="0 = FP32, 1 = FP16 + refinement")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-compare", action="store_true", help="skip timing the other precision form")
@@ -349,6 +542,8 @@ def main():
 
     if args.config in BATCH:
         return main_batch(args, R, torch)
+    if args.config in SERVE:
+        return main_serve(args, R, torch)
     wl = Workload(args.config, args.seed, R, torch)
     wl.seed()
     precision = WORKLOADS[args.config]["precision"] if args.precision is None else args.precision
