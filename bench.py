@@ -249,9 +249,23 @@ class BatchWorkload:
         return elapsed, float(np.mean(fs)), float(np.mean(rs)), infos
 
 
+def calibrate_copy(torch, dev):
+    """A plain elementwise pass reading 1 GiB and writing 1 GiB (one kernel
+    per call), for scaling the FETCH_SIZE / WRITE_SIZE counters of a
+    profiled run to bytes."""
+    src = torch.ones(1 << 28, dtype=torch.float32, device=dev)
+    dst = torch.empty_like(src)
+    for _ in range(2):
+        torch.add(src, 1.0, out=dst)
+    torch.cuda.synchronize()
+    del src, dst
+
+
 def main_batch(args, R, torch):
     wl = BatchWorkload(args.config, args.seed, R, torch)
     wl.seed()
+    if args.calibrate_copy:
+        calibrate_copy(torch, wl.dev)
     elapsed, filt_ms, recon_ms, infos = wl.timed(args.steps, args.warmup)
     ms_per_step = elapsed * 1e3 / args.steps
     value = wl.regs * args.steps / elapsed
@@ -550,12 +564,7 @@ def main():
     opts = R.rpca_opts_default(precision=precision)
 
     if args.calibrate_copy:
-        src = torch.ones(1 << 28, dtype=torch.float32, device=wl.dev)
-        dst = torch.empty_like(src)
-        for _ in range(2):
-            dst.copy_(src)
-        torch.cuda.synchronize()
-        del src, dst
+        calibrate_copy(torch, wl.dev)
 
     elapsed, filt_ms, recon_ms, K, unconv = wl.timed(opts, args.steps, args.warmup)
     ms_per_step = elapsed * 1e3 / args.steps
@@ -581,7 +590,8 @@ def main():
                     "frac": round(filt_tflops / peak, 4),
                     "traffic": counter_traffic(f"l1_filter_{args.config}", digest)}
     else:
-        digest = source_digest(["paper_1108_5359_amd/csrc/reconstruct.hip"])
+        digest = source_digest(["paper_1108_5359_amd/csrc/reconstruct.hip",
+                                "paper_1108_5359_amd/csrc/recon_kernel.h"])
         roofline = {"bound": "hbm", "kernel": "reconstruct_kernel (+ assemble_factors)",
                     "achieved": round(recon_gbs, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
                     "frac": round(recon_gbs / PEAK_HBM_GBS, 4),
