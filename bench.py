@@ -150,7 +150,15 @@ class Workload:
         log(f"bench: seed status={R.rpca_status_string(st)} r_used={self.r_used} "
             f"iters={self.seed_iters} t={self.t_seed_ms:.1f} ms")
 
+    def step_overlapped(self, opts, stream):
+        """Steps 3-5 in one call, the completion overlapped with the filter."""
+        self.R.rpca_filter_complete(self.ctx, self.Md, self.m, self.n, self.m, self.dI, self.p,
+                                    self.dJ, self.q, self.dJc, self.dIc, self.U, self.sg, self.V,
+                                    self.r_used, opts, self.Qt, self.kc, self.Pt, self.kr, self.L,
+                                    self.m, self.S, self.m, stream)
+
     def step(self, opts, stream, evs=None):
+        """Steps 3-5 as two calls (filter, then completion), events around each."""
         R = self.R
         if evs:
             evs[0].record(stream)
@@ -166,18 +174,24 @@ class Workload:
             evs[2].record(stream)
 
     def timed(self, opts, steps, warmup):
+        """Headline: `steps` overlapped steps between two synchronisations.
+        Then as many sequential steps with events around each kernel launch
+        (the per-kernel durations of the roofline)."""
         torch = self.torch
         stream = torch.cuda.current_stream()
+        overlap = opts.overlap_chunks > 0
         for _ in range(warmup):
-            self.step(opts, stream)
-        torch.cuda.synchronize()
-        events = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(steps)]
+            (self.step_overlapped if overlap else self.step)(opts, stream)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for k in range(steps):
-            self.step(opts, stream, events[k])
+            (self.step_overlapped if overlap else self.step)(opts, stream)
         torch.cuda.synchronize()
         elapsed = time.perf_counter() - t0
+        events = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(steps)]
+        for k in range(steps):
+            self.step(opts, stream, events[k])
+        torch.cuda.synchronize()
         filt_ms = float(np.mean([e[0].elapsed_time(e[1]) for e in events]))
         recon_ms = float(np.mean([e[1].elapsed_time(e[2]) for e in events]))
         K = np.abs(np.concatenate([self.kc.cpu().numpy(), self.kr.cpu().numpy()]).astype(np.int64))
@@ -293,7 +307,9 @@ def main_batch(args, R, torch):
                     "achieved": round(filt_tflops, 3), "peak": PEAK_FP32_MFMA_TFLOPS,
                     "unit": "TFLOP/s", "frac": round(filt_tflops / PEAK_FP32_MFMA_TFLOPS, 4),
                     "traffic": counter_traffic(f"lane_filter_{args.config}", digest)}
-    detail = {"filter_ms": round(filt_ms, 4), "reconstruct_ms": round(recon_ms, 4),
+    detail = {"overlap_chunks": args.overlap_chunks,
+              "filter_ms": round(filt_ms, 4), "reconstruct_ms": round(recon_ms, 4),
+              "sequential_ms_per_step": round(filt_ms + recon_ms, 4),
               "reconstruct_gbs": round(recon_gbs, 1),
               "filter_tflops_contraction": round(filt_tflops, 3),
               "iters_mean": round(iters_total / wl.regs, 2),
@@ -535,6 +551,8 @@ def main():
     ap.add_argument("--workers", type=int, default=3, help="served form: worker threads")
     ap.add_argument("--max-batch", type=int, default=64, help="served form: requests per batch")
     ap.add_argument("--precision", type=int, default=None, help="0 = FP32, 1 = FP16 + refinement")
+    ap.add_argument("--overlap-chunks", type=int, default=0,
+                    help="column slabs of the overlapped filter + completion (0 = one after the other)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-compare", action="store_true", help="skip timing the other precision form")
     ap.add_argument("--cpu-sample", type=int, default=None,
@@ -561,7 +579,7 @@ def main():
     wl = Workload(args.config, args.seed, R, torch)
     wl.seed()
     precision = WORKLOADS[args.config]["precision"] if args.precision is None else args.precision
-    opts = R.rpca_opts_default(precision=precision)
+    opts = R.rpca_opts_default(precision=precision, overlap_chunks=args.overlap_chunks)
 
     if args.calibrate_copy:
         calibrate_copy(torch, wl.dev)
@@ -570,8 +588,9 @@ def main():
     ms_per_step = elapsed * 1e3 / args.steps
     regs = wl.nc + wl.mr
     value = regs * args.steps / elapsed
-    log(f"bench: precision={precision} {ms_per_step:.3f} ms/step  filter {filt_ms:.3f} ms  "
-        f"reconstruct {recon_ms:.3f} ms  K mean {K.mean():.1f} max {K.max()} unconverged {unconv}")
+    log(f"bench: precision={precision} overlap_chunks={args.overlap_chunks} {ms_per_step:.3f} ms/step "
+        f"(kernels one after the other: filter {filt_ms:.3f} ms + reconstruct {recon_ms:.3f} ms)  "
+        f"K mean {K.mean():.1f} max {K.max()} unconverged {unconv}")
 
     # Algorithmic work per launch: the filter's two contractions per iteration
     # (A^T g and A w: 4 p r flops per regression), the completion's 12 bytes
@@ -597,7 +616,9 @@ def main():
                     "frac": round(recon_gbs / PEAK_HBM_GBS, 4),
                     "traffic": counter_traffic(f"reconstruct_{args.config}", digest)}
 
-    detail = {"filter_ms": round(filt_ms, 4), "reconstruct_ms": round(recon_ms, 4),
+    detail = {"overlap_chunks": args.overlap_chunks,
+              "filter_ms": round(filt_ms, 4), "reconstruct_ms": round(recon_ms, 4),
+              "sequential_ms_per_step": round(filt_ms + recon_ms, 4),
               "filter_tflops_contraction": round(filt_tflops, 3),
               "reconstruct_gbs": round(recon_gbs, 1), "iters_mean": round(float(K.mean()), 2),
               "iters_max": int(K.max()), "unconverged": unconv,
@@ -611,7 +632,9 @@ def main():
         other = 1 - precision
         key = "precision_form" if other == 1 else "plain_fp32_form"
         try:
-            e2, f2, r2, K2, u2 = wl.timed(R.rpca_opts_default(precision=other), args.steps, 1)
+            e2, f2, r2, K2, u2 = wl.timed(R.rpca_opts_default(precision=other,
+                                                              overlap_chunks=args.overlap_chunks),
+                                          args.steps, 1)
         except R.RpcaError as err:
             detail[key] = {"unsupported": str(err)}
             e2 = None

@@ -86,6 +86,11 @@ typedef struct {
     uint64_t rng_seed;           /* seed of rpca_sample_indices inside rpca_solve           */
     int32_t precision;           /* 0 = FP32 filter; 1 = FP16 MFMA contractions + FP32      */
                                  /* refinement for regressions with p >= 48 (0)             */
+    int32_t overlap_chunks;      /* rpca_filter_complete / rpca_solve: column slabs whose   */
+                                 /* completion overlaps the filtering of the next slab;     */
+                                 /* 0 = filter, then complete (0: a filter launch whose     */
+                                 /* grid does not fill the chip lasts one wave's latency,   */
+                                 /* so slicing it costs more than the overlap saves)        */
 } rpca_opts;
 
 /* What rpca_solve reports. */
@@ -97,8 +102,9 @@ typedef struct {
     int64_t filt_iters_total;    /* sum of iteration counts (|count| for unconverged ones)  */
     int64_t filt_not_converged;  /* number of regressions that missed filt_eps              */
     double t_seed_ms;            /* wall time of step 2 (seed)                              */
-    double t_filter_ms;          /* device time of steps 3 + 4                              */
-    double t_reconstruct_ms;     /* device time of step 5                                   */
+    double t_filter_ms;          /* device time of steps 3 + 4 (with overlap_chunks > 0:    */
+                                 /* of steps 3-5, which then share the chip)                */
+    double t_reconstruct_ms;     /* device time of step 5 (0 with overlap_chunks > 0)       */
 } rpca_info;
 
 /* Fill *opts with the defaults listed above. */
@@ -221,6 +227,28 @@ int rpca_reconstruct(rpca_ctx_t ctx, const float *M, int64_t m, int64_t n, int64
                      int64_t q, const double *U, const double *sigma, const double *V,
                      int32_t r, const float *Qt, const float *Pt, float *L, int64_t ldl,
                      float *S, int64_t lds, hipStream_t stream);
+
+/*
+ * Steps 3, 4 and 5 together (Sec. 3.2-3.3; eqs. l1c', l1r', l1s'): what
+ * rpca_filter followed by rpca_reconstruct computes, with the completion of
+ * L and S overlapped with the filtering when opts->overlap_chunks > 0: the
+ * row regressions run first, then the column regressions in overlap_chunks
+ * slabs of columns, and the completion of each slab (on a second stream of
+ * the context) runs while the next slab's regressions are filtered.  The
+ * results are identical to the two calls made one after the other.
+ *   cols, rows   device int64: the sorted complements of seed_cols (n - q)
+ *                and seed_rows (m - p) (every other argument as in
+ *                rpca_filter and rpca_reconstruct; Qt / Pt and the iteration
+ *                arrays are outputs as there, iteration arrays may be NULL).
+ * Asynchronous on `stream`; later work on `stream` follows the whole call.
+ * Calls on one context must be ordered on one stream.
+ */
+int rpca_filter_complete(rpca_ctx_t ctx, const float *M, int64_t m, int64_t n, int64_t ldm,
+                         const int64_t *seed_rows, int64_t p, const int64_t *seed_cols, int64_t q,
+                         const int64_t *cols, const int64_t *rows, const double *U,
+                         const double *sigma, const double *V, int32_t r, const rpca_opts *opts,
+                         float *Qt, int32_t *col_iters, float *Pt, int32_t *row_iters, float *L,
+                         int64_t ldl, float *S, int64_t lds, hipStream_t stream);
 
 /*
  * Algorithm 2 end to end on M (m x n): steps 1-5 with target rank r.

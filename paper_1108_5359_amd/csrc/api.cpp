@@ -111,6 +111,8 @@ int check_opts(rpca_ctx *ctx, const rpca_opts &o)
         return set_status(ctx, RPCA_ERR_ARG, "opts: bad seed constants");
     if (o.precision != 0 && o.precision != 1)
         return set_status(ctx, RPCA_ERR_ARG, "opts: precision must be 0 (FP32) or 1 (FP16 + FP32 refinement)");
+    if (o.overlap_chunks < 0 || o.overlap_chunks > 16)
+        return set_status(ctx, RPCA_ERR_ARG, "opts: overlap_chunks must be in [0, 16]");
     return RPCA_OK;
 }
 
@@ -174,6 +176,7 @@ void rpca_opts_default(rpca_opts *o)
     o->filt_refresh = 8;
     o->rng_seed = 1;
     o->precision = 0;
+    o->overlap_chunks = 0;
 }
 
 const char *rpca_status_string(int s)
@@ -244,6 +247,10 @@ int rpca_ctx_destroy(rpca_ctx_t ctx)
         if (b->ptr) (void)hipFree(b->ptr);
     for (auto &e : ctx->ev)
         if (e) (void)hipEventDestroy(e);
+    for (auto &e : ctx->pev)
+        if (e) (void)hipEventDestroy(e);
+    if (ctx->aux) (void)hipStreamDestroy(ctx->aux);
+    if (ctx->xbuf_ws.ptr) (void)hipFree(ctx->xbuf_ws.ptr);
     if (ctx->blas) rocblas_destroy_handle(ctx->blas);
     delete ctx;
     return RPCA_OK;
@@ -426,6 +433,54 @@ int rpca_reconstruct(rpca_ctx_t ctx, const float *M, int64_t m, int64_t n, int64
     return launch_reconstruct(ctx, a, stream);
 }
 
+int rpca_filter_complete(rpca_ctx_t ctx, const float *M, int64_t m, int64_t n, int64_t ldm,
+                         const int64_t *seed_rows, int64_t p, const int64_t *seed_cols, int64_t q,
+                         const int64_t *cols, const int64_t *rows, const double *U,
+                         const double *sigma, const double *V, int32_t r, const rpca_opts *opts,
+                         float *Qt, int32_t *col_iters, float *Pt, int32_t *row_iters, float *L,
+                         int64_t ldl, float *S, int64_t lds, hipStream_t stream)
+{
+    if (!ctx) return RPCA_ERR_ARG;
+    ctx->last_error.clear();
+    int st;
+    if ((st = check_matrix(ctx, M, m, n, ldm, "M")) != RPCA_OK) return st;
+    if ((st = check_matrix(ctx, L, m, n, ldl, "L")) != RPCA_OK) return st;
+    if ((st = check_matrix(ctx, S, m, n, lds, "S")) != RPCA_OK) return st;
+    if (!opts) return set_status(ctx, RPCA_ERR_ARG, "filter_complete: NULL opts");
+    if ((st = check_opts(ctx, *opts)) != RPCA_OK) return st;
+    if (!seed_rows || !seed_cols || !U || !sigma || !V || (p < m && (!rows || !Pt)) ||
+        (q < n && (!cols || !Qt)))
+        return set_status(ctx, RPCA_ERR_ARG, "filter_complete: NULL argument");
+    if (p < 1 || q < 1 || p > m || q > n || r < 1 || r > std::min(p, q))
+        return set_status(ctx, RPCA_ERR_ARG, "filter_complete: need 1 <= r <= min(p, q), p <= m, q <= n");
+    if ((const void *)L == (const void *)S || (const void *)L == (const void *)M ||
+        (const void *)S == (const void *)M)
+        return set_status(ctx, RPCA_ERR_ARG, "filter_complete: L, S and M must be distinct buffers");
+    if ((q < n && !filter_supported(ctx, (int)p, r, opts->precision)) ||
+        (p < m && !filter_supported(ctx, (int)q, r, opts->precision)))
+        return set_status(ctx, RPCA_ERR_UNSUPPORTED, "filter_complete: seed size outside the built kernel classes");
+    RPCA_HIP_TRY(ctx, hipSetDevice(ctx->device));
+    ReconArgs a{M, m, n, ldm, seed_rows, p, seed_cols, q, U, sigma, V, r, Qt, Pt, L, ldl, S, lds};
+    const FilterConsts c = consts_of(*opts);
+    if (opts->overlap_chunks == 0) {
+        FilterSide sides[2]{};
+        int ns = 0;
+        if (q < n) sides[ns++] = FilterSide{M, seed_rows, cols, 1, ldm, m, n, U, (int32_t)p, (int32_t)p, r,
+                                            n - q, Qt, r, col_iters, nullptr, nullptr};
+        if (p < m) sides[ns++] = FilterSide{M, seed_cols, rows, ldm, 1, n, m, V, (int32_t)q, (int32_t)q, r,
+                                            m - p, Pt, r, row_iters, nullptr, nullptr};
+        if (ns == 2 && !filter_same_class(sides[0].p, sides[0].r, sides[1].p, sides[1].r)) {
+            if ((st = launch_filter(ctx, &sides[0], 1, c, stream)) != RPCA_OK) return st;
+            if ((st = launch_filter(ctx, &sides[1], 1, c, stream)) != RPCA_OK) return st;
+        } else if (ns > 0) {
+            if ((st = launch_filter(ctx, sides, ns, c, stream)) != RPCA_OK) return st;
+        }
+        return launch_reconstruct(ctx, a, stream);
+    }
+    PipelineArgs pa{a, cols, rows, col_iters, row_iters};
+    return launch_filter_complete(ctx, pa, c, opts->overlap_chunks, stream);
+}
+
 int rpca_solve(rpca_ctx_t ctx, const float *M, int64_t m, int64_t n, int64_t ldm, int32_t r,
                const rpca_opts *opts, const int64_t *seed_rows, const int64_t *seed_cols, float *L,
                int64_t ldl, float *S, int64_t lds, rpca_info *info, hipStream_t stream)
@@ -504,18 +559,26 @@ int rpca_solve(rpca_ctx_t ctx, const float *M, int64_t m, int64_t n, int64_t ldm
         s = FilterSide{M, dJ, dIc, ldm, 1, n, m, dV, (int32_t)q, (int32_t)q, ru, mc, dPt, ru, dit + nc};
     }
     const FilterConsts c = consts_of(*opts);
-    RPCA_HIP_TRY(ctx, hipEventRecord(ctx->ev[0], sm));
-    if (ns == 2 && !filter_same_class(sides[0].p, sides[0].r, sides[1].p, sides[1].r)) {
-        // different size classes: two launches
-        if ((st = launch_filter(ctx, &sides[0], 1, c, sm)) != RPCA_OK) return st;
-        if ((st = launch_filter(ctx, &sides[1], 1, c, sm)) != RPCA_OK) return st;
-    } else if (ns > 0) {
-        if ((st = launch_filter(ctx, sides, ns, c, sm)) != RPCA_OK) return st;
-    }
-    RPCA_HIP_TRY(ctx, hipEventRecord(ctx->ev[1], sm));
     ReconArgs a{M, m, n, ldm, dI, p, dJ, q, dU, dsig, dV, ru, dQt, dPt, L, ldl, S, lds};
-    if ((st = launch_reconstruct(ctx, a, sm)) != RPCA_OK) return st;
-    RPCA_HIP_TRY(ctx, hipEventRecord(ctx->ev[2], sm));
+    RPCA_HIP_TRY(ctx, hipEventRecord(ctx->ev[0], sm));
+    if (opts->overlap_chunks > 0) {
+        // steps 3-5 with the completion overlapped with the filter
+        PipelineArgs pa{a, dJc, dIc, dit, dit + nc};
+        if ((st = launch_filter_complete(ctx, pa, c, opts->overlap_chunks, sm)) != RPCA_OK) return st;
+        RPCA_HIP_TRY(ctx, hipEventRecord(ctx->ev[1], sm));
+        RPCA_HIP_TRY(ctx, hipEventRecord(ctx->ev[2], sm));
+    } else {
+        if (ns == 2 && !filter_same_class(sides[0].p, sides[0].r, sides[1].p, sides[1].r)) {
+            // different size classes: two launches
+            if ((st = launch_filter(ctx, &sides[0], 1, c, sm)) != RPCA_OK) return st;
+            if ((st = launch_filter(ctx, &sides[1], 1, c, sm)) != RPCA_OK) return st;
+        } else if (ns > 0) {
+            if ((st = launch_filter(ctx, sides, ns, c, sm)) != RPCA_OK) return st;
+        }
+        RPCA_HIP_TRY(ctx, hipEventRecord(ctx->ev[1], sm));
+        if ((st = launch_reconstruct(ctx, a, sm)) != RPCA_OK) return st;
+        RPCA_HIP_TRY(ctx, hipEventRecord(ctx->ev[2], sm));
+    }
 
     std::vector<int32_t> its((size_t)(nc + mc));
     if (!its.empty())

@@ -145,7 +145,15 @@ l1_filter_kernel(FilterLaunch L)
     const int64_t ldz = SIDE(ldz);
     int32_t *__restrict__ iters = SIDE(iters);
     floatx4 *__restrict__ xbuf = reinterpret_cast<floatx4 *>(SIDE(xbuf));
+    const int64_t *range = SIDE(range);
 #undef SIDE
+    // positions served: [jbeg, jend) (a device range when the launch serves
+    // one chunk of a side whose size is known only on the device)
+    int64_t jbeg = 0, jend = nreg;
+    if (range) {
+        jbeg = range[0];
+        jend = range[1];
+    }
 
     // ---- stage the basis in LDS, in the two fragment orders -------------
     for (int idx = threadIdx.x; idx < PT * RT * 256; idx += kWavesPerBlock * 64) {
@@ -173,10 +181,10 @@ l1_filter_kernel(FilterLaunch L)
     const int lane = threadIdx.x & 63;
     const int g = lane >> 4, c = lane & 15;
     const int64_t tile = (int64_t)block_in_side * kWavesPerBlock + wave;
-    const int64_t j = tile * 16 + c;
-    if (tile * 16 >= nreg) return;     // whole wave idle (no barrier follows)
+    const int64_t j = jbeg + tile * 16 + c;
+    if (jbeg + tile * 16 >= jend) return;     // whole wave idle (no barrier follows)
 
-    bool valid = j < nreg;
+    bool valid = j < jend;
     int64_t roff = 0;
     if (valid) {
         const int64_t ri = reg_idx[j];
@@ -326,7 +334,7 @@ l1_filter_kernel(FilterLaunch L)
         }
     }
 
-    if (j < nreg) {
+    if (j < jend) {
         if (valid) {
 #pragma unroll
             for (int mt = 0; mt < RT; ++mt)
@@ -386,7 +394,15 @@ l1_filter_kernel_f16(FilterLaunch L)
     const int64_t ldz = SIDE(ldz);
     int32_t *__restrict__ iters = SIDE(iters);
     floatx4 *__restrict__ xbuf = reinterpret_cast<floatx4 *>(SIDE(xbuf));
+    const int64_t *range = SIDE(range);
 #undef SIDE
+    // positions served: [jbeg, jend) (a device range when the launch serves
+    // one chunk of a side whose size is known only on the device)
+    int64_t jbeg = 0, jend = nreg;
+    if (range) {
+        jbeg = range[0];
+        jend = range[1];
+    }
     const float *f2glob = second ? L.frag32[1] : L.frag32[0];
 
     // ---- stage the basis -------------------------------------------------
@@ -429,10 +445,10 @@ l1_filter_kernel_f16(FilterLaunch L)
     const int lane = threadIdx.x & 63;
     const int g = lane >> 4, c = lane & 15;
     const int64_t tile = (int64_t)block_in_side * kWavesPerBlock + wave;
-    const int64_t j = tile * 16 + c;
-    if (tile * 16 >= nreg) return;     // whole wave idle (no barrier follows)
+    const int64_t j = jbeg + tile * 16 + c;
+    if (jbeg + tile * 16 >= jend) return;     // whole wave idle (no barrier follows)
 
-    bool valid = j < nreg;
+    bool valid = j < jend;
     int64_t roff = 0;
     if (valid) {
         const int64_t ri = reg_idx[j];
@@ -608,7 +624,7 @@ l1_filter_kernel_f16(FilterLaunch L)
         }
     }
 
-    if (j < nreg) {
+    if (j < jend) {
         if (valid) {
 #pragma unroll
             for (int mt = 0; mt < RT; ++mt)

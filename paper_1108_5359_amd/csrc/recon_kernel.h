@@ -40,10 +40,11 @@ constexpr int kIdxLds = 4096;
 // One workgroup of the factor assembly.  F: m x R4 row-major, G: n x R4
 // row-major, zero-padded to R4 >= r.  Threads [0, m) of the problem build
 // rows of F, threads [m, m + n) rows of G; `first` is the problem's thread
-// index of this workgroup's thread 0.  The sorted seed indices are staged in
-// LDS (when they fit) for the binary searches.  Contains a workgroup barrier:
-// every thread of the workgroup must call it.
-__device__ __forceinline__ void assemble_block(int64_t first, int64_t *sidx,
+// index of this workgroup's thread 0; threads at or beyond `end` only take
+// part in the barrier.  The sorted seed indices are staged in LDS (when they
+// fit) for the binary searches.  Contains a workgroup barrier: every thread
+// of the workgroup must call it.
+__device__ __forceinline__ void assemble_block(int64_t first, int64_t end, int64_t *sidx,
                                                const int64_t *__restrict__ seed_rows, int64_t p,
                                                const int64_t *__restrict__ seed_cols, int64_t q,
                                                const double *__restrict__ U,
@@ -65,6 +66,7 @@ __device__ __forceinline__ void assemble_block(int64_t first, int64_t *sidx,
     __syncthreads();
 
     const int64_t t = first + threadIdx.x;
+    if (t >= end) return;                 // after the barrier: nothing below waits
     if (t < m) {
         const int64_t i = t;
         const int64_t *idx = rows_in_lds ? sidx : seed_rows;

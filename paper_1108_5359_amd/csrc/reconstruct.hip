@@ -10,7 +10,7 @@ using namespace reconk;
 namespace {
 
 __global__ void __launch_bounds__(kAssembleThreads)
-assemble_factors(const int64_t *__restrict__ seed_rows, int64_t p,
+assemble_factors(int64_t first, int64_t end, const int64_t *__restrict__ seed_rows, int64_t p,
                  const int64_t *__restrict__ seed_cols, int64_t q,
                  const double *__restrict__ U, const double *__restrict__ sigma,
                  const double *__restrict__ V, int r,
@@ -18,8 +18,8 @@ assemble_factors(const int64_t *__restrict__ seed_rows, int64_t p,
                  int64_t m, int64_t n, int R4, float *__restrict__ F, float *__restrict__ G)
 {
     __shared__ int64_t sidx[kIdxLds];
-    assemble_block((int64_t)blockIdx.x * blockDim.x, sidx, seed_rows, p, seed_cols, q, U, sigma,
-                   V, r, Qt, Pt, m, n, R4, F, G);
+    assemble_block(first + (int64_t)blockIdx.x * blockDim.x, end, sidx, seed_rows, p, seed_cols, q,
+                   U, sigma, V, r, Qt, Pt, m, n, R4, F, G);
 }
 
 template <int R4, bool VEC>
@@ -66,14 +66,34 @@ int launch_reconstruct(rpca_ctx *ctx, const ReconArgs &a, hipStream_t stream)
     if (st != RPCA_OK) return st;
     float *F = static_cast<float *>(ctx->factors.ptr);
     float *G = F + (size_t)a.m * R4;
-    const int64_t nthreads = a.m + a.n;
-    hipLaunchKernelGGL(assemble_factors,
-                       dim3((unsigned)((nthreads + kAssembleThreads - 1) / kAssembleThreads)),
-                       dim3(kAssembleThreads), 0,
-                       stream, a.seed_rows, a.p, a.seed_cols, a.q, a.U, a.sigma, a.V, a.r, a.Qt,
-                       a.Pt, a.m, a.n, R4, F, G);
-    RPCA_HIP_TRY(ctx, hipGetLastError());
+    st = launch_assemble_range(ctx, a, R4, F, G, 0, a.m + a.n, stream);
+    if (st != RPCA_OK) return st;
+    return launch_complete_slab(ctx, a, R4, F, G, 0, a.n, stream);
+}
 
+int launch_assemble_range(rpca_ctx *ctx, const ReconArgs &a, int R4, float *F, float *G,
+                          int64_t first, int64_t end, hipStream_t stream)
+{
+    if (end <= first) return RPCA_OK;
+    hipLaunchKernelGGL(assemble_factors,
+                       dim3((unsigned)((end - first + kAssembleThreads - 1) / kAssembleThreads)),
+                       dim3(kAssembleThreads), 0, stream, first, end, a.seed_rows, a.p, a.seed_cols,
+                       a.q, a.U, a.sigma, a.V, a.r, a.Qt, a.Pt, a.m, a.n, R4, F, G);
+    RPCA_HIP_TRY(ctx, hipGetLastError());
+    return RPCA_OK;
+}
+
+int launch_complete_slab(rpca_ctx *ctx, const ReconArgs &full, int R4, const float *F,
+                         const float *G, int64_t j0, int64_t j1, hipStream_t stream)
+{
+    if (j1 <= j0) return RPCA_OK;
+    // the slab is the matrix of columns j0 .. j1 - 1 (contiguous in memory)
+    ReconArgs a = full;
+    a.M = full.M + j0 * full.ldm;
+    a.L = full.L + j0 * full.ldl;
+    a.S = full.S + j0 * full.lds;
+    a.n = j1 - j0;
+    G = G + j0 * R4;
     const bool vec = (a.ldm % 4 == 0) && (a.ldl % 4 == 0) && (a.lds % 4 == 0) &&
                      ((uintptr_t)a.M % 16 == 0) && ((uintptr_t)a.L % 16 == 0) &&
                      ((uintptr_t)a.S % 16 == 0);

@@ -18,6 +18,8 @@ struct DevBuf {
 
 struct rpca_ctx {
     int device = 0;
+    hipStream_t aux = nullptr;      // second stream of the overlapped form (created on first use)
+    hipEvent_t pev[40] = {};        // its events
     int num_cu = 0;
     size_t max_lds = 0;
     std::string last_error;
@@ -73,6 +75,8 @@ struct FilterSide {
     int64_t ldz;
     int32_t *iters;
     float *xbuf;          // workspace: x in fragment order, for the periodic refresh
+    const int64_t *range; // optional device [begin, end): regression positions served
+                          // (nreg then only bounds end - begin); null = [0, nreg)
 };
 
 struct FilterConsts {
@@ -110,6 +114,25 @@ struct ReconArgs {
 };
 
 int launch_reconstruct(rpca_ctx *ctx, const ReconArgs &a, hipStream_t stream);
+
+// Pieces of the completion for the overlapped form: assemble rows
+// [first, end) of the stacked factors (F rows are [0, m), G row j is m + j)
+// and complete the column slab [j0, j1) of L and S.
+int launch_assemble_range(rpca_ctx *ctx, const ReconArgs &a, int R4, float *F, float *G,
+                          int64_t first, int64_t end, hipStream_t stream);
+int launch_complete_slab(rpca_ctx *ctx, const ReconArgs &a, int R4, const float *F,
+                         const float *G, int64_t j0, int64_t j1, hipStream_t stream);
+
+// Steps 3-5 of one problem with the completion of column slab k overlapped
+// with the filtering of the column regressions of slab k + 1 (second stream).
+struct PipelineArgs {
+    ReconArgs rec;               // M, sizes, seed indices and factors, Qt, Pt, L, S
+    const int64_t *cols;         // sorted complement of the seed columns (n - q)
+    const int64_t *rows;         // sorted complement of the seed rows (m - p)
+    int32_t *col_iters, *row_iters;
+};
+int launch_filter_complete(rpca_ctx *ctx, const PipelineArgs &a, const FilterConsts &c,
+                           int chunks, hipStream_t stream);
 
 // ---------------------------------------------------------------- seed
 struct SeedOut {

@@ -44,6 +44,7 @@ class rpca_opts(ctypes.Structure):
         ("filt_beta0_scale", ctypes.c_double), ("filt_beta_max_scale", ctypes.c_double),
         ("filt_max_iter", ctypes.c_int32), ("filt_refresh", ctypes.c_int32),
         ("rng_seed", ctypes.c_uint64), ("precision", ctypes.c_int32),
+        ("overlap_chunks", ctypes.c_int32),
     ]
 
 
@@ -83,6 +84,10 @@ lib.rpca_filter.argtypes = [_vp, _vp, _i64, _i64, _i64, _vp, _i64, _vp, _i64, _v
                             _vp, _vp, _i32, ctypes.POINTER(rpca_opts), _vp, _vp, _vp, _vp, _vp]
 lib.rpca_reconstruct.argtypes = [_vp, _vp, _i64, _i64, _i64, _vp, _i64, _vp, _i64, _vp, _vp,
                                  _vp, _i32, _vp, _vp, _vp, _i64, _vp, _i64, _vp]
+lib.rpca_filter_complete.argtypes = [_vp, _vp, _i64, _i64, _i64, _vp, _i64, _vp, _i64, _vp, _vp,
+                                     _vp, _vp, _vp, _i32, ctypes.POINTER(rpca_opts), _vp, _vp,
+                                     _vp, _vp, _vp, _i64, _vp, _i64, _vp]
+lib.rpca_filter_complete.restype = ctypes.c_int
 lib.rpca_solve.argtypes = [_vp, _vp, _i64, _i64, _i64, _i32, ctypes.POINTER(rpca_opts), _vp,
                            _vp, _vp, _i64, _vp, _i64, ctypes.POINTER(rpca_info), _vp]
 for _f in ("rpca_ctx_create", "rpca_ctx_destroy", "rpca_sample_indices", "rpca_seed",
@@ -431,3 +436,12 @@ class Server:
             self.close()
         except Exception:
             pass
+
+
+def rpca_filter_complete(ctx: Context, M, m, n, ldm, seed_rows, p, seed_cols, q, cols, rows, U, sigma,
+                         V, r, opts, Qt, col_iters, Pt, row_iters, L, ldl, S, lds, stream=None):
+    return ctx.check(lib.rpca_filter_complete(ctx.handle, _ptr(M), m, n, ldm, _ptr(seed_rows), p,
+                                              _ptr(seed_cols), q, _ptr(cols), _ptr(rows), _ptr(U),
+                                              _ptr(sigma), _ptr(V), r, ctypes.byref(opts), _ptr(Qt),
+                                              _ptr(col_iters), _ptr(Pt), _ptr(row_iters), _ptr(L),
+                                              ldl, _ptr(S), lds, _stream(stream)))
