@@ -224,6 +224,7 @@ class BatchWorkload:
         log(f"bench: generated in {time.perf_counter() - t0:.1f} s")
         self.ctx = R.Context(0)
         self.tuning = tuning if tuning is not None else R.rpca_batch_tuning_default()
+        self.tuning_source = "library defaults" if tuning is None else "autotuner"
         self.batch = R.Batch(self.ctx, jobs, R.rpca_opts_default(precision=w["precision"]),
                              self.tuning)
         self.regs = sum((s.m - s.p) + (s.n - s.q) for s in self.specs)
@@ -276,7 +277,10 @@ def calibrate_copy(torch, dev):
 
 
 def main_batch(args, R, torch):
-    wl = BatchWorkload(args.config, args.seed, R, torch)
+    from paper_1108_5359_amd import autotune
+    tuned = None if args.no_tuned else autotune.load()
+    tuning = R.rpca_batch_tuning_default(**tuned) if tuned else None
+    wl = BatchWorkload(args.config, args.seed, R, torch, tuning)
     wl.seed()
     if args.calibrate_copy:
         calibrate_copy(torch, wl.dev)
@@ -315,7 +319,7 @@ def main_batch(args, R, torch):
               "iters_mean": round(iters_total / wl.regs, 2),
               "iters_max": int(max(i.filt_iters_max for i in infos)), "unconverged": int(unconv),
               "t_seed_ms": round(wl.t_seed_ms, 1), "jobs": len(wl.specs),
-              "tuning": wl.tuning.as_dict()}
+              "tuning": wl.tuning.as_dict(), "tuning_source": wl.tuning_source}
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline_batch(wl, args.cpu_sample if args.cpu_sample is not None else 6)
@@ -549,6 +553,8 @@ def main():
     ap.add_argument("--plain-requests", type=int, default=20,
                     help="served form: requests of the plain-rate measurement")
     ap.add_argument("--workers", type=int, default=3, help="served form: worker threads")
+    ap.add_argument("--no-tuned", action="store_true",
+                    help="batched form: library defaults instead of the autotuner's results")
     ap.add_argument("--max-batch", type=int, default=64, help="served form: requests per batch")
     ap.add_argument("--precision", type=int, default=None, help="0 = FP32, 1 = FP16 + refinement")
     ap.add_argument("--overlap-chunks", type=int, default=0,
