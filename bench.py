@@ -94,6 +94,13 @@ def source_digest(paths) -> str:
     return h.hexdigest()[:16]
 
 
+# filter kernel forms (rpca_filter_form): names, kernels, counter summary keys
+FORM_NAMES = {0: "fp16", 1: "tile", 2: "split"}
+FORM_KERNELS = {0: "l1_filter_kernel_f16 (fp16 MFMA)", 1: "l1_filter_kernel (fp32 MFMA, tile form)",
+                2: "l1_filter_split_kernel (fp32 MFMA, split form)"}
+FORM_KEYS = {0: "l1_filter", 1: "l1_filter", 2: "l1_filter_split"}
+
+
 def counter_traffic(kernel_key: str, digest: str):
     """HBM bytes per launch from the committed rocprofv3 counter summary, or
     None when there is none or the kernel source changed since."""
@@ -311,7 +318,7 @@ def main_batch(args, R, torch):
                     "achieved": round(filt_tflops, 3), "peak": PEAK_FP32_MFMA_TFLOPS,
                     "unit": "TFLOP/s", "frac": round(filt_tflops / PEAK_FP32_MFMA_TFLOPS, 4),
                     "traffic": counter_traffic(f"lane_filter_{args.config}", digest)}
-    detail = {"overlap_chunks": args.overlap_chunks,
+    detail = {"overlap_chunks": args.overlap_chunks, "filter_form": FORM_NAMES[form],
               "filter_ms": round(filt_ms, 4), "reconstruct_ms": round(recon_ms, 4),
               "sequential_ms_per_step": round(filt_ms + recon_ms, 4),
               "reconstruct_gbs": round(recon_gbs, 1),
@@ -559,6 +566,8 @@ def main():
     ap.add_argument("--precision", type=int, default=None, help="0 = FP32, 1 = FP16 + refinement")
     ap.add_argument("--overlap-chunks", type=int, default=0,
                     help="column slabs of the overlapped filter + completion (0 = one after the other)")
+    ap.add_argument("--filter-form", type=int, default=0,
+                    help="FP32 filter kernel: 0 = automatic, 1 = tile form, 2 = split form")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-compare", action="store_true", help="skip timing the other precision form")
     ap.add_argument("--cpu-sample", type=int, default=None,
@@ -585,7 +594,9 @@ def main():
     wl = Workload(args.config, args.seed, R, torch)
     wl.seed()
     precision = WORKLOADS[args.config]["precision"] if args.precision is None else args.precision
-    opts = R.rpca_opts_default(precision=precision, overlap_chunks=args.overlap_chunks)
+    opts = R.rpca_opts_default(precision=precision, overlap_chunks=args.overlap_chunks,
+                               filter_form=args.filter_form)
+    form = R.rpca_filter_form(wl.ctx, wl.p, wl.r_used, wl.nc + wl.mr, opts)
 
     if args.calibrate_copy:
         calibrate_copy(torch, wl.dev)
@@ -594,7 +605,8 @@ def main():
     ms_per_step = elapsed * 1e3 / args.steps
     regs = wl.nc + wl.mr
     value = regs * args.steps / elapsed
-    log(f"bench: precision={precision} overlap_chunks={args.overlap_chunks} {ms_per_step:.3f} ms/step "
+    log(f"bench: precision={precision} form={FORM_NAMES[form]} overlap_chunks={args.overlap_chunks} "
+        f"{ms_per_step:.3f} ms/step "
         f"(kernels one after the other: filter {filt_ms:.3f} ms + reconstruct {recon_ms:.3f} ms)  "
         f"K mean {K.mean():.1f} max {K.max()} unconverged {unconv}")
 
@@ -607,13 +619,11 @@ def main():
     recon_gbs = recon_bytes / (recon_ms * 1e-3) / 1e9
     if filt_ms >= recon_ms:
         digest = source_digest(["paper_1108_5359_amd/csrc/filter_kernel.h"])
-        peak = PEAK_FP16_MFMA_TFLOPS if precision == 1 and wl.p >= 48 else PEAK_FP32_MFMA_TFLOPS
-        roofline = {"bound": "mfma",
-                    "kernel": "l1_filter_kernel_f16 (fp16 MFMA)" if peak > 1000 else
-                              "l1_filter_kernel (fp32 MFMA)",
+        peak = PEAK_FP16_MFMA_TFLOPS if form == 0 else PEAK_FP32_MFMA_TFLOPS
+        roofline = {"bound": "mfma", "kernel": FORM_KERNELS[form],
                     "achieved": round(filt_tflops, 3), "peak": peak, "unit": "TFLOP/s",
                     "frac": round(filt_tflops / peak, 4),
-                    "traffic": counter_traffic(f"l1_filter_{args.config}", digest)}
+                    "traffic": counter_traffic(f"{FORM_KEYS[form]}_{args.config}", digest)}
     else:
         digest = source_digest(["paper_1108_5359_amd/csrc/reconstruct.hip",
                                 "paper_1108_5359_amd/csrc/recon_kernel.h"])
@@ -658,6 +668,19 @@ def main():
                        "relF_vs_headline_form": round(float(np.hypot(dq, dp) / np.hypot(nq, np_)), 10)}
         log(f"bench: precision={other} {e2 * 1e3 / args.steps:.3f} ms/step  filter {f2:.3f} ms")
         wl.timed(opts, 1, 0)        # leave the headline form's outputs in place
+
+    if not args.no_compare and form in (1, 2):
+        # the other FP32 kernel form on the same matrix
+        other_form = 3 - form
+        o2 = R.rpca_opts_default(precision=precision, overlap_chunks=args.overlap_chunks,
+                                 filter_form=other_form)
+        if R.rpca_filter_form(wl.ctx, wl.p, wl.r_used, wl.nc + wl.mr, o2) == other_form:
+            e3, f3, r3, K3, u3 = wl.timed(o2, args.steps, 1)
+            detail[f"{FORM_NAMES[other_form]}_form"] = {
+                "ms_per_step": round(e3 * 1e3 / args.steps, 4), "filter_ms": round(f3, 4),
+                "iters_mean": round(float(K3.mean()), 2), "unconverged": u3}
+            log(f"bench: form={FORM_NAMES[other_form]} {e3 * 1e3 / args.steps:.3f} ms/step  filter {f3:.3f} ms")
+            wl.timed(opts, 1, 0)
 
     cpu = None
     if not args.no_cpu_baseline:

@@ -91,6 +91,13 @@ typedef struct {
                                  /* 0 = filter, then complete (0: a filter launch whose     */
                                  /* grid does not fill the chip lasts one wave's latency,   */
                                  /* so slicing it costs more than the overlap saves)        */
+    int32_t filter_form;         /* FP32 filter kernels: 0 = chosen from the regression     */
+                                 /* count (automatic), 1 = tile form (one wave per 16      */
+                                 /* regressions), 2 = split form (one workgroup of four    */
+                                 /* waves per 16 regressions, each wave a quarter of the   */
+                                 /* elements) where built for the class, else the tile     */
+                                 /* form.  Results agree within rounding, not bit for bit. */
+                                 /* (0)                                                    */
 } rpca_opts;
 
 /* What rpca_solve reports. */
@@ -106,6 +113,14 @@ typedef struct {
                                  /* of steps 3-5, which then share the chip)                */
     double t_reconstruct_ms;     /* device time of step 5 (0 with overlap_chunks > 0)       */
 } rpca_info;
+
+/* Which filter kernel a call with these options takes for `nreg`
+ * regressions of p elements and rank r (nreg: all regressions of the call,
+ * both families): *form = 0 FP16 contractions (precision form), 1 FP32 tile
+ * form, 2 FP32 split form (see filter_form).  Host only; launches nothing.
+ * Errors: RPCA_ERR_ARG (null pointer, bad options, p < 1, r < 1, nreg < 0). */
+int rpca_filter_form(rpca_ctx_t ctx, int64_t p, int32_t r, int64_t nreg, const rpca_opts *opts,
+                     int32_t *form);
 
 /* Fill *opts with the defaults listed above. */
 void rpca_opts_default(rpca_opts *opts);

@@ -113,6 +113,8 @@ int check_opts(rpca_ctx *ctx, const rpca_opts &o)
         return set_status(ctx, RPCA_ERR_ARG, "opts: precision must be 0 (FP32) or 1 (FP16 + FP32 refinement)");
     if (o.overlap_chunks < 0 || o.overlap_chunks > 16)
         return set_status(ctx, RPCA_ERR_ARG, "opts: overlap_chunks must be in [0, 16]");
+    if (o.filter_form < 0 || o.filter_form > 2)
+        return set_status(ctx, RPCA_ERR_ARG, "opts: filter_form must be 0 (automatic), 1 (tile) or 2 (split)");
     return RPCA_OK;
 }
 
@@ -126,6 +128,8 @@ FilterConsts consts_of(const rpca_opts &o)
     c.max_iter = o.filt_max_iter;
     c.refresh = o.filt_refresh;
     c.precision = o.precision;
+    c.form = o.filter_form;
+    c.plan_regs = 0;
     return c;
 }
 
@@ -177,6 +181,7 @@ void rpca_opts_default(rpca_opts *o)
     o->rng_seed = 1;
     o->precision = 0;
     o->overlap_chunks = 0;
+    o->filter_form = 0;
 }
 
 const char *rpca_status_string(int s)
@@ -343,7 +348,8 @@ int rpca_filter(rpca_ctx_t ctx, const float *M, int64_t m, int64_t n, int64_t ld
     if (nc < 0 || nr < 0) return set_status(ctx, RPCA_ERR_ARG, "filter: negative count");
     if (ns == 0) return RPCA_OK;
     RPCA_HIP_TRY(ctx, hipSetDevice(ctx->device));
-    const FilterConsts c = consts_of(*opts);
+    FilterConsts c = consts_of(*opts);
+    c.plan_regs = nc + nr;
     if (ns == 2 && !filter_same_class(sides[0].p, sides[0].r, sides[1].p, sides[1].r)) {
         if ((st = launch_filter(ctx, &sides[0], 1, c, stream)) != RPCA_OK) return st;
         return launch_filter(ctx, &sides[1], 1, c, stream);
@@ -461,7 +467,8 @@ int rpca_filter_complete(rpca_ctx_t ctx, const float *M, int64_t m, int64_t n, i
         return set_status(ctx, RPCA_ERR_UNSUPPORTED, "filter_complete: seed size outside the built kernel classes");
     RPCA_HIP_TRY(ctx, hipSetDevice(ctx->device));
     ReconArgs a{M, m, n, ldm, seed_rows, p, seed_cols, q, U, sigma, V, r, Qt, Pt, L, ldl, S, lds};
-    const FilterConsts c = consts_of(*opts);
+    FilterConsts c = consts_of(*opts);
+    c.plan_regs = (n - q) + (m - p);
     if (opts->overlap_chunks == 0) {
         FilterSide sides[2]{};
         int ns = 0;
@@ -479,6 +486,20 @@ int rpca_filter_complete(rpca_ctx_t ctx, const float *M, int64_t m, int64_t n, i
     }
     PipelineArgs pa{a, cols, rows, col_iters, row_iters};
     return launch_filter_complete(ctx, pa, c, opts->overlap_chunks, stream);
+}
+
+int rpca_filter_form(rpca_ctx_t ctx, int64_t p, int32_t r, int64_t nreg, const rpca_opts *opts,
+                     int32_t *form)
+{
+    if (!ctx) return RPCA_ERR_ARG;
+    ctx->last_error.clear();
+    if (!opts || !form) return set_status(ctx, RPCA_ERR_ARG, "filter_form: NULL argument");
+    int st = check_opts(ctx, *opts);
+    if (st != RPCA_OK) return st;
+    if (p < 1 || p > INT32_MAX || r < 1 || nreg < 0)
+        return set_status(ctx, RPCA_ERR_ARG, "filter_form: need p >= 1, r >= 1, nreg >= 0");
+    *form = filter_form_of(ctx, (int)p, r, opts->precision, opts->filter_form, nreg);
+    return RPCA_OK;
 }
 
 int rpca_solve(rpca_ctx_t ctx, const float *M, int64_t m, int64_t n, int64_t ldm, int32_t r,
@@ -558,7 +579,8 @@ int rpca_solve(rpca_ctx_t ctx, const float *M, int64_t m, int64_t n, int64_t ldm
         FilterSide &s = sides[ns++];
         s = FilterSide{M, dJ, dIc, ldm, 1, n, m, dV, (int32_t)q, (int32_t)q, ru, mc, dPt, ru, dit + nc};
     }
-    const FilterConsts c = consts_of(*opts);
+    FilterConsts c = consts_of(*opts);
+    c.plan_regs = nc + mc;
     ReconArgs a{M, m, n, ldm, dI, p, dJ, q, dU, dsig, dV, ru, dQt, dPt, L, ldl, S, lds};
     RPCA_HIP_TRY(ctx, hipEventRecord(ctx->ev[0], sm));
     if (opts->overlap_chunks > 0) {

@@ -7,19 +7,19 @@
 #include <string>
 
 namespace filterk {
-extern template int launch_filter_pt<1>(rpca_ctx *, int, const FilterLaunch &, int, hipStream_t);
-extern template int launch_filter_pt<2>(rpca_ctx *, int, const FilterLaunch &, int, hipStream_t);
-extern template int launch_filter_pt<3>(rpca_ctx *, int, const FilterLaunch &, int, hipStream_t);
-extern template int launch_filter_pt<4>(rpca_ctx *, int, const FilterLaunch &, int, hipStream_t);
-extern template int launch_filter_pt<5>(rpca_ctx *, int, const FilterLaunch &, int, hipStream_t);
-extern template int launch_filter_pt<7>(rpca_ctx *, int, const FilterLaunch &, int, hipStream_t);
-extern template int launch_filter_pt<8>(rpca_ctx *, int, const FilterLaunch &, int, hipStream_t);
-extern template int launch_filter_pt<10>(rpca_ctx *, int, const FilterLaunch &, int, hipStream_t);
-extern template int launch_filter_pt<13>(rpca_ctx *, int, const FilterLaunch &, int, hipStream_t);
-extern template int launch_filter_pt<16>(rpca_ctx *, int, const FilterLaunch &, int, hipStream_t);
-extern template int launch_filter_pt<19>(rpca_ctx *, int, const FilterLaunch &, int, hipStream_t);
-extern template int launch_filter_pt<26>(rpca_ctx *, int, const FilterLaunch &, int, hipStream_t);
-extern template int launch_filter_pt<32>(rpca_ctx *, int, const FilterLaunch &, int, hipStream_t);
+extern template int launch_filter_pt<1>(rpca_ctx *, int, const FilterLaunch &, int, bool, hipStream_t);
+extern template int launch_filter_pt<2>(rpca_ctx *, int, const FilterLaunch &, int, bool, hipStream_t);
+extern template int launch_filter_pt<3>(rpca_ctx *, int, const FilterLaunch &, int, bool, hipStream_t);
+extern template int launch_filter_pt<4>(rpca_ctx *, int, const FilterLaunch &, int, bool, hipStream_t);
+extern template int launch_filter_pt<5>(rpca_ctx *, int, const FilterLaunch &, int, bool, hipStream_t);
+extern template int launch_filter_pt<7>(rpca_ctx *, int, const FilterLaunch &, int, bool, hipStream_t);
+extern template int launch_filter_pt<8>(rpca_ctx *, int, const FilterLaunch &, int, bool, hipStream_t);
+extern template int launch_filter_pt<10>(rpca_ctx *, int, const FilterLaunch &, int, bool, hipStream_t);
+extern template int launch_filter_pt<13>(rpca_ctx *, int, const FilterLaunch &, int, bool, hipStream_t);
+extern template int launch_filter_pt<16>(rpca_ctx *, int, const FilterLaunch &, int, bool, hipStream_t);
+extern template int launch_filter_pt<19>(rpca_ctx *, int, const FilterLaunch &, int, bool, hipStream_t);
+extern template int launch_filter_pt<26>(rpca_ctx *, int, const FilterLaunch &, int, bool, hipStream_t);
+extern template int launch_filter_pt<32>(rpca_ctx *, int, const FilterLaunch &, int, bool, hipStream_t);
 } // namespace filterk
 
 using namespace filterk;
@@ -48,6 +48,22 @@ size_t lds_limit(rpca_ctx *ctx) { return ctx->max_lds ? ctx->max_lds : 65536; }
 // tolerance under FP16 products (measured: p = 30 -> 2e-3, p = 50 -> 1.5e-7).
 constexpr int kMinPHalf = 48;
 
+// Automatic choice of the FP32 kernel form for `tiles` 16-regression tiles
+// of class (PT, KS) on `ncu` compute units.  The tile form gives each SIMD
+// whole tiles (a workgroup of four tile waves per CU slot), the split form a
+// quarter of a tile per wave (one tile per workgroup).  Compare the
+// contraction work of the busiest SIMD: ceil(tiles / 4 / ncu) tiles of PT
+// element tiles against ceil(tiles / ncu) waves of ceil(PT / 4); the split
+// form must win by a quarter to pay for its exchange and barrier per step.
+bool choose_split(int PT, int KS, int64_t tiles, int ncu)
+{
+    if (!split_built(PT, KS) || ncu < 1 || tiles < 1) return false;
+    const int64_t tile_blocks = (tiles + kWavesPerBlock - 1) / kWavesPerBlock;
+    const int64_t busiest_tile = (tile_blocks + ncu - 1) / ncu * PT;
+    const int64_t busiest_split = (tiles + ncu - 1) / ncu * ((PT + kWavesPerBlock - 1) / kWavesPerBlock);
+    return 5 * busiest_split <= 4 * busiest_tile;
+}
+
 } // namespace
 
 bool filter_supported(rpca_ctx *ctx, int p, int r, int precision)
@@ -58,6 +74,15 @@ bool filter_supported(rpca_ctx *ctx, int p, int r, int precision)
     if (PT < 0 || KS < 0) return false;
     if (precision == 1) return lds_bytes_f16(PT, KS, false) <= lds_limit(ctx);
     return lds_bytes(PT, KS) <= lds_limit(ctx);
+}
+
+int filter_form_of(rpca_ctx *ctx, int p, int r, int precision, int form, int64_t regs)
+{
+    if (precision == 1 && p >= kMinPHalf) return 0;
+    const int PT = pick_pt(p, 0), KS = pick_ks(r);
+    if (PT < 0 || KS < 0 || form == 1 || !split_built(PT, KS)) return 1;
+    if (form == 2) return 2;
+    return choose_split(PT, KS, (regs + 15) / 16, ctx->num_cu) ? 2 : 1;
 }
 
 bool filter_same_class(int p0, int r0, int p1, int r1)
@@ -118,12 +143,26 @@ int launch_filter(rpca_ctx *ctx, const FilterSide *sides, int nsides, const Filt
         }
         if (nsides == 1) L.frag32[1] = L.frag32[0];
     }
+    // FP32 kernel form: the caller's choice, else from the tile count of the
+    // whole call (plan_regs) or of this launch
+    bool split = false;
+    if (c.precision == 0 && c.form != 1 && split_built(PT, KS)) {
+        if (c.form == 2) {
+            split = true;
+        } else {
+            int64_t tiles = 0;
+            if (c.plan_regs > 0) tiles = (c.plan_regs + 15) / 16;
+            else
+                for (int s = 0; s < nsides; ++s) tiles += (sides[s].nreg + 15) / 16;
+            split = choose_split(PT, KS, tiles, ctx->num_cu);
+        }
+    }
     int nblocks = 0;
     for (int s = 0; s < nsides; ++s) {
         L.side[s] = sides[s];
         L.side[s].xbuf = static_cast<float *>(ctx->xbuf_ws.ptr) + xoff[s];
         const int64_t tiles = (sides[s].nreg + 15) / 16;
-        const int64_t blocks = (tiles + kWavesPerBlock - 1) / kWavesPerBlock;
+        const int64_t blocks = split ? tiles : (tiles + kWavesPerBlock - 1) / kWavesPerBlock;
         if (blocks > INT_MAX / 2) return set_status(ctx, RPCA_ERR_UNSUPPORTED, "filter: too many regressions");
         if (s == 0) L.nblocks0 = (int)blocks;
         nblocks += (int)blocks;
@@ -131,19 +170,19 @@ int launch_filter(rpca_ctx *ctx, const FilterSide *sides, int nsides, const Filt
     if (nsides == 1) L.side[1] = sides[0];
     if (nblocks == 0) return RPCA_OK;
     switch (PT) {
-    case 1: return launch_filter_pt<1>(ctx, KS, L, nblocks, stream);
-    case 2: return launch_filter_pt<2>(ctx, KS, L, nblocks, stream);
-    case 3: return launch_filter_pt<3>(ctx, KS, L, nblocks, stream);
-    case 4: return launch_filter_pt<4>(ctx, KS, L, nblocks, stream);
-    case 5: return launch_filter_pt<5>(ctx, KS, L, nblocks, stream);
-    case 7: return launch_filter_pt<7>(ctx, KS, L, nblocks, stream);
-    case 8: return launch_filter_pt<8>(ctx, KS, L, nblocks, stream);
-    case 10: return launch_filter_pt<10>(ctx, KS, L, nblocks, stream);
-    case 13: return launch_filter_pt<13>(ctx, KS, L, nblocks, stream);
-    case 16: return launch_filter_pt<16>(ctx, KS, L, nblocks, stream);
-    case 19: return launch_filter_pt<19>(ctx, KS, L, nblocks, stream);
-    case 26: return launch_filter_pt<26>(ctx, KS, L, nblocks, stream);
-    case 32: return launch_filter_pt<32>(ctx, KS, L, nblocks, stream);
+    case 1: return launch_filter_pt<1>(ctx, KS, L, nblocks, split, stream);
+    case 2: return launch_filter_pt<2>(ctx, KS, L, nblocks, split, stream);
+    case 3: return launch_filter_pt<3>(ctx, KS, L, nblocks, split, stream);
+    case 4: return launch_filter_pt<4>(ctx, KS, L, nblocks, split, stream);
+    case 5: return launch_filter_pt<5>(ctx, KS, L, nblocks, split, stream);
+    case 7: return launch_filter_pt<7>(ctx, KS, L, nblocks, split, stream);
+    case 8: return launch_filter_pt<8>(ctx, KS, L, nblocks, split, stream);
+    case 10: return launch_filter_pt<10>(ctx, KS, L, nblocks, split, stream);
+    case 13: return launch_filter_pt<13>(ctx, KS, L, nblocks, split, stream);
+    case 16: return launch_filter_pt<16>(ctx, KS, L, nblocks, split, stream);
+    case 19: return launch_filter_pt<19>(ctx, KS, L, nblocks, split, stream);
+    case 26: return launch_filter_pt<26>(ctx, KS, L, nblocks, split, stream);
+    case 32: return launch_filter_pt<32>(ctx, KS, L, nblocks, split, stream);
     default: return set_status(ctx, RPCA_ERR_UNSUPPORTED, "filter: p class not built");
     }
 }

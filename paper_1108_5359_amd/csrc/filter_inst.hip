@@ -8,5 +8,5 @@
 #endif
 
 namespace filterk {
-template int launch_filter_pt<RPCA_PT>(rpca_ctx *, int, const FilterLaunch &, int, hipStream_t);
+template int launch_filter_pt<RPCA_PT>(rpca_ctx *, int, const FilterLaunch &, int, bool, hipStream_t);
 }

@@ -349,6 +349,270 @@ l1_filter_kernel(FilterLaunch L)
     }
 }
 
+// ---------------------------------------------------------------------------
+// Split form (FP32): one 16-regression tile per workgroup.  The PT 16-element
+// tiles of the tile are dealt to the four waves (wave part w takes tiles
+// [w PT / 4, (w + 1) PT / 4), the part rotated with the tile so that the
+// heavier parts spread over the SIMDs); each wave keeps its slice of both
+// basis fragments, of x and of the state u, y in VGPRs, contracts its slice
+// and publishes its partial w = A^T g in LDS.  After one barrier every wave
+// sums the four partials in part order, so all waves hold the identical w and
+// z, and a regression's result does not depend on the tile it sits in.  The residual of step k is published with the partials of step
+// k + 1, so the stopping test of a step is taken one step later (the state
+// it reads is not changed by that delay: a stopped regression only stops
+// moving z and u).  Used where a launch has too few tiles to give every SIMD
+// the same number of tile waves: there each SIMD gets about a quarter of the
+// contraction work of each tile in flight instead of all of it.
+// ---------------------------------------------------------------------------
+// Classes with a split kernel: PT >= 4 (below, a quarter of a tile is too
+// little work per step for the exchange), and the state kept per lane (both
+// fragments, x, u, y for PTW tiles; z and the two w partials) within 176 VGPRs
+// so that two waves fit per SIMD.
+constexpr bool split_built(int PT, int KS)
+{
+    const int RT = (KS + 3) / 4, PTW = (PT + kWavesPerBlock - 1) / kWavesPerBlock;
+    return PT >= 4 && 2 * PTW * RT * 4 + 3 * PTW * 4 + 4 * RT * 4 <= 176;
+}
+
+template <int PT, int KS>
+struct SplitShape {
+    static constexpr int RT = (KS + 3) / 4;
+    static constexpr int PTW = (PT + kWavesPerBlock - 1) / kWavesPerBlock;   // tiles of the heaviest part
+    static constexpr int NV = RT * 4 + 1;         // floats a lane publishes per step: w partial, residual
+};
+
+template <int PT, int KS>
+__global__ void __launch_bounds__(kWavesPerBlock * 64)
+__attribute__((amdgpu_waves_per_eu(2)))
+l1_filter_split_kernel(FilterLaunch L)
+{
+    using Sh = SplitShape<PT, KS>;
+    constexpr int RT = Sh::RT, PTW = Sh::PTW, NV = Sh::NV;
+    __shared__ float xch[2][kWavesPerBlock][NV][64];
+
+    const bool second = (int)blockIdx.x >= L.nblocks0;
+#define SIDE(f) (second ? L.side[1].f : L.side[0].f)
+    const int64_t tile = second ? (int)blockIdx.x - L.nblocks0 : (int)blockIdx.x;
+    const int p = SIDE(p), r = SIDE(r);
+    const double *__restrict__ A = SIDE(A);
+    const int lda = SIDE(lda);
+    const int64_t *__restrict__ elem_idx = SIDE(elem_idx);
+    const int64_t *__restrict__ reg_idx = SIDE(reg_idx);
+    const int64_t elem_stride = SIDE(elem_stride), reg_stride = SIDE(reg_stride);
+    const int64_t elem_bound = SIDE(elem_bound), reg_bound = SIDE(reg_bound);
+    const int64_t nreg = SIDE(nreg);
+    const float *__restrict__ M = SIDE(M);
+    float *__restrict__ Zout = SIDE(Z);
+    const int64_t ldz = SIDE(ldz);
+    int32_t *__restrict__ iters = SIDE(iters);
+    const int64_t *range = SIDE(range);
+#undef SIDE
+    int64_t jbeg = 0, jend = nreg;
+    if (range) {
+        jbeg = range[0];
+        jend = range[1];
+    }
+    if (jbeg + tile * 16 >= jend) return;           // the whole block is idle (before any barrier)
+
+    const int wave = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63;
+    const int g = lane >> 4, c = lane & 15;
+    const int rot = (int)(tile & 3);
+    const int part = (wave + rot) & 3;                       // wave of part pp: (pp - rot) & 3
+    const int t0 = part * PT / kWavesPerBlock;
+    const int cnt = (part + 1) * PT / kWavesPerBlock - t0;   // wave-uniform, 1 <= cnt <= PTW
+    const int64_t j = jbeg + tile * 16 + c;
+    bool valid = j < jend;
+    int64_t roff = 0;
+    if (valid) {
+        const int64_t ri = reg_idx[j];
+        if (ri >= 0 && ri < reg_bound) roff = ri * reg_stride;
+        else valid = false;
+    }
+
+    // ---- this wave's slice of the basis (FP64 -> FP32), x and the state ----
+    floatx4 a1[PTW][RT], a2[PTW][RT];
+    float x[PTW][4], u[PTW][4], y[PTW][4];
+    float xinf = 0.0f, xx = 0.0f;
+#pragma unroll
+    for (int s = 0; s < PTW; ++s) {
+        const int t = t0 + s;
+        const bool on = s < cnt;
+#pragma unroll
+        for (int mt = 0; mt < RT; ++mt)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int e1 = 16 * t + 4 * g + v, k1 = 16 * mt + 4 * (c & 3) + (c >> 2);
+                a1[s][mt][v] = (on && e1 < p && k1 < r) ? (float)A[e1 + (int64_t)k1 * lda] : 0.0f;
+                const int e2 = 16 * t + c, k2 = 16 * mt + 4 * v + g;
+                a2[s][mt][v] = (on && e2 < p && k2 < r) ? (float)A[e2 + (int64_t)k2 * lda] : 0.0f;
+            }
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int e = 16 * t + 4 * g + v;
+            float xv = 0.0f;
+            if (valid && on && e < p) {
+                const int64_t ei = elem_idx[e];
+                if (ei >= 0 && ei < elem_bound) xv = M[roff + ei * elem_stride];
+            }
+            x[s][v] = xv;
+            u[s][v] = xv;
+            y[s][v] = 0.0f;
+            xinf = fmaxf(xinf, fabsf(xv));
+            xx = fmaf(xv, xv, xx);
+        }
+    }
+    // norms of x over the four parts, summed in part order: the same value in
+    // every wave, and the same for a regression wherever it sits
+    xch[0][wave][0][lane] = xinf;
+    xch[0][wave][1][lane] = xx;
+    __syncthreads();
+    xinf = 0.0f;
+    xx = 0.0f;
+#pragma unroll
+    for (int pp = 0; pp < kWavesPerBlock; ++pp) {
+        const int w = (pp - rot) & 3;
+        xinf = fmaxf(xinf, xch[0][w][0][lane]);
+        xx += xch[0][w][1][lane];
+    }
+    xinf = colmax(xinf);
+    xx = colsum(xx);
+
+    float beta = xx > 0.0f ? L.c.beta0_scale / sqrtf(xx) : 1.0f;
+    const float beta_bar = L.c.beta_max_scale * beta;
+    const float tol = L.c.eps * xinf;
+    bool done = !(valid && xinf > 0.0f);
+    int K = 0;
+    float inv_beta_prev = 0.0f, res_part = 0.0f;
+    floatx4 z[RT];
+#pragma unroll
+    for (int mt = 0; mt < RT; ++mt) z[mt] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
+
+    // buffer 0 was read above; the first step writes buffer 1
+    for (int k = 0;; ++k) {
+        const bool last = k >= L.c.max_iter;               // only the pending test is left
+        floatx4 Wa[RT], Wb[RT];
+#pragma unroll
+        for (int mt = 0; mt < RT; ++mt) {
+            Wa[mt] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
+            Wb[mt] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
+        }
+        if (!last) {
+#pragma unroll
+            for (int s = 0; s < PTW; ++s) {
+                if (s < cnt) {
+                    float gv[4];
+#pragma unroll
+                    for (int v = 0; v < 4; ++v)
+                        gv[v] = __builtin_amdgcn_fmed3f(fmaf(beta, u[s][v], y[s][v]), -1.0f, 1.0f);
+#pragma unroll
+                    for (int mt = 0; mt < RT; ++mt)
+#pragma unroll
+                        for (int v = 0; v < 4; ++v) {
+                            if (s & 1) Wb[mt] = mfma4(a1[s][mt][v], gv[v], Wb[mt]);
+                            else Wa[mt] = mfma4(a1[s][mt][v], gv[v], Wa[mt]);
+                        }
+                }
+            }
+        }
+        const int buf = (k + 1) & 1;
+#pragma unroll
+        for (int mt = 0; mt < RT; ++mt)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) xch[buf][wave][4 * mt + v][lane] = Wa[mt][v] + Wb[mt][v];
+        xch[buf][wave][4 * RT][lane] = res_part;
+        __syncthreads();
+        // w = sum of the partials in part order
+        floatx4 W[RT];
+        float res = 0.0f;
+        {
+            const int w0 = (0 - rot) & 3;
+#pragma unroll
+            for (int mt = 0; mt < RT; ++mt)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) W[mt][v] = xch[buf][w0][4 * mt + v][lane];
+        }
+#pragma unroll
+        for (int pp = 1; pp < kWavesPerBlock; ++pp) {
+            const int w = (pp - rot) & 3;
+#pragma unroll
+            for (int mt = 0; mt < RT; ++mt)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) W[mt][v] += xch[buf][w][4 * mt + v][lane];
+        }
+#pragma unroll
+        for (int w = 0; w < kWavesPerBlock; ++w) res = fmaxf(res, xch[buf][w][4 * RT][lane]);
+        res = colmax(res);
+        // the stopping test of step k - 1
+        if (k > 0 && !done) {
+            ++K;
+            if (!(res * inv_beta_prev >= tol)) done = true;
+        }
+        if (last || !__any(!done)) break;                 // the same in every wave of the block
+
+        const float inv_beta = 1.0f / beta;
+        const float ib = done ? 0.0f : inv_beta;
+#pragma unroll
+        for (int mt = 0; mt < RT; ++mt)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) z[mt][v] = fmaf(W[mt][v], ib, z[mt][v]);
+
+        res_part = 0.0f;
+#pragma unroll
+        for (int s = 0; s < PTW; ++s) {
+            if (s < cnt) {
+                floatx4 V = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+                for (int mt = 0; mt < RT; ++mt)
+#pragma unroll
+                    for (int v = 0; v < 4; ++v)
+                        if (4 * mt + v < KS) V = mfma4(a2[s][mt][v], W[mt][v], V);
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const float gg = __builtin_amdgcn_fmed3f(fmaf(beta, u[s][v], y[s][v]), -1.0f, 1.0f);
+                    const float yn = gg - V[v];
+                    res_part = fmaxf(res_part, fabsf(yn - y[s][v]));
+                    u[s][v] = fmaf(-V[v], ib, u[s][v]);
+                    y[s][v] = yn;
+                }
+            }
+        }
+        inv_beta_prev = inv_beta;
+        beta = fminf(L.c.rho * beta, beta_bar);
+
+        if (L.c.refresh > 0 && ((k + 1) % L.c.refresh) == 0) {
+#pragma unroll
+            for (int s = 0; s < PTW; ++s) {
+                if (s < cnt) {
+                    floatx4 Az = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+                    for (int mt = 0; mt < RT; ++mt)
+#pragma unroll
+                        for (int v = 0; v < 4; ++v)
+                            if (4 * mt + v < KS) Az = mfma4(a2[s][mt][v], z[mt][v], Az);
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) u[s][v] = x[s][v] - Az[v];
+                }
+            }
+        }
+    }
+
+    // every wave holds the same z: wave 0 writes it
+    if (wave == 0 && j < jend) {
+        if (valid) {
+#pragma unroll
+            for (int mt = 0; mt < RT; ++mt)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int kk = 16 * mt + 4 * v + g;
+                    if (kk < r) Zout[kk + j * ldz] = z[mt][v];
+                }
+        }
+        if (iters && g == 0)
+            iters[j] = !valid ? INT_MIN : (done ? K : -L.c.max_iter);
+    }
+}
+
 
 // ---------------------------------------------------------------------------
 // Precision form: the two contractions on v_mfma_f32_16x16x32_f16 (FP16
@@ -654,8 +918,17 @@ static __global__ void prep_frag32(const double *__restrict__ A, int lda, int p,
 }
 
 template <int PT, int KS>
-int launch_pt_ks(rpca_ctx *ctx, const FilterLaunch &L, int nblocks, hipStream_t stream)
+int launch_pt_ks(rpca_ctx *ctx, const FilterLaunch &L, int nblocks, bool split, hipStream_t stream)
 {
+    if constexpr (split_built(PT, KS)) {
+        if (split && L.c.precision == 0) {
+            hipLaunchKernelGGL((l1_filter_split_kernel<PT, KS>), dim3(nblocks), dim3(kWavesPerBlock * 64),
+                               0, stream, L);
+            RPCA_HIP_TRY(ctx, hipGetLastError());
+            return RPCA_OK;
+        }
+    }
+    if (split) return set_status(ctx, RPCA_ERR_UNSUPPORTED, "filter: split form not built for this class");
     if (L.c.precision == 1) {
         // the FP32 refresh fragments live in HBM when the launcher prepared them
         const size_t lds = lds_bytes_f16(PT, KS, L.frag32[0] == nullptr);
@@ -693,19 +966,20 @@ int launch_pt_ks(rpca_ctx *ctx, const FilterLaunch &L, int nblocks, hipStream_t 
 
 // Launch the class (PT, KS); defined in filter_inst.hip, one object per PT.
 template <int PT>
-int launch_filter_pt(rpca_ctx *ctx, int KS, const FilterLaunch &L, int nblocks, hipStream_t stream)
+int launch_filter_pt(rpca_ctx *ctx, int KS, const FilterLaunch &L, int nblocks, bool split,
+                     hipStream_t stream)
 {
     switch (KS) {
-    case 1: return launch_pt_ks<PT, 1>(ctx, L, nblocks, stream);
-    case 2: return launch_pt_ks<PT, 2>(ctx, L, nblocks, stream);
-    case 3: return launch_pt_ks<PT, 3>(ctx, L, nblocks, stream);
-    case 4: return launch_pt_ks<PT, 4>(ctx, L, nblocks, stream);
-    case 5: return launch_pt_ks<PT, 5>(ctx, L, nblocks, stream);
-    case 6: return launch_pt_ks<PT, 6>(ctx, L, nblocks, stream);
-    case 8: return launch_pt_ks<PT, 8>(ctx, L, nblocks, stream);
-    case 10: return launch_pt_ks<PT, 10>(ctx, L, nblocks, stream);
-    case 13: return launch_pt_ks<PT, 13>(ctx, L, nblocks, stream);
-    case 16: return launch_pt_ks<PT, 16>(ctx, L, nblocks, stream);
+    case 1: return launch_pt_ks<PT, 1>(ctx, L, nblocks, split, stream);
+    case 2: return launch_pt_ks<PT, 2>(ctx, L, nblocks, split, stream);
+    case 3: return launch_pt_ks<PT, 3>(ctx, L, nblocks, split, stream);
+    case 4: return launch_pt_ks<PT, 4>(ctx, L, nblocks, split, stream);
+    case 5: return launch_pt_ks<PT, 5>(ctx, L, nblocks, split, stream);
+    case 6: return launch_pt_ks<PT, 6>(ctx, L, nblocks, split, stream);
+    case 8: return launch_pt_ks<PT, 8>(ctx, L, nblocks, split, stream);
+    case 10: return launch_pt_ks<PT, 10>(ctx, L, nblocks, split, stream);
+    case 13: return launch_pt_ks<PT, 13>(ctx, L, nblocks, split, stream);
+    case 16: return launch_pt_ks<PT, 16>(ctx, L, nblocks, split, stream);
     default: return set_status(ctx, RPCA_ERR_UNSUPPORTED, "filter: rank class not built");
     }
 }

@@ -83,6 +83,11 @@ struct FilterConsts {
     float eps, rho, beta0_scale, beta_max_scale;
     int32_t max_iter, refresh;
     int32_t precision;    // 0 = FP32 contractions, 1 = FP16 contractions + FP32 refinement
+    int32_t form;         // FP32 kernels: 0 = automatic, 1 = tile form, 2 = split form
+    int64_t plan_regs;    // regressions of the whole call the launch belongs to (0 = the
+                          // launch's own): the automatic form choice is made on this count,
+                          // so a call cut into several launches picks the form the single
+                          // launch would
 };
 
 // Enqueue the regressions of up to two sides (same p class and r class) in
@@ -92,6 +97,10 @@ int launch_filter(rpca_ctx *ctx, const FilterSide *sides, int nsides, const Filt
 
 // Whether launch_filter supports (p, r) in the given precision mode.
 bool filter_supported(rpca_ctx *ctx, int p, int r, int precision);
+
+// The kernel form launch_filter takes for `regs` regressions of size (p, r):
+// 0 = FP16 contractions (precision form), 1 = FP32 tile form, 2 = FP32 split form.
+int filter_form_of(rpca_ctx *ctx, int p, int r, int precision, int form, int64_t regs);
 
 // Whether two (p, r) pairs use the same kernel and can share one launch.
 bool filter_same_class(int p0, int r0, int p1, int r1);

@@ -44,7 +44,7 @@ class rpca_opts(ctypes.Structure):
         ("filt_beta0_scale", ctypes.c_double), ("filt_beta_max_scale", ctypes.c_double),
         ("filt_max_iter", ctypes.c_int32), ("filt_refresh", ctypes.c_int32),
         ("rng_seed", ctypes.c_uint64), ("precision", ctypes.c_int32),
-        ("overlap_chunks", ctypes.c_int32),
+        ("overlap_chunks", ctypes.c_int32), ("filter_form", ctypes.c_int32),
     ]
 
 
@@ -74,6 +74,7 @@ lib.rpca_last_error.restype = ctypes.c_char_p
 lib.rpca_status_string.argtypes = [ctypes.c_int]
 lib.rpca_status_string.restype = ctypes.c_char_p
 lib.rpca_sample_indices.argtypes = [_i64, _i64, _i64, _i64, ctypes.c_uint64, _vp, _vp]
+lib.rpca_filter_form.argtypes = [_vp, _i64, _i32, _i64, ctypes.POINTER(rpca_opts), ctypes.POINTER(_i32)]
 lib.rpca_seed.argtypes = [_vp, _vp, _i64, _i64, _i64, _vp, _i64, _vp, _i64, _i32,
                           ctypes.POINTER(rpca_opts), _vp, _vp, _vp,
                           ctypes.POINTER(_i32), ctypes.POINTER(_i32)]
@@ -183,6 +184,13 @@ def rpca_seed(ctx: Context, M, m, n, ldm, seed_rows, p, seed_cols, q, r, opts, U
                                  _ptr(seed_cols), q, r, ctypes.byref(opts), _ptr(U), _ptr(sigma),
                                  _ptr(V), ctypes.byref(ru), ctypes.byref(it)))
     return st, ru.value, it.value
+
+
+def rpca_filter_form(ctx: Context, p: int, r: int, nreg: int, opts) -> int:
+    """The filter kernel form a call takes: 0 FP16 precision form, 1 FP32 tile, 2 FP32 split."""
+    f = _i32(0)
+    ctx.check(lib.rpca_filter_form(ctx.handle, p, r, nreg, ctypes.byref(opts), ctypes.byref(f)))
+    return f.value
 
 
 def rpca_filter_cols(ctx: Context, M, m, n, ldm, seed_rows, p, cols, nc, U, r, opts, Qt, iters,
