@@ -405,7 +405,8 @@ batch_assemble(const ReconJob *__restrict__ jobs, const int32_t *__restrict__ bl
 {
     __shared__ int64_t sidx[reconk::kIdxLds];
     const ReconJob &J = jobs[block_job[blockIdx.x]];
-    reconk::assemble_block(block_first[blockIdx.x], J.m + J.n, sidx, J.seed_rows, J.p, J.seed_cols, J.q, J.U,
+    reconk::assemble_block(block_first[blockIdx.x], (J.m + J.n) * (J.R4 / 4), sidx, J.seed_rows, J.p,
+                           J.seed_cols, J.q, J.U,
                            J.sigma, J.V, J.r, J.Qt, J.Pt, J.m, J.n, J.R4,
                            const_cast<float *>(J.F), const_cast<float *>(J.G));
 }

@@ -217,7 +217,9 @@ int build_tables(rpca_batch *b)
                      ((uintptr_t)J.S % 16 == 0);
             const int64_t cpw = std::max<int32_t>(1, b->tun.recon_cols_per_wave);
             rj.row_blocks = (uint32_t)((J.m + 255) / 256);
-            rj.col_parts = (uint32_t)std::max<int64_t>(1, std::min<int64_t>(J.n, (J.n + cpw - 1) / cpw));
+            // waves per row block: one per recon_cols_per_wave columns, at most one
+            // per batch of 4 columns (the unit a completion wave takes)
+            rj.col_parts = (uint32_t)std::max<int64_t>(1, std::min<int64_t>((J.n + 3) / 4, (J.n + cpw - 1) / cpw));
             rjobs.push_back(rj);
         } else {
             b->single_recon.push_back(a);
@@ -249,8 +251,8 @@ int build_tables(rpca_batch *b)
     std::vector<uint32_t> rec_local;
     for (size_t k = 0; k < rjobs.size(); ++k) {
         const ReconJob &rj = rjobs[k];
-        const int64_t threads = rj.m + rj.n;
-        for (int64_t f = 0; f < threads; f += 256) {
+        const int64_t units = (rj.m + rj.n) * (rj.R4 / 4);   // one row, 4 ranks each
+        for (int64_t f = 0; f < units; f += 256) {
             asm_job.push_back((int32_t)k);
             asm_first.push_back(f);
         }

@@ -37,6 +37,7 @@
 #include "rpca_internal.h"
 
 #include <climits>
+#include <type_traits>
 
 namespace filterk {
 
@@ -379,16 +380,21 @@ struct SplitShape {
     static constexpr int RT = (KS + 3) / 4;
     static constexpr int PTW = (PT + kWavesPerBlock - 1) / kWavesPerBlock;   // tiles of the heaviest part
     static constexpr int NV = RT * 4 + 1;         // floats a lane publishes per step: w partial, residual
+    // three waves per SIMD (168 VGPRs) where the loop fits them without
+    // spilling (checked at build time for every class), else two
+    static constexpr int kWavesPerEU = (KS <= 5 && PTW <= 4) ? 3 : 2;
 };
 
 template <int PT, int KS>
 __global__ void __launch_bounds__(kWavesPerBlock * 64)
-__attribute__((amdgpu_waves_per_eu(2)))
+__attribute__((amdgpu_waves_per_eu(SplitShape<PT, KS>::kWavesPerEU)))
 l1_filter_split_kernel(FilterLaunch L)
 {
     using Sh = SplitShape<PT, KS>;
     constexpr int RT = Sh::RT, PTW = Sh::PTW, NV = Sh::NV;
     __shared__ float xch[2][kWavesPerBlock][NV][64];
+    // x of each wave's slice, read back by the refresh (LDS instead of VGPRs)
+    __shared__ floatx4 xs[kWavesPerBlock][PTW][64];
 
     const bool second = (int)blockIdx.x >= L.nblocks0;
 #define SIDE(f) (second ? L.side[1].f : L.side[0].f)
@@ -414,7 +420,10 @@ l1_filter_split_kernel(FilterLaunch L)
     }
     if (jbeg + tile * 16 >= jend) return;           // the whole block is idle (before any barrier)
 
-    const int wave = threadIdx.x >> 6;
+    // the wave index through readfirstlane: the compiler then knows every
+    // quantity derived from it (part, slice, slot count) is wave-uniform and
+    // branches on it with scalar branches instead of exec masks
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const int lane = threadIdx.x & 63;
     const int g = lane >> 4, c = lane & 15;
     const int rot = (int)(tile & 3);
@@ -432,7 +441,7 @@ l1_filter_split_kernel(FilterLaunch L)
 
     // ---- this wave's slice of the basis (FP64 -> FP32), x and the state ----
     floatx4 a1[PTW][RT], a2[PTW][RT];
-    float x[PTW][4], u[PTW][4], y[PTW][4];
+    float u[PTW][4], y[PTW][4];
     float xinf = 0.0f, xx = 0.0f;
 #pragma unroll
     for (int s = 0; s < PTW; ++s) {
@@ -455,7 +464,7 @@ l1_filter_split_kernel(FilterLaunch L)
                 const int64_t ei = elem_idx[e];
                 if (ei >= 0 && ei < elem_bound) xv = M[roff + ei * elem_stride];
             }
-            x[s][v] = xv;
+            xs[wave][s][lane][v] = xv;
             u[s][v] = xv;
             y[s][v] = 0.0f;
             xinf = fmaxf(xinf, fabsf(xv));
@@ -488,113 +497,148 @@ l1_filter_split_kernel(FilterLaunch L)
 #pragma unroll
     for (int mt = 0; mt < RT; ++mt) z[mt] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
 
-    // buffer 0 was read above; the first step writes buffer 1
-    for (int k = 0;; ++k) {
-        const bool last = k >= L.c.max_iter;               // only the pending test is left
-        floatx4 Wa[RT], Wb[RT];
+    // The step loop, for a compile-time number NC of element tiles: no branch
+    // per tile, so the MFMA chains of all the wave's tiles run back to back
+    // (a branch per tile would end a basic block after each and wait out the
+    // MFMA latency to move the accumulators).  Buffer 0 was read above; the
+    // first step writes buffer 1.
+    auto sweep = [&](auto nc_tag) {
+        constexpr int NC = decltype(nc_tag)::value;
+        for (int k = 0;; ++k) {
+            // after max_iter steps only the pending stopping test is left (the
+            // partial w of that pass is computed but not used)
+            const bool last = k >= L.c.max_iter;
+            floatx4 Wa[RT], Wb[RT];
 #pragma unroll
-        for (int mt = 0; mt < RT; ++mt) {
-            Wa[mt] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
-            Wb[mt] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
-        }
-        if (!last) {
-#pragma unroll
-            for (int s = 0; s < PTW; ++s) {
-                if (s < cnt) {
-                    float gv[4];
-#pragma unroll
-                    for (int v = 0; v < 4; ++v)
-                        gv[v] = __builtin_amdgcn_fmed3f(fmaf(beta, u[s][v], y[s][v]), -1.0f, 1.0f);
-#pragma unroll
-                    for (int mt = 0; mt < RT; ++mt)
-#pragma unroll
-                        for (int v = 0; v < 4; ++v) {
-                            if (s & 1) Wb[mt] = mfma4(a1[s][mt][v], gv[v], Wb[mt]);
-                            else Wa[mt] = mfma4(a1[s][mt][v], gv[v], Wa[mt]);
-                        }
-                }
+            for (int mt = 0; mt < RT; ++mt) {
+                Wa[mt] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
+                Wb[mt] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
             }
-        }
-        const int buf = (k + 1) & 1;
 #pragma unroll
-        for (int mt = 0; mt < RT; ++mt)
+            for (int s = 0; s < NC; ++s) {
+                float gv[4];
 #pragma unroll
-            for (int v = 0; v < 4; ++v) xch[buf][wave][4 * mt + v][lane] = Wa[mt][v] + Wb[mt][v];
-        xch[buf][wave][4 * RT][lane] = res_part;
-        __syncthreads();
-        // w = sum of the partials in part order
-        floatx4 W[RT];
-        float res = 0.0f;
-        {
-            const int w0 = (0 - rot) & 3;
+                for (int v = 0; v < 4; ++v)
+                    gv[v] = __builtin_amdgcn_fmed3f(fmaf(beta, u[s][v], y[s][v]), -1.0f, 1.0f);
 #pragma unroll
-            for (int mt = 0; mt < RT; ++mt)
+                for (int mt = 0; mt < RT; ++mt)
 #pragma unroll
-                for (int v = 0; v < 4; ++v) W[mt][v] = xch[buf][w0][4 * mt + v][lane];
-        }
-#pragma unroll
-        for (int pp = 1; pp < kWavesPerBlock; ++pp) {
-            const int w = (pp - rot) & 3;
+                    for (int v = 0; v < 4; ++v) {
+                        if (s & 1) Wb[mt] = mfma4(a1[s][mt][v], gv[v], Wb[mt]);
+                        else Wa[mt] = mfma4(a1[s][mt][v], gv[v], Wa[mt]);
+                    }
+            }
+            const int buf = (k + 1) & 1;
 #pragma unroll
             for (int mt = 0; mt < RT; ++mt)
 #pragma unroll
-                for (int v = 0; v < 4; ++v) W[mt][v] += xch[buf][w][4 * mt + v][lane];
-        }
+                for (int v = 0; v < 4; ++v) xch[buf][wave][4 * mt + v][lane] = Wa[mt][v] + Wb[mt][v];
+            xch[buf][wave][4 * RT][lane] = res_part;
+            __syncthreads();
+            // w = sum of the partials in part order
+            floatx4 W[RT];
+            float res = 0.0f;
+            {
+                const int w0 = (0 - rot) & 3;
 #pragma unroll
-        for (int w = 0; w < kWavesPerBlock; ++w) res = fmaxf(res, xch[buf][w][4 * RT][lane]);
-        res = colmax(res);
-        // the stopping test of step k - 1
-        if (k > 0 && !done) {
-            ++K;
-            if (!(res * inv_beta_prev >= tol)) done = true;
-        }
-        if (last || !__any(!done)) break;                 // the same in every wave of the block
+                for (int mt = 0; mt < RT; ++mt)
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) W[mt][v] = xch[buf][w0][4 * mt + v][lane];
+            }
+#pragma unroll
+            for (int pp = 1; pp < kWavesPerBlock; ++pp) {
+                const int w = (pp - rot) & 3;
+#pragma unroll
+                for (int mt = 0; mt < RT; ++mt)
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) W[mt][v] += xch[buf][w][4 * mt + v][lane];
+            }
+#pragma unroll
+            for (int w = 0; w < kWavesPerBlock; ++w) res = fmaxf(res, xch[buf][w][4 * RT][lane]);
+            res = colmax(res);
+            // the stopping test of step k - 1
+            if (k > 0 && !done) {
+                ++K;
+                if (!(res * inv_beta_prev >= tol)) done = true;
+            }
+            if (last || !__any(!done)) break;                 // the same in every wave of the block
 
-        const float inv_beta = 1.0f / beta;
-        const float ib = done ? 0.0f : inv_beta;
+            const float inv_beta = 1.0f / beta;
+            const float ib = done ? 0.0f : inv_beta;
 #pragma unroll
-        for (int mt = 0; mt < RT; ++mt)
+            for (int mt = 0; mt < RT; ++mt)
 #pragma unroll
-            for (int v = 0; v < 4; ++v) z[mt][v] = fmaf(W[mt][v], ib, z[mt][v]);
+                for (int v = 0; v < 4; ++v) z[mt][v] = fmaf(W[mt][v], ib, z[mt][v]);
 
-        res_part = 0.0f;
+            // v = A w for two tiles at a time (K-step outer: two interleaved
+            // chains), then their dual / residual update
+            res_part = 0.0f;
 #pragma unroll
-        for (int s = 0; s < PTW; ++s) {
-            if (s < cnt) {
-                floatx4 V = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
+            for (int s0 = 0; s0 < NC; s0 += 2) {
+                constexpr int kPair = 2;
+                floatx4 V[kPair];
+#pragma unroll
+                for (int h = 0; h < kPair; ++h) V[h] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
                 for (int mt = 0; mt < RT; ++mt)
 #pragma unroll
                     for (int v = 0; v < 4; ++v)
-                        if (4 * mt + v < KS) V = mfma4(a2[s][mt][v], W[mt][v], V);
+                        if (4 * mt + v < KS)
 #pragma unroll
-                for (int v = 0; v < 4; ++v) {
-                    const float gg = __builtin_amdgcn_fmed3f(fmaf(beta, u[s][v], y[s][v]), -1.0f, 1.0f);
-                    const float yn = gg - V[v];
-                    res_part = fmaxf(res_part, fabsf(yn - y[s][v]));
-                    u[s][v] = fmaf(-V[v], ib, u[s][v]);
-                    y[s][v] = yn;
+                            for (int h = 0; h < kPair; ++h)
+                                if (s0 + h < NC) V[h] = mfma4(a2[s0 + h][mt][v], W[mt][v], V[h]);
+#pragma unroll
+                for (int h = 0; h < kPair; ++h) {
+                    const int s = s0 + h;
+                    if (s < NC) {
+#pragma unroll
+                        for (int v = 0; v < 4; ++v) {
+                            // g again from the unchanged u, y (cheaper than keeping it)
+                            const float gg =
+                                __builtin_amdgcn_fmed3f(fmaf(beta, u[s][v], y[s][v]), -1.0f, 1.0f);
+                            const float yn = gg - V[h][v];
+                            res_part = fmaxf(res_part, fabsf(yn - y[s][v]));
+                            u[s][v] = fmaf(-V[h][v], ib, u[s][v]);
+                            y[s][v] = yn;
+                        }
+                    }
                 }
             }
-        }
-        inv_beta_prev = inv_beta;
-        beta = fminf(L.c.rho * beta, beta_bar);
+            inv_beta_prev = inv_beta;
+            beta = fminf(L.c.rho * beta, beta_bar);
 
-        if (L.c.refresh > 0 && ((k + 1) % L.c.refresh) == 0) {
+            if (L.c.refresh > 0 && ((k + 1) % L.c.refresh) == 0) {
 #pragma unroll
-            for (int s = 0; s < PTW; ++s) {
-                if (s < cnt) {
-                    floatx4 Az = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
+                for (int s0 = 0; s0 < NC; s0 += 2) {
+                    floatx4 Az[2];
+#pragma unroll
+                    for (int h = 0; h < 2; ++h) Az[h] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
                     for (int mt = 0; mt < RT; ++mt)
 #pragma unroll
                         for (int v = 0; v < 4; ++v)
-                            if (4 * mt + v < KS) Az = mfma4(a2[s][mt][v], z[mt][v], Az);
+                            if (4 * mt + v < KS)
 #pragma unroll
-                    for (int v = 0; v < 4; ++v) u[s][v] = x[s][v] - Az[v];
+                                for (int h = 0; h < 2; ++h)
+                                    if (s0 + h < NC) Az[h] = mfma4(a2[s0 + h][mt][v], z[mt][v], Az[h]);
+#pragma unroll
+                    for (int h = 0; h < 2; ++h) {
+                        if (s0 + h < NC) {
+                            const floatx4 xv = xs[wave][s0 + h][lane];
+#pragma unroll
+                            for (int v = 0; v < 4; ++v) u[s0 + h][v] = xv[v] - Az[h][v];
+                        }
+                    }
                 }
             }
         }
+    };
+    if constexpr (PT % kWavesPerBlock == 0) {
+        sweep(std::integral_constant<int, PTW>{});
+    } else {
+        // parts hold floor(PT / 4) or ceil(PT / 4) tiles
+        if (cnt == PTW) sweep(std::integral_constant<int, PTW>{});
+        else sweep(std::integral_constant<int, PTW - 1>{});
     }
 
     // every wave holds the same z: wave 0 writes it

@@ -36,8 +36,8 @@ template <int R4>
 int launch_r4(rpca_ctx *ctx, const ReconArgs &a, const float *F, const float *G, bool vec,
               hipStream_t stream)
 {
-    // ~recon_waves_per_cu waves per CU across the chip (32 measured best for
-    // this column-block pattern), at least 4 columns each
+    // ~recon_waves_per_cu waves per CU across the chip (32 measured best),
+    // at least one batch of 4 columns each
     const int64_t row_blocks = (a.m + kRowsPerWave - 1) / kRowsPerWave;
     const int64_t target_waves =
         (int64_t)(ctx->num_cu > 0 ? ctx->num_cu : 256) * ctx->recon_waves_per_cu;
@@ -72,9 +72,11 @@ int launch_reconstruct(rpca_ctx *ctx, const ReconArgs &a, hipStream_t stream)
 }
 
 int launch_assemble_range(rpca_ctx *ctx, const ReconArgs &a, int R4, float *F, float *G,
-                          int64_t first, int64_t end, hipStream_t stream)
+                          int64_t first_row, int64_t end_row, hipStream_t stream)
 {
-    if (end <= first) return RPCA_OK;
+    if (end_row <= first_row) return RPCA_OK;
+    // units of one row and 4 ranks
+    const int64_t first = first_row * (R4 / 4), end = end_row * (R4 / 4);
     hipLaunchKernelGGL(assemble_factors,
                        dim3((unsigned)((end - first + kAssembleThreads - 1) / kAssembleThreads)),
                        dim3(kAssembleThreads), 0, stream, first, end, a.seed_rows, a.p, a.seed_cols,

@@ -125,10 +125,10 @@ struct ReconArgs {
 int launch_reconstruct(rpca_ctx *ctx, const ReconArgs &a, hipStream_t stream);
 
 // Pieces of the completion for the overlapped form: assemble rows
-// [first, end) of the stacked factors (F rows are [0, m), G row j is m + j)
-// and complete the column slab [j0, j1) of L and S.
+// [first_row, end_row) of the stacked factors (F rows are [0, m), G row j is
+// m + j) and complete the column slab [j0, j1) of L and S.
 int launch_assemble_range(rpca_ctx *ctx, const ReconArgs &a, int R4, float *F, float *G,
-                          int64_t first, int64_t end, hipStream_t stream);
+                          int64_t first_row, int64_t end_row, hipStream_t stream);
 int launch_complete_slab(rpca_ctx *ctx, const ReconArgs &a, int R4, const float *F,
                          const float *G, int64_t j0, int64_t j1, hipStream_t stream);
 
