@@ -86,6 +86,14 @@ __device__ __forceinline__ floatx4 mfma4(float a, float b, floatx4 acc)
     return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc, 0, 0, 0);
 }
 
+// v_mfma_f32_4x4x1_16b_f32: 16 independent 4x4x1 blocks.  Lane 4 b + i
+// gives row i of block b's A operand, lane 4 b + j column j of its B
+// operand, and accumulator register i of lane 4 b + j is D_b[i][j].
+__device__ __forceinline__ floatx4 mfma4x4(float a, float b, floatx4 acc)
+{
+    return __builtin_amdgcn_mfma_f32_4x4x1f32(a, b, acc, 0, 0, 0);
+}
+
 __device__ __forceinline__ floatx4 mfma16h(halfx8 a, halfx8 b, floatx4 acc)
 {
     return __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, acc, 0, 0, 0);
@@ -379,7 +387,18 @@ template <int PT, int KS>
 struct SplitShape {
     static constexpr int RT = (KS + 3) / 4;
     static constexpr int PTW = (PT + kWavesPerBlock - 1) / kWavesPerBlock;   // tiles of the heaviest part
-    static constexpr int NV = RT * 4 + 1;         // floats a lane publishes per step: w partial, residual
+    // The last rank tile holds NQ = KS - 4 (RT - 1) quads of ranks.  When it
+    // holds one or two (NQ <= 2), its part of w = A^T g runs on
+    // v_mfma_f32_4x4x1_16b_f32 (a quarter of the cycles of a 16x16x4 per quad)
+    // instead of a padded 16x16x4 tile; with three the saving is small and the
+    // accumulators do not fit.  NCH independent chains per quad.
+    static constexpr int LT = RT - 1;
+    static constexpr int NQ = KS - 4 * LT;
+    static constexpr bool kQuad = NQ <= 2;
+    static constexpr int NCH = NQ == 1 ? 4 : 2;
+    static constexpr int FT = kQuad ? LT : RT;   // rank tiles of w on 16x16x4
+    // floats a lane publishes per step: w partials, residual
+    static constexpr int NV = 4 * FT + (kQuad ? 4 * NQ : 0) + 1;
     // three waves per SIMD (168 VGPRs) where the loop fits them without
     // spilling (checked at build time for every class), else two
     static constexpr int kWavesPerEU = (KS <= 5 && PTW <= 4) ? 3 : 2;
@@ -392,6 +411,10 @@ l1_filter_split_kernel(FilterLaunch L)
 {
     using Sh = SplitShape<PT, KS>;
     constexpr int RT = Sh::RT, PTW = Sh::PTW, NV = Sh::NV;
+    constexpr int LT = Sh::LT, NQ = Sh::NQ, FT = Sh::FT;
+    constexpr bool kQuad = Sh::kQuad;
+    constexpr int NQA = kQuad ? NQ : 1;          // array extent of the quad parts
+    constexpr int NCH = Sh::NCH;
     __shared__ float xch[2][kWavesPerBlock][NV][64];
     // x of each wave's slice, read back by the refresh (LDS instead of VGPRs)
     __shared__ floatx4 xs[kWavesPerBlock][PTW][64];
@@ -440,7 +463,11 @@ l1_filter_split_kernel(FilterLaunch L)
     }
 
     // ---- this wave's slice of the basis (FP64 -> FP32), x and the state ----
-    floatx4 a1[PTW][RT], a2[PTW][RT];
+    // a1: A operand of w = A^T g on 16x16x4 (rank tiles 0 .. FT-1);
+    // a1q: A operand on 4x4x1 for quad q of the last rank tile: lane (g, c) is
+    //      row c % 4 of block 4 g + c / 4, whose K-step is element 16 t + 4 g + v;
+    // a2: A operand of v = A w and of the refresh.
+    floatx4 a1[PTW][FT > 0 ? FT : 1], a1q[PTW][NQA], a2[PTW][RT];
     float u[PTW][4], y[PTW][4];
     float xinf = 0.0f, xx = 0.0f;
 #pragma unroll
@@ -451,11 +478,23 @@ l1_filter_split_kernel(FilterLaunch L)
         for (int mt = 0; mt < RT; ++mt)
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
-                const int e1 = 16 * t + 4 * g + v, k1 = 16 * mt + 4 * (c & 3) + (c >> 2);
-                a1[s][mt][v] = (on && e1 < p && k1 < r) ? (float)A[e1 + (int64_t)k1 * lda] : 0.0f;
+                const int e1 = 16 * t + 4 * g + v;
+                if (mt < FT) {
+                    const int k1 = 16 * mt + 4 * (c & 3) + (c >> 2);
+                    a1[s][mt][v] = (on && e1 < p && k1 < r) ? (float)A[e1 + (int64_t)k1 * lda] : 0.0f;
+                }
                 const int e2 = 16 * t + c, k2 = 16 * mt + 4 * v + g;
                 a2[s][mt][v] = (on && e2 < p && k2 < r) ? (float)A[e2 + (int64_t)k2 * lda] : 0.0f;
             }
+        if constexpr (kQuad) {
+#pragma unroll
+            for (int q = 0; q < NQ; ++q)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int e1 = 16 * t + 4 * g + v, k1 = 16 * LT + 4 * q + (c & 3);
+                    a1q[s][q][v] = (on && e1 < p && k1 < r) ? (float)A[e1 + (int64_t)k1 * lda] : 0.0f;
+                }
+        }
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
             const int e = 16 * t + 4 * g + v;
@@ -508,12 +547,17 @@ l1_filter_split_kernel(FilterLaunch L)
             // after max_iter steps only the pending stopping test is left (the
             // partial w of that pass is computed but not used)
             const bool last = k >= L.c.max_iter;
-            floatx4 Wa[RT], Wb[RT];
+            floatx4 Wa[FT > 0 ? FT : 1], Wb[FT > 0 ? FT : 1];
+            floatx4 Wq[NQA][NCH];                // quad part: NCH chains (by v)
 #pragma unroll
-            for (int mt = 0; mt < RT; ++mt) {
+            for (int mt = 0; mt < FT; ++mt) {
                 Wa[mt] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
                 Wb[mt] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
             }
+#pragma unroll
+            for (int q = 0; q < NQA; ++q)
+#pragma unroll
+                for (int h = 0; h < NCH; ++h) Wq[q][h] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
             for (int s = 0; s < NC; ++s) {
                 float gv[4];
@@ -521,40 +565,72 @@ l1_filter_split_kernel(FilterLaunch L)
                 for (int v = 0; v < 4; ++v)
                     gv[v] = __builtin_amdgcn_fmed3f(fmaf(beta, u[s][v], y[s][v]), -1.0f, 1.0f);
 #pragma unroll
-                for (int mt = 0; mt < RT; ++mt)
+                for (int mt = 0; mt < FT; ++mt)
 #pragma unroll
                     for (int v = 0; v < 4; ++v) {
                         if (s & 1) Wb[mt] = mfma4(a1[s][mt][v], gv[v], Wb[mt]);
                         else Wa[mt] = mfma4(a1[s][mt][v], gv[v], Wa[mt]);
                     }
+                if constexpr (kQuad) {
+#pragma unroll
+                    for (int q = 0; q < NQ; ++q)
+#pragma unroll
+                        for (int v = 0; v < 4; ++v)
+                            Wq[q][v % NCH] = mfma4x4(a1q[s][q][v], gv[v], Wq[q][v % NCH]);
+                }
             }
             const int buf = (k + 1) & 1;
 #pragma unroll
-            for (int mt = 0; mt < RT; ++mt)
+            for (int mt = 0; mt < FT; ++mt)
 #pragma unroll
                 for (int v = 0; v < 4; ++v) xch[buf][wave][4 * mt + v][lane] = Wa[mt][v] + Wb[mt][v];
-            xch[buf][wave][4 * RT][lane] = res_part;
+            if constexpr (kQuad) {
+                // lane (g, c) register i: ranks 16 LT + 4 q + i of regression c,
+                // summed over this lane's elements (rows 4 g .. 4 g + 3 of each tile)
+#pragma unroll
+                for (int q = 0; q < NQ; ++q) {
+                    floatx4 wq = Wq[q][0];
+#pragma unroll
+                    for (int h = 1; h < NCH; ++h) wq += Wq[q][h];
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) xch[buf][wave][4 * FT + 4 * q + i][lane] = wq[i];
+                }
+            }
+            xch[buf][wave][NV - 1][lane] = res_part;
             __syncthreads();
             // w = sum of the partials in part order
             floatx4 W[RT];
             float res = 0.0f;
             {
+                float ws[NV - 1];
                 const int w0 = (0 - rot) & 3;
 #pragma unroll
-                for (int mt = 0; mt < RT; ++mt)
+                for (int e = 0; e < NV - 1; ++e) ws[e] = xch[buf][w0][e][lane];
 #pragma unroll
-                    for (int v = 0; v < 4; ++v) W[mt][v] = xch[buf][w0][4 * mt + v][lane];
+                for (int pp = 1; pp < kWavesPerBlock; ++pp) {
+                    const int w = (pp - rot) & 3;
+#pragma unroll
+                    for (int e = 0; e < NV - 1; ++e) ws[e] += xch[buf][w][e][lane];
+                }
+#pragma unroll
+                for (int mt = 0; mt < FT; ++mt)
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) W[mt][v] = ws[4 * mt + v];
+                if constexpr (kQuad) {
+                    // sum over the four g lanes of the regression, then lane (g, c)
+                    // keeps rank 16 LT + 4 q + g, the layout of the 16x16 tiles
+                    W[LT] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+                    for (int q = 0; q < NQ; ++q) {
+                        float t4[4];
+#pragma unroll
+                        for (int i = 0; i < 4; ++i) t4[i] = colsum(ws[4 * FT + 4 * q + i]);
+                        W[LT][q] = g == 0 ? t4[0] : g == 1 ? t4[1] : g == 2 ? t4[2] : t4[3];
+                    }
+                }
             }
 #pragma unroll
-            for (int pp = 1; pp < kWavesPerBlock; ++pp) {
-                const int w = (pp - rot) & 3;
-#pragma unroll
-                for (int mt = 0; mt < RT; ++mt)
-#pragma unroll
-                    for (int v = 0; v < 4; ++v) W[mt][v] += xch[buf][w][4 * mt + v][lane];
-            }
-#pragma unroll
-            for (int w = 0; w < kWavesPerBlock; ++w) res = fmaxf(res, xch[buf][w][4 * RT][lane]);
+            for (int w = 0; w < kWavesPerBlock; ++w) res = fmaxf(res, xch[buf][w][NV - 1][lane]);
             res = colmax(res);
             // the stopping test of step k - 1
             if (k > 0 && !done) {
@@ -563,7 +639,7 @@ l1_filter_split_kernel(FilterLaunch L)
             }
             if (last || !__any(!done)) break;                 // the same in every wave of the block
 
-            const float inv_beta = 1.0f / beta;
+            const float inv_beta = __builtin_amdgcn_rcpf(beta);
             const float ib = done ? 0.0f : inv_beta;
 #pragma unroll
             for (int mt = 0; mt < RT; ++mt)
