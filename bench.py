@@ -318,7 +318,7 @@ def main_batch(args, R, torch):
                     "achieved": round(filt_tflops, 3), "peak": PEAK_FP32_MFMA_TFLOPS,
                     "unit": "TFLOP/s", "frac": round(filt_tflops / PEAK_FP32_MFMA_TFLOPS, 4),
                     "traffic": counter_traffic(f"lane_filter_{args.config}", digest)}
-    detail = {"overlap_chunks": args.overlap_chunks, "filter_form": FORM_NAMES[form],
+    detail = {"overlap_chunks": args.overlap_chunks,
               "filter_ms": round(filt_ms, 4), "reconstruct_ms": round(recon_ms, 4),
               "sequential_ms_per_step": round(filt_ms + recon_ms, 4),
               "reconstruct_gbs": round(recon_gbs, 1),
@@ -632,7 +632,7 @@ def main():
                     "frac": round(recon_gbs / PEAK_HBM_GBS, 4),
                     "traffic": counter_traffic(f"reconstruct_{args.config}", digest)}
 
-    detail = {"overlap_chunks": args.overlap_chunks,
+    detail = {"overlap_chunks": args.overlap_chunks, "filter_form": FORM_NAMES[form],
               "filter_ms": round(filt_ms, 4), "reconstruct_ms": round(recon_ms, 4),
               "sequential_ms_per_step": round(filt_ms + recon_ms, 4),
               "filter_tflops_contraction": round(filt_tflops, 3),

@@ -18,6 +18,9 @@
 
 #include "rpca_internal.h"
 
+#include <algorithm>
+#include <type_traits>
+
 namespace reconk {
 
 typedef float floatx4 __attribute__((ext_vector_type(4)));
@@ -119,24 +122,40 @@ __device__ __forceinline__ void assemble_block(int64_t first, int64_t end, int64
     }
 }
 
-constexpr int kRowsPerLane = 4;
-constexpr int kRowsPerWave = 64 * kRowsPerLane;
+// Rows of F a lane keeps in VGPRs: 4, or 2 above rank 32 (4 rows x 52 ranks
+// would take every VGPR and leave one wave per SIMD).
+constexpr int rows_per_lane(int R4) { return R4 > 32 ? 2 : 4; }
+constexpr int rows_per_wave(int R4) { return 64 * rows_per_lane(R4); }
 constexpr int kColBatch = 4;    // columns whose loads are in flight together
 
-// One wave of the completion: rows [256 bx, 256 bx + 256) and, of the
-// nb = ceil(n / 4) batches of 4 columns, batches by, by + gy, by + 2 gy, ...:
-// the gy waves of a row block take turns along the columns, so all waves of
-// the grid sweep the matrix together and the addresses in flight stay inside
-// one narrow band of columns whatever the leading dimensions (measured on
-// MI355X: 13% more bandwidth than contiguous column ranges per wave when the
-// columns are not 512-byte aligned, the same when they are); only the
-// matrix's last batch can be partial.  VEC (16-byte aligned columns): lane l
-// owns rows 4l .. 4l+3 of the block and moves float4s; otherwise lane l owns
-// rows l, l+64, l+128, l+192, so each load and store instruction of the wave
-// is one contiguous 256-byte run whatever the alignment of the column.  The
-// loads of a batch's 4 columns are issued together in every row block, the
-// ragged last one included (its lanes past m load nothing and store
-// nothing), so no wave waits out one memory latency per column.
+template <int N> struct VecOf;
+template <> struct VecOf<2> { typedef float type __attribute__((ext_vector_type(2))); };
+template <> struct VecOf<4> { typedef float type __attribute__((ext_vector_type(4))); };
+
+// One wave of the completion: RPL = rows_per_lane(R4) rows per lane, the
+// row block [RPW bx, RPW (bx + 1)) with RPW = 64 RPL, and a share of the
+// nb = ceil(n / 4) batches of 4 columns, one of gy shares per row block:
+//   * R4 <= 32 (most waves resident at once): batches by, by + gy, by + 2 gy,
+//     ... -- the waves of a row block take turns along the columns, so the
+//     whole grid sweeps the matrix together and the addresses in flight stay
+//     in one narrow band of columns whatever the leading dimensions
+//     (measured on MI355X at m = n = 10000: 13% more bandwidth than
+//     contiguous ranges when the columns are not 512-byte aligned, the same
+//     when they are);
+//   * R4 > 32 (the grid runs in many rounds): the contiguous batches
+//     [nb by / gy, nb (by + 1) / gy).
+// Only the matrix's last batch can be partial.  VEC (16-byte aligned
+// columns): lane l owns rows RPL l .. RPL l + RPL - 1 of the block and moves
+// RPL-float vectors; otherwise lane l owns rows l, l + 64, ..., so each load
+// and store instruction of the wave is one contiguous 256-byte run whatever
+// the alignment of the column.  The loads of a batch's 4 columns are issued
+// together, with no condition on any of them.
+//
+// The ragged last row block (m not a multiple of RPW) runs as a full block
+// shifted to end at row m, in the element-wise layout: its rows that the
+// previous block also covers are computed again by the same arithmetic and
+// written again with the same bits.  Only a matrix of fewer than RPW rows
+// takes a guarded, column-by-column path.
 template <int R4, bool VEC>
 __device__ __forceinline__ void recon_wave(const float *__restrict__ M, int64_t ldm,
                                            const float *__restrict__ F,
@@ -145,105 +164,114 @@ __device__ __forceinline__ void recon_wave(const float *__restrict__ M, int64_t 
                                            float *__restrict__ So, int64_t lds, uint32_t bx,
                                            uint32_t by, uint32_t gy, int lane)
 {
-    const int64_t blk = (int64_t)bx * kRowsPerWave;
-    // row of register rr of this lane
-    auto row = [&](int rr) -> int64_t {
-        return VEC ? blk + lane * kRowsPerLane + rr : blk + lane + 64 * rr;
-    };
+    constexpr int RPL = rows_per_lane(R4);
+    constexpr int RPW = rows_per_wave(R4);
+    typedef typename VecOf<RPL>::type vec;
 
-    // the factor rows of this lane (rows past m read row m - 1 and are
-    // zeroed): no branch, so all R4 / 4 loads per row go out together
-    float f[kRowsPerLane][R4];
-#pragma unroll
-    for (int rr = 0; rr < kRowsPerLane; ++rr) {
-        const int64_t i = row(rr);
-        const bool in = i < m;
-        const float *fi = F + (in ? i : m - 1) * R4;
-#pragma unroll
-        for (int k = 0; k < R4; k += 4) {
-            const floatx4 v = *reinterpret_cast<const floatx4 *>(fi + k);
-#pragma unroll
-            for (int e = 0; e < 4; ++e) f[rr][k + e] = in ? v[e] : 0.0f;
-        }
-    }
-    // L and S of column j from its M values mv and the factor row G[j]
-    auto product = [&](int64_t j) -> floatx4 {
+    constexpr bool kSweep = R4 <= 32;
+    const int64_t nb = (n + kColBatch - 1) / kColBatch;
+    const int64_t step = kSweep ? (int64_t)gy * kColBatch : kColBatch;
+    const int64_t jbeg = kSweep ? (int64_t)by * kColBatch : kColBatch * (nb * (int64_t)by / gy);
+    // end of the wave's columns (the sweep runs to n)
+    const int64_t jend = kSweep ? n : std::min<int64_t>(n, kColBatch * (nb * ((int64_t)by + 1) / gy));
+
+    float f[RPL][R4];
+    // L of column j for this lane's rows, from the factor row G[j]
+    auto product = [&](int64_t j) -> vec {
         const float *gj = G + j * R4;     // uniform across the wave
-        floatx4 lv = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
+        vec lv;
+#pragma unroll
+        for (int rr = 0; rr < RPL; ++rr) lv[rr] = 0.0f;
 #pragma unroll
         for (int k = 0; k < R4; ++k) {
             const float gk = gj[k];
 #pragma unroll
-            for (int rr = 0; rr < kRowsPerLane; ++rr) lv[rr] = fmaf(f[rr][k], gk, lv[rr]);
+            for (int rr = 0; rr < RPL; ++rr) lv[rr] = fmaf(f[rr][k], gk, lv[rr]);
         }
         return lv;
     };
-    const int64_t step = (int64_t)gy * kColBatch;
-    int64_t j = (int64_t)by * kColBatch;
-    if (blk + kRowsPerWave <= m) {
-        // full row block (wave-uniform): no condition on any load or store, so
-        // the loads of a batch go out together
-        auto load = [&](int64_t jj) -> floatx4 {
-            if constexpr (VEC) {
-                return __builtin_nontemporal_load(reinterpret_cast<const floatx4 *>(M + jj * ldm + row(0)));
-            } else {
-                floatx4 mv;
+    // the factor rows of this lane (rows past m read row m - 1 and are zeroed;
+    // no branch, so all R4 / 4 loads per row go out together)
+    auto load_f = [&](auto row) {
 #pragma unroll
-                for (int rr = 0; rr < kRowsPerLane; ++rr)
+        for (int rr = 0; rr < RPL; ++rr) {
+            const int64_t i = row(rr);
+            const bool in = i < m;
+            const float *fi = F + (in ? i : m - 1) * R4;
+#pragma unroll
+            for (int k = 0; k < R4; k += 4) {
+                const floatx4 v = *reinterpret_cast<const floatx4 *>(fi + k);
+#pragma unroll
+                for (int e = 0; e < 4; ++e) f[rr][k + e] = in ? v[e] : 0.0f;
+            }
+        }
+    };
+    // a full block starting at row blk0, vector (V) or element-wise layout
+    auto full_block = [&](auto vec_tag, int64_t blk0) {
+        constexpr bool V = decltype(vec_tag)::value;
+        auto row = [&](int rr) -> int64_t { return V ? blk0 + lane * RPL + rr : blk0 + lane + 64 * rr; };
+        load_f(row);
+        auto load = [&](int64_t jj) -> vec {
+            if constexpr (V) {
+                return __builtin_nontemporal_load(reinterpret_cast<const vec *>(M + jj * ldm + row(0)));
+            } else {
+                vec mv;
+#pragma unroll
+                for (int rr = 0; rr < RPL; ++rr)
                     mv[rr] = __builtin_nontemporal_load(M + jj * ldm + row(rr));
                 return mv;
             }
         };
-        auto store = [&](int64_t jj, const floatx4 &mv) {
-            const floatx4 lv = product(jj);
-            const floatx4 sv = mv - lv;
-            if constexpr (VEC) {
-                __builtin_nontemporal_store(lv, reinterpret_cast<floatx4 *>(Lo + jj * ldl + row(0)));
-                __builtin_nontemporal_store(sv, reinterpret_cast<floatx4 *>(So + jj * lds + row(0)));
+        auto store = [&](int64_t jj, const vec &mv) {
+            const vec lv = product(jj);
+            const vec sv = mv - lv;
+            if constexpr (V) {
+                __builtin_nontemporal_store(lv, reinterpret_cast<vec *>(Lo + jj * ldl + row(0)));
+                __builtin_nontemporal_store(sv, reinterpret_cast<vec *>(So + jj * lds + row(0)));
             } else {
 #pragma unroll
-                for (int rr = 0; rr < kRowsPerLane; ++rr) {
+                for (int rr = 0; rr < RPL; ++rr) {
                     __builtin_nontemporal_store(lv[rr], Lo + jj * ldl + row(rr));
                     __builtin_nontemporal_store(sv[rr], So + jj * lds + row(rr));
                 }
             }
         };
+        int64_t j = jbeg;
 #pragma unroll 1
-        for (; j + kColBatch <= n; j += step) {
-            floatx4 mv[kColBatch];
+        for (; j + kColBatch <= jend; j += step) {
+            vec mv[kColBatch];
 #pragma unroll
             for (int cb = 0; cb < kColBatch; ++cb) mv[cb] = load(j + cb);
 #pragma unroll
             for (int cb = 0; cb < kColBatch; ++cb) store(j + cb, mv[cb]);
         }
-        // the matrix's last, partial batch (j < n only for the wave that owns it)
-        for (; j < n; ++j) store(j, load(j));
+        // the matrix's last, partial batch (j < jend only for the wave that owns it)
+        for (; j < jend; ++j) store(j, load(j));
+    };
+
+    const int64_t blk = (int64_t)bx * RPW;
+    if (blk + RPW <= m) {
+        full_block(std::integral_constant<bool, VEC>{}, blk);
+    } else if (m >= RPW) {
+        full_block(std::integral_constant<bool, false>{}, m - RPW);
     } else {
-        // the ragged last row block: element by element, rows past m skipped,
-        // the loads of a batch still issued together
-        // (clamped addresses, so the loads carry no branch)
+        // fewer than RPW rows in the matrix: guarded, one column at a time
+        auto row = [&](int rr) -> int64_t { return lane + 64 * rr; };
+        load_f(row);
 #pragma unroll 1
-        for (; j < n; j += step) {
-            float mv[kColBatch][kRowsPerLane];
+        for (int64_t j = jbeg; j < jend; j += (kSweep ? step : 1)) {
+#pragma unroll 1
+            for (int cb = 0; cb < (kSweep ? kColBatch : 1); ++cb) {
+                const int64_t jj = j + cb;
+                if (jj >= jend) break;
+                const vec lv = product(jj);
 #pragma unroll
-            for (int cb = 0; cb < kColBatch; ++cb)
-#pragma unroll
-                for (int rr = 0; rr < kRowsPerLane; ++rr) {
-                    const int64_t jc = j + cb < n ? j + cb : n - 1;
-                    const int64_t ic = row(rr) < m ? row(rr) : m - 1;
-                    mv[cb][rr] = M[jc * ldm + ic];
-                }
-#pragma unroll
-            for (int cb = 0; cb < kColBatch; ++cb) {
-                if (j + cb < n) {
-                    const floatx4 lv = product(j + cb);
-#pragma unroll
-                    for (int rr = 0; rr < kRowsPerLane; ++rr)
-                        if (row(rr) < m) {
-                            Lo[(j + cb) * ldl + row(rr)] = lv[rr];
-                            So[(j + cb) * lds + row(rr)] = mv[cb][rr] - lv[rr];
-                        }
-                }
+                for (int rr = 0; rr < RPL; ++rr)
+                    if (row(rr) < m) {
+                        const float mv = M[jj * ldm + row(rr)];
+                        Lo[jj * ldl + row(rr)] = lv[rr];
+                        So[jj * lds + row(rr)] = mv - lv[rr];
+                    }
             }
         }
     }

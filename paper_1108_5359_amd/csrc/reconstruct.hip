@@ -38,7 +38,7 @@ int launch_r4(rpca_ctx *ctx, const ReconArgs &a, const float *F, const float *G,
 {
     // ~recon_waves_per_cu waves per CU across the chip (32 measured best),
     // at least one batch of 4 columns each
-    const int64_t row_blocks = (a.m + kRowsPerWave - 1) / kRowsPerWave;
+    const int64_t row_blocks = (a.m + rows_per_wave(R4) - 1) / rows_per_wave(R4);
     const int64_t target_waves =
         (int64_t)(ctx->num_cu > 0 ? ctx->num_cu : 256) * ctx->recon_waves_per_cu;
     int64_t per_block = (target_waves + row_blocks - 1) / row_blocks;

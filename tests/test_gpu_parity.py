@@ -148,6 +148,45 @@ def test_reconstruct_matches_oracle_c1(R, ctx):
     assert np.array_equal(Sh, (pr.M.astype(np.float32) - Lh.astype(np.float32)).astype(np.float64))
 
 
+@pytest.mark.parametrize("m,n,r,p,q,ld_pad", [
+    (1500, 1100, 36, 360, 360, 0),     # R4 = 36: contiguous column ranges per wave
+    (1300, 1700, 50, 500, 500, 4),     # R4 = 52, ld % 4 == 0 with padding
+    (1031, 777, 64, 640, 640, 3),      # R4 = 64, odd ld: element-wise layout
+    (999, 1234, 29, 290, 290, 0),      # R4 = 32: the column sweep, ragged m
+])
+def test_reconstruct_high_rank(R, ctx, m, n, r, p, q, ld_pad):
+    # step 5 alone on arbitrary factors (orthonormal U, V; decreasing sigma;
+    # FP32-valued Q~, P~) against the oracle's four-block completion
+    import torch
+    rng = np.random.Generator(np.random.PCG64([m, n, r]))
+    I = np.sort(rng.choice(m, p, replace=False))
+    J = np.sort(rng.choice(n, q, replace=False))
+    U = np.linalg.qr(rng.standard_normal((p, r)))[0]
+    V = np.linalg.qr(rng.standard_normal((q, r)))[0]
+    sigma = np.sort(rng.uniform(0.5, 2.0, r))[::-1].copy()
+    Qt = rng.standard_normal((r, n - q)).astype(np.float32).astype(np.float64)
+    Pt = rng.standard_normal((r, m - p)).astype(np.float32).astype(np.float64)
+    M = np.asfortranarray(rng.standard_normal((m, n)).astype(np.float32))
+    ld = m + ld_pad
+    say(f"reconstruct m={m} n={n} r={r} ld={ld}")
+    Md = dev_matrix(M, ld)
+    L = torch.full((n, ld), float("nan"), dtype=torch.float32, device="cuda")
+    S = torch.full_like(L, float("nan"))
+    st = R.rpca_reconstruct(ctx, Md, m, n, ld, dev_i64(I), p, dev_i64(J), q, dev_f64_colmajor(U),
+                            torch.as_tensor(sigma).cuda(), dev_f64_colmajor(V), r,
+                            torch.as_tensor(np.ascontiguousarray(Qt.T, dtype=np.float32)).cuda(),
+                            torch.as_tensor(np.ascontiguousarray(Pt.T, dtype=np.float32)).cuda(),
+                            L, ld, S, ld)
+    torch.cuda.synchronize()
+    assert st == R.RPCA_OK
+    Lh, Sh = host_matrix(L, m), host_matrix(S, m)
+    Lref, Sref = oracle.complete(M, I, J, U, sigma, V, Qt, Pt)
+    assert relF(Lh, Lref) <= 1e-6 and relF(Sh, Sref) <= 1e-6
+    assert np.array_equal(Sh, (M - Lh.astype(np.float32)).astype(np.float64))
+    if ld_pad:
+        assert torch_isnan_all(L[:, m:]) and torch_isnan_all(S[:, m:])
+
+
 # ----------------------------------------------------------------- steps 1-5
 @pytest.mark.parametrize("seed", [1, 2, 3])
 def test_solve_matches_oracle_c1(R, ctx, seed):
