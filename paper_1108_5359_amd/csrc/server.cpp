@@ -7,8 +7,10 @@
 // state) and a non-blocking stream.  A free worker admits requests from the
 // head of the queue while the HBM footprint of all admitted, unfinished
 // requests stays within the budget (a request larger than the budget is
-// admitted alone), up to max_batch of them, and runs steps 2-5 for them as one
-// batch on its stream.  Requests that arrive while batches are on the GPU are
+// admitted alone), up to max_batch of them and to its share of the queue
+// (queued requests / workers, rounded up, so a burst is spread over the
+// workers instead of becoming one long batch), and runs steps 2-5 for them as
+// one batch on its stream.  Requests that arrive while batches are on the GPU are
 // taken by the next free worker, so batches of different workers overlap on
 // the device.  A batch that fails as a whole (a bad index array, a seed of
 // rank 0) is retried one request at a time, so one bad request never fails
@@ -115,8 +117,13 @@ void worker_main(rpca_server *s, int index)
         {
             std::unique_lock<std::mutex> lk(s->mu);
             s->cv_work.wait(lk, [&] { return s->admissible_locked() || (s->stop && s->queue.empty()); });
+            // this worker's share of the queue: what is queued split over all
+            // workers (busy ones take theirs when they come back), so a burst
+            // becomes several batches running side by side
+            const size_t nw = (size_t)s->so.workers;
+            const int share = (int)std::min<size_t>((size_t)s->so.max_batch, (s->queue.size() + nw - 1) / nw);
             if (s->queue.empty()) break;           // stop requested and nothing left
-            while (!s->queue.empty() && (int)mine.size() < s->so.max_batch) {
+            while (!s->queue.empty() && (int)mine.size() < std::max(1, share)) {
                 Request &R = s->reqs.at(s->queue.front());
                 if (!(s->inflight == 0 || s->inflight + R.footprint <= (size_t)s->so.hbm_budget_bytes))
                     break;
