@@ -72,7 +72,8 @@ bool filter_supported(rpca_ctx *ctx, int p, int r, int precision)
     if (precision == 1 && p < kMinPHalf) precision = 0;
     const int PT = pick_pt(p, precision), KS = pick_ks(r);
     if (PT < 0 || KS < 0) return false;
-    if (precision == 1) return lds_bytes_f16(PT, KS, false) <= lds_limit(ctx);
+    if (precision == 1)
+        return (half_form(PT) ? lds_bytes_f16h(PT, KS) : lds_bytes_f16(PT, KS, false)) <= lds_limit(ctx);
     return lds_bytes(PT, KS) <= lds_limit(ctx);
 }
 
@@ -128,7 +129,7 @@ int launch_filter(rpca_ctx *ctx, const FilterSide *sides, int nsides, const Filt
         int st = ensure_buf(ctx, ctx->xbuf_ws, xtotal * sizeof(float));
         if (st != RPCA_OK) return st;
     }
-    if (c.precision == 1 && lds_bytes_f16(PT, KS, true) > lds_limit(ctx)) {
+    if (c.precision == 1 && (half_form(PT) || lds_bytes_f16(PT, KS, true) > lds_limit(ctx))) {
         // FP32 refresh fragments do not fit next to the FP16 ones: build them in HBM
         const int RT = (KS + 3) / 4;
         const size_t per = (size_t)PT * RT * 256;
@@ -162,7 +163,9 @@ int launch_filter(rpca_ctx *ctx, const FilterSide *sides, int nsides, const Filt
         L.side[s] = sides[s];
         L.side[s].xbuf = static_cast<float *>(ctx->xbuf_ws.ptr) + xoff[s];
         const int64_t tiles = (sides[s].nreg + 15) / 16;
-        const int64_t blocks = split ? tiles : (tiles + kWavesPerBlock - 1) / kWavesPerBlock;
+        // tiles per workgroup: 1 (split form), 2 (half-tile precision form) or 4
+        const int64_t per = split ? 1 : (c.precision == 1 && half_form(PT)) ? 2 : kWavesPerBlock;
+        const int64_t blocks = (tiles + per - 1) / per;
         if (blocks > INT_MAX / 2) return set_status(ctx, RPCA_ERR_UNSUPPORTED, "filter: too many regressions");
         if (s == 0) L.nblocks0 = (int)blocks;
         nblocks += (int)blocks;

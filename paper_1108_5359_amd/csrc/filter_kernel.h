@@ -1023,6 +1023,301 @@ l1_filter_kernel_f16(FilterLaunch L)
     }
 }
 
+// ---------------------------------------------------------------------------
+// Precision form, half-tile variant for large p (PT >= 19).  One wave holding
+// all PT element tiles of its 16 regressions needs 8 PT floats of u, y per
+// lane (256 at p = 512: the whole register file, so the tile kernel spills).
+// Here each 16-regression tile has two waves, each holding half of the
+// element-tile pairs; a workgroup of four waves serves two tiles and shares
+// the FP16 basis fragments in LDS.  Per step each wave contracts its half
+// (w = A^T g), publishes the partial w and the previous step's residual
+// partial in LDS, and after one barrier both waves of a tile add the two
+// partials in half order (identical w and z in both); the stopping test of a
+// step is taken one step later, and a barrier-OR over the workgroup decides
+// when both tiles are done (a finished tile keeps iterating frozen, as a
+// finished regression does).  The refresh reads its FP32 fragments from HBM.
+// ---------------------------------------------------------------------------
+template <int PT, int KS>
+struct HalfShape {
+    static constexpr int RT = (KS + 3) / 4;
+    static constexpr int RP = (RT + 1) / 2;
+    static constexpr int PP = (PT + 1) / 2;          // element-tile pairs
+    static constexpr int NPH = (PP + 1) / 2;         // pairs per half (the second may pad)
+    static constexpr int PPA = 2 * NPH;              // pairs staged (padded)
+    static constexpr int TA = 2 * PPA;               // element tiles staged (padded)
+    static constexpr int NV = 4 * RT + 1;            // floats a lane publishes per step
+    static constexpr int kTiles = 2;                 // tiles per workgroup
+};
+
+constexpr bool half_form(int PT) { return PT >= 19; }
+
+inline size_t lds_bytes_f16h(int PT, int KS)
+{
+    const int RT = (KS + 3) / 4, RP = (RT + 1) / 2, PP = (PT + 1) / 2, NPH = (PP + 1) / 2;
+    const int PPA = 2 * NPH, TA = 2 * PPA, NV = 4 * RT + 1;
+    return (size_t)PPA * RT * 512 * sizeof(_Float16) + (size_t)TA * RP * 512 * sizeof(_Float16) +
+           (size_t)TA * 16 * sizeof(int64_t) + (size_t)kWavesPerBlock * NV * 64 * sizeof(float);
+}
+
+template <int PT, int KS>
+__global__ void __launch_bounds__(kWavesPerBlock * 64)
+l1_filter_kernel_f16h(FilterLaunch L)
+{
+    using Sh = HalfShape<PT, KS>;
+    constexpr int RT = Sh::RT, RP = Sh::RP, PP = Sh::PP, NPH = Sh::NPH, PPA = Sh::PPA, TA = Sh::TA;
+    constexpr int NV = Sh::NV, TPB = Sh::kTiles;
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+    _Float16 *h1 = reinterpret_cast<_Float16 *>(lds_raw);              // [PPA][RT][64][8]
+    _Float16 *h2 = h1 + PPA * RT * 512;                                  // [TA][RP][64][8]
+    int64_t *eoff = reinterpret_cast<int64_t *>(h2 + TA * RP * 512);    // [TA*16]
+    float *xch = reinterpret_cast<float *>(eoff + TA * 16);              // [4 waves][NV][64]
+
+    const bool second = (int)blockIdx.x >= L.nblocks0;
+#define SIDE(f) (second ? L.side[1].f : L.side[0].f)
+    const int block_in_side = second ? (int)blockIdx.x - L.nblocks0 : (int)blockIdx.x;
+    const int p = SIDE(p), r = SIDE(r);
+    const double *__restrict__ A = SIDE(A);
+    const int lda = SIDE(lda);
+    const int64_t *__restrict__ elem_idx = SIDE(elem_idx);
+    const int64_t *__restrict__ reg_idx = SIDE(reg_idx);
+    const int64_t elem_stride = SIDE(elem_stride), reg_stride = SIDE(reg_stride);
+    const int64_t elem_bound = SIDE(elem_bound), reg_bound = SIDE(reg_bound);
+    const int64_t nreg = SIDE(nreg);
+    const float *__restrict__ M = SIDE(M);
+    float *__restrict__ Zout = SIDE(Z);
+    const int64_t ldz = SIDE(ldz);
+    int32_t *__restrict__ iters = SIDE(iters);
+    floatx4 *__restrict__ xbuf = reinterpret_cast<floatx4 *>(SIDE(xbuf));
+    const int64_t *range = SIDE(range);
+#undef SIDE
+    int64_t jbeg = 0, jend = nreg;
+    if (range) {
+        jbeg = range[0];
+        jend = range[1];
+    }
+    const float *f2glob = second ? L.frag32[1] : L.frag32[0];
+    if (jbeg + (int64_t)block_in_side * TPB * 16 >= jend) return;   // whole block idle (before any barrier)
+
+    // ---- stage the basis (padded pairs and tiles are zero) -----------------
+    for (int idx = threadIdx.x; idx < PPA * RT * 512; idx += kWavesPerBlock * 64) {
+        const int i = idx & 7, ln = (idx >> 3) & 63, pm = idx >> 9;
+        const int pp = pm / RT, mt = pm - pp * RT;
+        const int g = ln >> 4, c = ln & 15;
+        const int e = 16 * (2 * pp + (i >> 2)) + 4 * g + (i & 3);
+        const int k = 16 * mt + 4 * (c & 3) + (c >> 2);
+        h1[idx] = (_Float16)((e < p && k < r) ? A[e + (int64_t)k * lda] : 0.0);
+    }
+    for (int idx = threadIdx.x; idx < TA * RP * 512; idx += kWavesPerBlock * 64) {
+        const int i = idx & 7, ln = (idx >> 3) & 63, tr = idx >> 9;
+        const int t = tr / RP, rp = tr - t * RP;
+        const int g = ln >> 4, c = ln & 15;
+        const int e = 16 * t + c;
+        const int k = 16 * (2 * rp + (i >> 2)) + 4 * (i & 3) + g;
+        h2[idx] = (_Float16)((e < p && k < r) ? A[e + (int64_t)k * lda] : 0.0);
+    }
+    for (int e = threadIdx.x; e < TA * 16; e += kWavesPerBlock * 64) {
+        int64_t off = -1;
+        if (e < p) {
+            const int64_t ei = elem_idx[e];
+            if (ei >= 0 && ei < elem_bound) off = ei * elem_stride;
+        }
+        eoff[e] = off;
+    }
+    __syncthreads();
+
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int lane = threadIdx.x & 63;
+    const int g = lane >> 4, c = lane & 15;
+    const int tl = wave >> 1, half = wave & 1;
+    const int64_t tile = (int64_t)block_in_side * TPB + tl;
+    const int64_t j = jbeg + tile * 16 + c;
+    const int pp0 = half * NPH;                       // this half's first pair
+    const bool tile_in = jbeg + tile * 16 < jend;     // wave-uniform: the tile holds regressions
+    bool valid = j < jend;
+    int64_t roff = 0;
+    if (valid) {
+        const int64_t ri = reg_idx[j];
+        if (ri >= 0 && ri < reg_bound) roff = ri * reg_stride;
+        else valid = false;
+    }
+
+    // ---- x of this half, its partial norms, the state ---------------------
+    float u[2 * NPH][4], y[2 * NPH][4];
+    float xinf = 0.0f, xx = 0.0f;
+    floatx4 *xtile = xbuf + tile * PT * 64 + lane;
+#pragma unroll
+    for (int s = 0; s < 2 * NPH; ++s) {
+        const int t = 2 * pp0 + s;
+        floatx4 xv;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int64_t off = eoff[16 * t + 4 * g + v];
+            const float x = (valid && off >= 0) ? M[roff + off] : 0.0f;
+            xv[v] = x;
+            u[s][v] = x;
+            y[s][v] = 0.0f;
+            xinf = fmaxf(xinf, fabsf(x));
+            xx = fmaf(x, x, xx);
+        }
+        if (t < PT && tile_in) xtile[t * 64] = xv;
+    }
+    // norms over both halves, in half order
+    xch[(wave * NV + 0) * 64 + lane] = xinf;
+    xch[(wave * NV + 1) * 64 + lane] = xx;
+    __syncthreads();
+    {
+        const int w0 = wave & ~1;
+        xinf = fmaxf(xch[(w0 * NV + 0) * 64 + lane], xch[((w0 + 1) * NV + 0) * 64 + lane]);
+        xx = xch[(w0 * NV + 1) * 64 + lane] + xch[((w0 + 1) * NV + 1) * 64 + lane];
+    }
+    xinf = colmax(xinf);
+    xx = colsum(xx);
+    __syncthreads();                                  // the buffer is reused below
+
+    float beta = xx > 0.0f ? L.c.beta0_scale / sqrtf(xx) : 1.0f;
+    const float beta_bar = L.c.beta_max_scale * beta;
+    const float tol = L.c.eps * xinf;
+    bool done = !(valid && xinf > 0.0f);
+    int K = 0;
+    float inv_beta_prev = 0.0f, res_part = 0.0f;
+    floatx4 z[RT];
+#pragma unroll
+    for (int mt = 0; mt < RT; ++mt) z[mt] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
+
+    const halfx8 *H1 = reinterpret_cast<const halfx8 *>(h1) + lane;
+    const halfx8 *H2 = reinterpret_cast<const halfx8 *>(h2) + lane;
+    const floatx4 *F2 = reinterpret_cast<const floatx4 *>(f2glob) + lane;
+    float *mine = xch + wave * NV * 64 + lane;
+    const float *hx0 = xch + (wave & ~1) * NV * 64 + lane;      // half 0 of this tile
+    const float *hx1 = hx0 + NV * 64;                            // half 1
+
+    for (int k = 0;; ++k) {
+        // after max_iter steps only the pending stopping test is left
+        const bool last = k >= L.c.max_iter;
+        // partial w = A^T g over this half's pairs (K = 32 elements per MFMA)
+        floatx4 Wp[RT];
+#pragma unroll
+        for (int mt = 0; mt < RT; ++mt) Wp[mt] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+        for (int q = 0; q < NPH; ++q) {
+            float glo[4], ghi[4];
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                glo[v] = __builtin_amdgcn_fmed3f(fmaf(beta, u[2 * q][v], y[2 * q][v]), -1.0f, 1.0f);
+                ghi[v] = __builtin_amdgcn_fmed3f(fmaf(beta, u[2 * q + 1][v], y[2 * q + 1][v]), -1.0f, 1.0f);
+            }
+            const halfx8 gb = pack8(glo, ghi);
+#pragma unroll
+            for (int mt = 0; mt < RT; ++mt) Wp[mt] = mfma16h(H1[((pp0 + q) * RT + mt) * 64], gb, Wp[mt]);
+        }
+#pragma unroll
+        for (int mt = 0; mt < RT; ++mt)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) mine[(4 * mt + v) * 64] = Wp[mt][v];
+        mine[(NV - 1) * 64] = res_part;
+        __syncthreads();
+        floatx4 W[RT];
+#pragma unroll
+        for (int mt = 0; mt < RT; ++mt)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) W[mt][v] = hx0[(4 * mt + v) * 64] + hx1[(4 * mt + v) * 64];
+        float res = colmax(fmaxf(hx0[(NV - 1) * 64], hx1[(NV - 1) * 64]));
+        // the stopping test of step k - 1
+        if (k > 0 && !done) {
+            ++K;
+            if (!(res * inv_beta_prev >= tol)) done = true;
+        }
+        // both tiles of the workgroup done (this barrier also ends the reads
+        // of the exchange buffer before the next step writes it)
+        if (last) break;
+        if (!__syncthreads_or(done ? 0 : 1)) break;
+
+        const float inv_beta = __builtin_amdgcn_rcpf(beta);
+        const float ib = done ? 0.0f : inv_beta;
+#pragma unroll
+        for (int mt = 0; mt < RT; ++mt)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) z[mt][v] = fmaf(W[mt][v], ib, z[mt][v]);
+
+        // w as the FP16 B operand of v = A w, rank-tile pairs
+        halfx8 wb[RP];
+#pragma unroll
+        for (int rp = 0; rp < RP; ++rp) {
+            float lo[4], hi[4];
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                lo[v] = W[2 * rp][v];
+                hi[v] = (2 * rp + 1 < RT) ? W[2 * rp + 1 < RT ? 2 * rp + 1 : 0][v] : 0.0f;
+            }
+            wb[rp] = pack8(lo, hi);
+        }
+        res_part = 0.0f;
+#pragma unroll
+        for (int s = 0; s < 2 * NPH; s += 2) {
+            floatx4 Va = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
+            floatx4 Vb = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
+            const int t = 2 * pp0 + s;
+#pragma unroll
+            for (int rp = 0; rp < RP; ++rp) {
+                Va = mfma16h(H2[(t * RP + rp) * 64], wb[rp], Va);
+                Vb = mfma16h(H2[((t + 1) * RP + rp) * 64], wb[rp], Vb);
+            }
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const floatx4 Vt = h ? Vb : Va;
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const float yo = y[s + h][v];
+                    const float gg = __builtin_amdgcn_fmed3f(fmaf(beta, u[s + h][v], yo), -1.0f, 1.0f);
+                    const float yn = gg - Vt[v];
+                    res_part = fmaxf(res_part, fabsf(yn - yo));
+                    u[s + h][v] = fmaf(-Vt[v], ib, u[s + h][v]);
+                    y[s + h][v] = yn;
+                }
+            }
+        }
+        inv_beta_prev = inv_beta;
+        beta = fminf(L.c.rho * beta, beta_bar);
+
+        // FP32 residual refinement: u = x - A z from the input
+        if (L.c.refresh > 0 && ((k + 1) % L.c.refresh) == 0) {
+#pragma unroll
+            for (int s = 0; s < 2 * NPH; ++s) {
+                const int t = 2 * pp0 + s;
+                if (t < PT) {
+                    __builtin_amdgcn_sched_barrier(0);
+                    floatx4 Az = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+                    for (int mt = 0; mt < RT; ++mt) {
+                        const floatx4 a = F2[(t * RT + mt) * 64];
+#pragma unroll
+                        for (int v = 0; v < 4; ++v)
+                            if (4 * mt + v < KS) Az = mfma4(a[v], z[mt][v], Az);
+                    }
+                    floatx4 xv = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
+                    if (tile_in) xv = xtile[t * 64];          // (no x slot for an idle tile)
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) u[s][v] = xv[v] - Az[v];
+                }
+            }
+        }
+    }
+
+    if (half == 0 && j < jend) {
+        if (valid) {
+#pragma unroll
+            for (int mt = 0; mt < RT; ++mt)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int kk = 16 * mt + 4 * v + g;
+                    if (kk < r) Zout[kk + j * ldz] = z[mt][v];
+                }
+        }
+        if (iters && g == 0)
+            iters[j] = !valid ? INT_MIN : (done ? K : -L.c.max_iter);
+    }
+}
+
 // FP32 refresh fragments of the precision form, for classes whose LDS cannot
 // hold them: out[(t RT + mt) 256 + lane 4 + v] = A[16 t + c][16 mt + 4 v + g].
 static __global__ void prep_frag32(const double *__restrict__ A, int lda, int p, int r, int PT, int RT,
@@ -1049,6 +1344,22 @@ int launch_pt_ks(rpca_ctx *ctx, const FilterLaunch &L, int nblocks, bool split, 
         }
     }
     if (split) return set_status(ctx, RPCA_ERR_UNSUPPORTED, "filter: split form not built for this class");
+    if constexpr (half_form(PT)) {
+        if (L.c.precision == 1) {
+            // half-tile variant: two tiles per workgroup, refresh fragments in HBM
+            const size_t lds = lds_bytes_f16h(PT, KS);
+            static bool attr_set_hh = false;
+            if (!attr_set_hh) {
+                RPCA_HIP_TRY(ctx, hipFuncSetAttribute((const void *)l1_filter_kernel_f16h<PT, KS>,
+                                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+                attr_set_hh = true;
+            }
+            hipLaunchKernelGGL((l1_filter_kernel_f16h<PT, KS>), dim3(nblocks), dim3(kWavesPerBlock * 64),
+                               lds, stream, L);
+            RPCA_HIP_TRY(ctx, hipGetLastError());
+            return RPCA_OK;
+        }
+    }
     if (L.c.precision == 1) {
         // the FP32 refresh fragments live in HBM when the launcher prepared them
         const size_t lds = lds_bytes_f16(PT, KS, L.frag32[0] == nullptr);
