@@ -322,6 +322,9 @@ typedef struct {
     int32_t graph;               /* 1 = replay runs after the first from HIP graphs (1)     */
     int32_t seed_batched;        /* 1 = seed blocks that fit in LDS are solved together, one */
                                  /* workgroup each (Jacobi SVD); 0 = one by one (1)         */
+    int32_t recon_waves_per_cu;  /* completion waves resident per CU at most, enforced by   */
+                                 /* each wave's LDS reservation; 0 = no cap (4: fewer       */
+                                 /* concurrent column streams keep HBM pages open longer)   */
 } rpca_batch_tuning;
 
 typedef struct rpca_batch *rpca_batch_t;

@@ -9,7 +9,9 @@ choices the library leaves open:
 * ``filter_waves_per_cu``: size of the persistent filter grid;
 * ``order``: work queue costliest side first, or problem order;
 * ``recon_cols_per_wave``: columns streamed by one wave of the batched
-  completion (the completion grid).
+  completion (the completion grid);
+* ``recon_waves_per_cu``: most completion waves resident per CU (through
+  their LDS reservation).
 
 Coordinate descent over these grids from the library's defaults, each
 candidate timed as the median of ``--reps`` runs of ``rpca_batch_run`` after
@@ -38,6 +40,7 @@ GRID = {
     "filter_waves_per_cu": [4, 6, 8, 12, 16],
     "order": [0, 1],
     "recon_cols_per_wave": [8, 16, 32, 64, 128, 256],
+    "recon_waves_per_cu": [0, 2, 3, 4, 6, 8],
 }
 
 

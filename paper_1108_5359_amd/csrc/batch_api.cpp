@@ -305,6 +305,11 @@ int build_tables(rpca_batch *b)
     t.rec_block_job = reinterpret_cast<const int32_t *>(base + o_rj);
     t.rec_block_local = reinterpret_cast<const uint32_t *>(base + o_rl);
     t.rec_blocks = (int32_t)rec_job.size();
+    // at most recon_waves_per_cu completion waves per CU: each reserves its share of the LDS
+    const size_t lds_cu = ctx->max_lds ? ctx->max_lds : 65536;
+    t.rec_lds_bytes = b->tun.recon_waves_per_cu > 0
+                          ? (int32_t)((lds_cu / (size_t)b->tun.recon_waves_per_cu) & ~(size_t)255)
+                          : 0;
     return RPCA_OK;
 }
 
@@ -316,7 +321,8 @@ int batch_check_tuning(rpca_ctx *ctx, const rpca_batch_tuning &tun)
         tun.lane_max_r > kLaneMaxR || tun.lane_split2_p < 0 || tun.lane_split2_p > 32 ||
         tun.lane_split4_p < tun.lane_split2_p || tun.lane_split4_p > 64 ||
         tun.filter_waves_per_cu < 0 || tun.filter_waves_per_cu > 64 ||
-        tun.recon_cols_per_wave < 1 || (tun.order != 0 && tun.order != 1) ||
+        tun.recon_cols_per_wave < 1 || tun.recon_waves_per_cu < 0 || tun.recon_waves_per_cu > 64 ||
+        (tun.order != 0 && tun.order != 1) ||
         (tun.graph != 0 && tun.graph != 1) || (tun.seed_batched != 0 && tun.seed_batched != 1))
         return set_status(ctx, RPCA_ERR_ARG, "batch: bad tuning");
     return RPCA_OK;
@@ -454,6 +460,7 @@ void rpca_batch_tuning_default(rpca_batch_tuning *t)
     t->order = 0;
     t->graph = 1;
     t->seed_batched = 1;
+    t->recon_waves_per_cu = 4;
 }
 
 int rpca_batch_create(rpca_ctx_t ctx, const rpca_job *jobs, int64_t njobs, const rpca_opts *opts,

@@ -226,6 +226,7 @@ struct BatchTables {
     const int32_t *rec_block_job;    // job of each completion wave
     const uint32_t *rec_block_local; // its index among the job's waves
     int32_t rec_blocks;
+    int32_t rec_lds_bytes;           // LDS reserved per completion wave (caps residency), 0 = none
 };
 
 // Enqueue the lane-form filter over every item (queue reset included).

@@ -246,6 +246,7 @@ class rpca_batch_tuning(ctypes.Structure):
         ("lane_max_p", _i32), ("lane_max_r", _i32), ("lane_split2_p", _i32),
         ("lane_split4_p", _i32), ("filter_waves_per_cu", _i32),
         ("recon_cols_per_wave", _i32), ("order", _i32), ("graph", _i32), ("seed_batched", _i32),
+        ("recon_waves_per_cu", _i32),
     ]
 
     def as_dict(self):
