@@ -467,13 +467,12 @@ int launch_batch_reconstruct(rpca_ctx *ctx, const BatchTables &t, hipStream_t st
     if (t.rec_blocks > 0) {
         if (t.rec_lds_bytes > 0) {
             // the reservation only limits residency; the kernel does not touch it
-            static bool attr_set = false;
-            if (!attr_set) {
-                RPCA_HIP_TRY(ctx, hipFuncSetAttribute((const void *)batch_reconstruct,
-                                                      hipFuncAttributeMaxDynamicSharedMemorySize,
-                                                      (int)(ctx->max_lds ? ctx->max_lds : 65536)));
-                attr_set = true;
-            }
+            // once per process (thread-safe static initialisation), before any
+            // launch can be captured in a graph
+            static const hipError_t attr =
+                hipFuncSetAttribute((const void *)batch_reconstruct, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                    (int)(ctx->max_lds ? ctx->max_lds : 65536));
+            RPCA_HIP_TRY(ctx, attr);
         }
         hipLaunchKernelGGL(batch_reconstruct, dim3((unsigned)t.rec_blocks), dim3(64),
                            (size_t)t.rec_lds_bytes, stream, t.jobs, t.rec_block_job, t.rec_block_local);

@@ -1348,12 +1348,11 @@ int launch_pt_ks(rpca_ctx *ctx, const FilterLaunch &L, int nblocks, bool split, 
         if (L.c.precision == 1) {
             // half-tile variant: two tiles per workgroup, refresh fragments in HBM
             const size_t lds = lds_bytes_f16h(PT, KS);
-            static bool attr_set_hh = false;
-            if (!attr_set_hh) {
-                RPCA_HIP_TRY(ctx, hipFuncSetAttribute((const void *)l1_filter_kernel_f16h<PT, KS>,
-                                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-                attr_set_hh = true;
-            }
+            // once per process (thread-safe static initialisation), before any
+            // launch can be captured in a graph
+            static const hipError_t attr = hipFuncSetAttribute(
+                (const void *)l1_filter_kernel_f16h<PT, KS>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+            RPCA_HIP_TRY(ctx, attr);
             hipLaunchKernelGGL((l1_filter_kernel_f16h<PT, KS>), dim3(nblocks), dim3(kWavesPerBlock * 64),
                                lds, stream, L);
             RPCA_HIP_TRY(ctx, hipGetLastError());
@@ -1363,15 +1362,11 @@ int launch_pt_ks(rpca_ctx *ctx, const FilterLaunch &L, int nblocks, bool split, 
     if (L.c.precision == 1) {
         // the FP32 refresh fragments live in HBM when the launcher prepared them
         const size_t lds = lds_bytes_f16(PT, KS, L.frag32[0] == nullptr);
-        static bool attr_set_h = false;
-        if (!attr_set_h) {
-            RPCA_HIP_TRY(ctx, hipFuncSetAttribute((const void *)l1_filter_kernel_f16<PT, KS>,
-                                                  hipFuncAttributeMaxDynamicSharedMemorySize,
-                                                  (int)lds_bytes_f16(PT, KS, true) > (int)ctx->max_lds
-                                                      ? (int)lds_bytes_f16(PT, KS, false)
-                                                      : (int)lds_bytes_f16(PT, KS, true)));
-            attr_set_h = true;
-        }
+        static const hipError_t attr = hipFuncSetAttribute(
+            (const void *)l1_filter_kernel_f16<PT, KS>, hipFuncAttributeMaxDynamicSharedMemorySize,
+            (int)lds_bytes_f16(PT, KS, true) > (int)ctx->max_lds ? (int)lds_bytes_f16(PT, KS, false)
+                                                                 : (int)lds_bytes_f16(PT, KS, true));
+        RPCA_HIP_TRY(ctx, attr);
         hipLaunchKernelGGL((l1_filter_kernel_f16<PT, KS>), dim3(nblocks), dim3(kWavesPerBlock * 64),
                            lds, stream, L);
         RPCA_HIP_TRY(ctx, hipGetLastError());
@@ -1379,13 +1374,9 @@ int launch_pt_ks(rpca_ctx *ctx, const FilterLaunch &L, int nblocks, bool split, 
     }
     if constexpr (PT <= 19) {
         const size_t lds = lds_bytes(PT, KS);
-        static bool attr_set = false;
-        if (!attr_set) {
-            RPCA_HIP_TRY(ctx, hipFuncSetAttribute((const void *)l1_filter_kernel<PT, KS>,
-                                                  hipFuncAttributeMaxDynamicSharedMemorySize,
-                                                  (int)lds));
-            attr_set = true;
-        }
+        static const hipError_t attr = hipFuncSetAttribute(
+            (const void *)l1_filter_kernel<PT, KS>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        RPCA_HIP_TRY(ctx, attr);
         hipLaunchKernelGGL((l1_filter_kernel<PT, KS>), dim3(nblocks), dim3(kWavesPerBlock * 64),
                            lds, stream, L);
         RPCA_HIP_TRY(ctx, hipGetLastError());
