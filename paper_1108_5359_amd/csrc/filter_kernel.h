@@ -1064,7 +1064,7 @@ __global__ void __launch_bounds__(kWavesPerBlock * 64)
 l1_filter_kernel_f16h(FilterLaunch L)
 {
     using Sh = HalfShape<PT, KS>;
-    constexpr int RT = Sh::RT, RP = Sh::RP, PP = Sh::PP, NPH = Sh::NPH, PPA = Sh::PPA, TA = Sh::TA;
+    constexpr int RT = Sh::RT, RP = Sh::RP, NPH = Sh::NPH, PPA = Sh::PPA, TA = Sh::TA;
     constexpr int NV = Sh::NV, TPB = Sh::kTiles;
     extern __shared__ __align__(16) unsigned char lds_raw[];
     _Float16 *h1 = reinterpret_cast<_Float16 *>(lds_raw);              // [PPA][RT][64][8]
