@@ -3,6 +3,7 @@
 // (column and row filtering, Sec. 3.3: independent steps) into one launch.
 #include "filter_kernel.h"
 
+#include <algorithm>
 #include <climits>
 #include <string>
 
@@ -73,7 +74,7 @@ bool filter_supported(rpca_ctx *ctx, int p, int r, int precision)
     const int PT = pick_pt(p, precision), KS = pick_ks(r);
     if (PT < 0 || KS < 0) return false;
     if (precision == 1)
-        return (half_form(PT) ? lds_bytes_f16h(PT, KS) : lds_bytes_f16(PT, KS, false)) <= lds_limit(ctx);
+        return (half_form(PT) ? lds_bytes_f16q(PT, KS) : lds_bytes_f16(PT, KS, false)) <= lds_limit(ctx);
     return lds_bytes(PT, KS) <= lds_limit(ctx);
 }
 
@@ -158,14 +159,25 @@ int launch_filter(rpca_ctx *ctx, const FilterSide *sides, int nsides, const Filt
             split = choose_split(PT, KS, tiles, ctx->num_cu);
         }
     }
+    // quarter-tile precision form: persistent, one workgroup per CU, the CUs
+    // shared between the sides in proportion to their tiles
+    const bool quarter = c.precision == 1 && half_form(PT);
+    int64_t all_tiles = 0;
+    for (int s = 0; s < nsides; ++s) all_tiles += (sides[s].nreg + 15) / 16;
+    const int64_t ncu = ctx->num_cu > 0 ? ctx->num_cu : 256;
     int nblocks = 0;
     for (int s = 0; s < nsides; ++s) {
         L.side[s] = sides[s];
         L.side[s].xbuf = static_cast<float *>(ctx->xbuf_ws.ptr) + xoff[s];
         const int64_t tiles = (sides[s].nreg + 15) / 16;
-        // tiles per workgroup: 1 (split form), 2 (half-tile precision form) or 4
-        const int64_t per = split ? 1 : (c.precision == 1 && half_form(PT)) ? 2 : kWavesPerBlock;
-        const int64_t blocks = (tiles + per - 1) / per;
+        int64_t blocks;
+        if (quarter) {
+            blocks = std::min<int64_t>(tiles, std::max<int64_t>(1, (ncu * tiles + all_tiles / 2) / std::max<int64_t>(all_tiles, 1)));
+        } else {
+            // tiles per workgroup: 1 (split form) or 4
+            const int64_t per = split ? 1 : kWavesPerBlock;
+            blocks = (tiles + per - 1) / per;
+        }
         if (blocks > INT_MAX / 2) return set_status(ctx, RPCA_ERR_UNSUPPORTED, "filter: too many regressions");
         if (s == 0) L.nblocks0 = (int)blocks;
         nblocks += (int)blocks;

@@ -1024,48 +1024,50 @@ l1_filter_kernel_f16(FilterLaunch L)
 }
 
 // ---------------------------------------------------------------------------
-// Precision form, half-tile variant for large p (PT >= 19).  One wave holding
-// all PT element tiles of its 16 regressions needs 8 PT floats of u, y per
-// lane (256 at p = 512: the whole register file, so the tile kernel spills).
-// Here each 16-regression tile has two waves, each holding half of the
-// element-tile pairs; a workgroup of four waves serves two tiles and shares
-// the FP16 basis fragments in LDS.  Per step each wave contracts its half
-// (w = A^T g), publishes the partial w and the previous step's residual
-// partial in LDS, and after one barrier both waves of a tile add the two
-// partials in half order (identical w and z in both); the stopping test of a
-// step is taken one step later, and a barrier-OR over the workgroup decides
-// when both tiles are done (a finished tile keeps iterating frozen, as a
-// finished regression does).  The refresh reads its FP32 fragments from HBM.
+// Precision form, quarter-tile persistent variant for large p (PT >= 19).  One
+// wave holding all PT element tiles of its 16 regressions needs 8 PT floats of
+// u, y per lane (256 at p = 512: the whole register file, so the tile kernel
+// spills, and the basis fragments of a contraction cannot be kept in flight).
+// Here the four waves of a workgroup serve one 16-regression tile together,
+// each holding a quarter of the element-tile pairs.  The workgroup stages the
+// FP16 basis fragments in LDS once and then takes the tiles of its side in
+// turn (its index, plus the side's workgroup count, ...), so the staging is
+// paid once per workgroup, not once per tile.  Per step each wave contracts its
+// quarter (w = A^T g) and publishes the partial w and the previous step's
+// residual partial in LDS; after a barrier every wave adds the four partials
+// in quarter order (identical w and z in all four waves, and the same bits for
+// a regression wherever it sits), and a second barrier frees the buffer.  The
+// stopping test of a step is taken one step later; a stopped regression only
+// stops moving z and u.  The refresh reads its FP32 fragments from HBM.
 // ---------------------------------------------------------------------------
 template <int PT, int KS>
-struct HalfShape {
+struct QuarterShape {
     static constexpr int RT = (KS + 3) / 4;
     static constexpr int RP = (RT + 1) / 2;
     static constexpr int PP = (PT + 1) / 2;          // element-tile pairs
-    static constexpr int NPH = (PP + 1) / 2;         // pairs per half (the second may pad)
-    static constexpr int PPA = 2 * NPH;              // pairs staged (padded)
+    static constexpr int NPP = (PP + 3) / 4;         // pairs per quarter (the last may pad)
+    static constexpr int PPA = 4 * NPP;              // pairs staged (padded)
     static constexpr int TA = 2 * PPA;               // element tiles staged (padded)
     static constexpr int NV = 4 * RT + 1;            // floats a lane publishes per step
-    static constexpr int kTiles = 2;                 // tiles per workgroup
 };
 
 constexpr bool half_form(int PT) { return PT >= 19; }
 
-inline size_t lds_bytes_f16h(int PT, int KS)
+inline size_t lds_bytes_f16q(int PT, int KS)
 {
-    const int RT = (KS + 3) / 4, RP = (RT + 1) / 2, PP = (PT + 1) / 2, NPH = (PP + 1) / 2;
-    const int PPA = 2 * NPH, TA = 2 * PPA, NV = 4 * RT + 1;
+    const int RT = (KS + 3) / 4, RP = (RT + 1) / 2, PP = (PT + 1) / 2, NPP = (PP + 3) / 4;
+    const int PPA = 4 * NPP, TA = 2 * PPA, NV = 4 * RT + 1;
     return (size_t)PPA * RT * 512 * sizeof(_Float16) + (size_t)TA * RP * 512 * sizeof(_Float16) +
            (size_t)TA * 16 * sizeof(int64_t) + (size_t)kWavesPerBlock * NV * 64 * sizeof(float);
 }
 
 template <int PT, int KS>
 __global__ void __launch_bounds__(kWavesPerBlock * 64)
-l1_filter_kernel_f16h(FilterLaunch L)
+l1_filter_kernel_f16q(FilterLaunch L)
 {
-    using Sh = HalfShape<PT, KS>;
-    constexpr int RT = Sh::RT, RP = Sh::RP, NPH = Sh::NPH, PPA = Sh::PPA, TA = Sh::TA;
-    constexpr int NV = Sh::NV, TPB = Sh::kTiles;
+    using Sh = QuarterShape<PT, KS>;
+    constexpr int RT = Sh::RT, RP = Sh::RP, NPP = Sh::NPP, PPA = Sh::PPA, TA = Sh::TA;
+    constexpr int NV = Sh::NV;
     extern __shared__ __align__(16) unsigned char lds_raw[];
     _Float16 *h1 = reinterpret_cast<_Float16 *>(lds_raw);              // [PPA][RT][64][8]
     _Float16 *h2 = h1 + PPA * RT * 512;                                  // [TA][RP][64][8]
@@ -1075,6 +1077,7 @@ l1_filter_kernel_f16h(FilterLaunch L)
     const bool second = (int)blockIdx.x >= L.nblocks0;
 #define SIDE(f) (second ? L.side[1].f : L.side[0].f)
     const int block_in_side = second ? (int)blockIdx.x - L.nblocks0 : (int)blockIdx.x;
+    const int side_blocks = second ? (int)gridDim.x - L.nblocks0 : L.nblocks0;
     const int p = SIDE(p), r = SIDE(r);
     const double *__restrict__ A = SIDE(A);
     const int lda = SIDE(lda);
@@ -1096,9 +1099,9 @@ l1_filter_kernel_f16h(FilterLaunch L)
         jend = range[1];
     }
     const float *f2glob = second ? L.frag32[1] : L.frag32[0];
-    if (jbeg + (int64_t)block_in_side * TPB * 16 >= jend) return;   // whole block idle (before any barrier)
+    if (jbeg + (int64_t)block_in_side * 16 >= jend) return;   // no tile for this block (before any barrier)
 
-    // ---- stage the basis (padded pairs and tiles are zero) -----------------
+    // ---- stage the basis once (padded pairs and tiles are zero) -----------
     for (int idx = threadIdx.x; idx < PPA * RT * 512; idx += kWavesPerBlock * 64) {
         const int i = idx & 7, ln = (idx >> 3) & 63, pm = idx >> 9;
         const int pp = pm / RT, mt = pm - pp * RT;
@@ -1128,193 +1131,226 @@ l1_filter_kernel_f16h(FilterLaunch L)
     const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const int lane = threadIdx.x & 63;
     const int g = lane >> 4, c = lane & 15;
-    const int tl = wave >> 1, half = wave & 1;
-    const int64_t tile = (int64_t)block_in_side * TPB + tl;
-    const int64_t j = jbeg + tile * 16 + c;
-    const int pp0 = half * NPH;                       // this half's first pair
-    const bool tile_in = jbeg + tile * 16 < jend;     // wave-uniform: the tile holds regressions
-    bool valid = j < jend;
-    int64_t roff = 0;
-    if (valid) {
-        const int64_t ri = reg_idx[j];
-        if (ri >= 0 && ri < reg_bound) roff = ri * reg_stride;
-        else valid = false;
-    }
-
-    // ---- x of this half, its partial norms, the state ---------------------
-    float u[2 * NPH][4], y[2 * NPH][4];
-    float xinf = 0.0f, xx = 0.0f;
-    floatx4 *xtile = xbuf + tile * PT * 64 + lane;
-#pragma unroll
-    for (int s = 0; s < 2 * NPH; ++s) {
-        const int t = 2 * pp0 + s;
-        floatx4 xv;
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-            const int64_t off = eoff[16 * t + 4 * g + v];
-            const float x = (valid && off >= 0) ? M[roff + off] : 0.0f;
-            xv[v] = x;
-            u[s][v] = x;
-            y[s][v] = 0.0f;
-            xinf = fmaxf(xinf, fabsf(x));
-            xx = fmaf(x, x, xx);
-        }
-        if (t < PT && tile_in) xtile[t * 64] = xv;
-    }
-    // norms over both halves, in half order
-    xch[(wave * NV + 0) * 64 + lane] = xinf;
-    xch[(wave * NV + 1) * 64 + lane] = xx;
-    __syncthreads();
-    {
-        const int w0 = wave & ~1;
-        xinf = fmaxf(xch[(w0 * NV + 0) * 64 + lane], xch[((w0 + 1) * NV + 0) * 64 + lane]);
-        xx = xch[(w0 * NV + 1) * 64 + lane] + xch[((w0 + 1) * NV + 1) * 64 + lane];
-    }
-    xinf = colmax(xinf);
-    xx = colsum(xx);
-    __syncthreads();                                  // the buffer is reused below
-
-    float beta = xx > 0.0f ? L.c.beta0_scale / sqrtf(xx) : 1.0f;
-    const float beta_bar = L.c.beta_max_scale * beta;
-    const float tol = L.c.eps * xinf;
-    bool done = !(valid && xinf > 0.0f);
-    int K = 0;
-    float inv_beta_prev = 0.0f, res_part = 0.0f;
-    floatx4 z[RT];
-#pragma unroll
-    for (int mt = 0; mt < RT; ++mt) z[mt] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
-
+    const int pp0 = wave * NPP;                       // this quarter's first pair
     const halfx8 *H1 = reinterpret_cast<const halfx8 *>(h1) + lane;
     const halfx8 *H2 = reinterpret_cast<const halfx8 *>(h2) + lane;
     const floatx4 *F2 = reinterpret_cast<const floatx4 *>(f2glob) + lane;
     float *mine = xch + wave * NV * 64 + lane;
-    const float *hx0 = xch + (wave & ~1) * NV * 64 + lane;      // half 0 of this tile
-    const float *hx1 = hx0 + NV * 64;                            // half 1
+    const float *all = xch + lane;
 
-    for (int k = 0;; ++k) {
-        // after max_iter steps only the pending stopping test is left
-        const bool last = k >= L.c.max_iter;
-        // partial w = A^T g over this half's pairs (K = 32 elements per MFMA)
-        floatx4 Wp[RT];
-#pragma unroll
-        for (int mt = 0; mt < RT; ++mt) Wp[mt] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
-#pragma unroll
-        for (int q = 0; q < NPH; ++q) {
-            float glo[4], ghi[4];
-#pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                glo[v] = __builtin_amdgcn_fmed3f(fmaf(beta, u[2 * q][v], y[2 * q][v]), -1.0f, 1.0f);
-                ghi[v] = __builtin_amdgcn_fmed3f(fmaf(beta, u[2 * q + 1][v], y[2 * q + 1][v]), -1.0f, 1.0f);
-            }
-            const halfx8 gb = pack8(glo, ghi);
-#pragma unroll
-            for (int mt = 0; mt < RT; ++mt) Wp[mt] = mfma16h(H1[((pp0 + q) * RT + mt) * 64], gb, Wp[mt]);
+#pragma unroll 1
+    for (int64_t tile = block_in_side; jbeg + tile * 16 < jend; tile += side_blocks) {
+        const int64_t j = jbeg + tile * 16 + c;
+        bool valid = j < jend;
+        int64_t roff = 0;
+        if (valid) {
+            const int64_t ri = reg_idx[j];
+            if (ri >= 0 && ri < reg_bound) roff = ri * reg_stride;
+            else valid = false;
         }
-#pragma unroll
-        for (int mt = 0; mt < RT; ++mt)
-#pragma unroll
-            for (int v = 0; v < 4; ++v) mine[(4 * mt + v) * 64] = Wp[mt][v];
-        mine[(NV - 1) * 64] = res_part;
-        __syncthreads();
-        floatx4 W[RT];
-#pragma unroll
-        for (int mt = 0; mt < RT; ++mt)
-#pragma unroll
-            for (int v = 0; v < 4; ++v) W[mt][v] = hx0[(4 * mt + v) * 64] + hx1[(4 * mt + v) * 64];
-        float res = colmax(fmaxf(hx0[(NV - 1) * 64], hx1[(NV - 1) * 64]));
-        // the stopping test of step k - 1
-        if (k > 0 && !done) {
-            ++K;
-            if (!(res * inv_beta_prev >= tol)) done = true;
-        }
-        // both tiles of the workgroup done (this barrier also ends the reads
-        // of the exchange buffer before the next step writes it)
-        if (last) break;
-        if (!__syncthreads_or(done ? 0 : 1)) break;
 
-        const float inv_beta = __builtin_amdgcn_rcpf(beta);
-        const float ib = done ? 0.0f : inv_beta;
+        // ---- x of this quarter, its partial norms, the state ---------------
+        float u[2 * NPP][4], y[2 * NPP][4];
+        float xinf = 0.0f, xx = 0.0f;
+        floatx4 *xtile = xbuf + tile * PT * 64 + lane;
 #pragma unroll
-        for (int mt = 0; mt < RT; ++mt)
-#pragma unroll
-            for (int v = 0; v < 4; ++v) z[mt][v] = fmaf(W[mt][v], ib, z[mt][v]);
-
-        // w as the FP16 B operand of v = A w, rank-tile pairs
-        halfx8 wb[RP];
-#pragma unroll
-        for (int rp = 0; rp < RP; ++rp) {
-            float lo[4], hi[4];
-#pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                lo[v] = W[2 * rp][v];
-                hi[v] = (2 * rp + 1 < RT) ? W[2 * rp + 1 < RT ? 2 * rp + 1 : 0][v] : 0.0f;
-            }
-            wb[rp] = pack8(lo, hi);
-        }
-        res_part = 0.0f;
-#pragma unroll
-        for (int s = 0; s < 2 * NPH; s += 2) {
-            floatx4 Va = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
-            floatx4 Vb = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
+        for (int s = 0; s < 2 * NPP; ++s) {
             const int t = 2 * pp0 + s;
+            floatx4 xv;
 #pragma unroll
-            for (int rp = 0; rp < RP; ++rp) {
-                Va = mfma16h(H2[(t * RP + rp) * 64], wb[rp], Va);
-                Vb = mfma16h(H2[((t + 1) * RP + rp) * 64], wb[rp], Vb);
+            for (int v = 0; v < 4; ++v) {
+                const int64_t off = eoff[16 * t + 4 * g + v];
+                const float x = (valid && off >= 0) ? M[roff + off] : 0.0f;
+                xv[v] = x;
+                u[s][v] = x;
+                y[s][v] = 0.0f;
+                xinf = fmaxf(xinf, fabsf(x));
+                xx = fmaf(x, x, xx);
             }
+            if (t < PT) xtile[t * 64] = xv;
+        }
+        // norms over the quarters, in quarter order
+        mine[0] = xinf;
+        mine[64] = xx;
+        __syncthreads();
+        xinf = all[0];
+        xx = all[64];
 #pragma unroll
-            for (int h = 0; h < 2; ++h) {
-                const floatx4 Vt = h ? Vb : Va;
+        for (int w = 1; w < kWavesPerBlock; ++w) {
+            xinf = fmaxf(xinf, all[w * NV * 64]);
+            xx += all[w * NV * 64 + 64];
+        }
+        xinf = colmax(xinf);
+        xx = colsum(xx);
+        __syncthreads();                              // the buffer is reused below
+
+        float beta = xx > 0.0f ? L.c.beta0_scale / sqrtf(xx) : 1.0f;
+        const float beta_bar = L.c.beta_max_scale * beta;
+        const float tol = L.c.eps * xinf;
+        bool done = !(valid && xinf > 0.0f);
+        int K = 0;
+        float inv_beta_prev = 0.0f, res_part = 0.0f;
+        floatx4 z[RT];
+#pragma unroll
+        for (int mt = 0; mt < RT; ++mt) z[mt] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
+
+        for (int k = 0;; ++k) {
+            // after max_iter steps only the pending stopping test is left
+            const bool last = k >= L.c.max_iter;
+            // partial w = A^T g over this quarter's pairs (K = 32 elements per
+            // MFMA); the quarter's fragments are read from LDS all at once, so
+            // their latency is paid once per contraction, not once per MFMA
+            halfx8 f1[NPP][RT];
+#pragma unroll
+            for (int q = 0; q < NPP; ++q)
+#pragma unroll
+                for (int mt = 0; mt < RT; ++mt) f1[q][mt] = H1[((pp0 + q) * RT + mt) * 64];
+            __builtin_amdgcn_sched_barrier(0);
+            floatx4 Wp[RT];
+#pragma unroll
+            for (int mt = 0; mt < RT; ++mt) Wp[mt] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+            for (int q = 0; q < NPP; ++q) {
+                float glo[4], ghi[4];
 #pragma unroll
                 for (int v = 0; v < 4; ++v) {
-                    const float yo = y[s + h][v];
-                    const float gg = __builtin_amdgcn_fmed3f(fmaf(beta, u[s + h][v], yo), -1.0f, 1.0f);
-                    const float yn = gg - Vt[v];
-                    res_part = fmaxf(res_part, fabsf(yn - yo));
-                    u[s + h][v] = fmaf(-Vt[v], ib, u[s + h][v]);
-                    y[s + h][v] = yn;
+                    glo[v] = __builtin_amdgcn_fmed3f(fmaf(beta, u[2 * q][v], y[2 * q][v]), -1.0f, 1.0f);
+                    ghi[v] = __builtin_amdgcn_fmed3f(fmaf(beta, u[2 * q + 1][v], y[2 * q + 1][v]), -1.0f, 1.0f);
                 }
+                const halfx8 gb = pack8(glo, ghi);
+#pragma unroll
+                for (int mt = 0; mt < RT; ++mt) Wp[mt] = mfma16h(f1[q][mt], gb, Wp[mt]);
             }
-        }
-        inv_beta_prev = inv_beta;
-        beta = fminf(L.c.rho * beta, beta_bar);
-
-        // FP32 residual refinement: u = x - A z from the input
-        if (L.c.refresh > 0 && ((k + 1) % L.c.refresh) == 0) {
-#pragma unroll
-            for (int s = 0; s < 2 * NPH; ++s) {
-                const int t = 2 * pp0 + s;
-                if (t < PT) {
-                    __builtin_amdgcn_sched_barrier(0);
-                    floatx4 Az = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
-#pragma unroll
-                    for (int mt = 0; mt < RT; ++mt) {
-                        const floatx4 a = F2[(t * RT + mt) * 64];
-#pragma unroll
-                        for (int v = 0; v < 4; ++v)
-                            if (4 * mt + v < KS) Az = mfma4(a[v], z[mt][v], Az);
-                    }
-                    floatx4 xv = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
-                    if (tile_in) xv = xtile[t * 64];          // (no x slot for an idle tile)
-#pragma unroll
-                    for (int v = 0; v < 4; ++v) u[s][v] = xv[v] - Az[v];
-                }
-            }
-        }
-    }
-
-    if (half == 0 && j < jend) {
-        if (valid) {
 #pragma unroll
             for (int mt = 0; mt < RT; ++mt)
 #pragma unroll
+                for (int v = 0; v < 4; ++v) mine[(4 * mt + v) * 64] = Wp[mt][v];
+            mine[(NV - 1) * 64] = res_part;
+            __syncthreads();
+            floatx4 W[RT];
+            float res = all[(NV - 1) * 64];
+#pragma unroll
+            for (int mt = 0; mt < RT; ++mt)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) W[mt][v] = all[(4 * mt + v) * 64];
+#pragma unroll
+            for (int w = 1; w < kWavesPerBlock; ++w) {
+#pragma unroll
+                for (int mt = 0; mt < RT; ++mt)
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) W[mt][v] += all[(w * NV + 4 * mt + v) * 64];
+                res = fmaxf(res, all[(w * NV + NV - 1) * 64]);
+            }
+            res = colmax(res);
+            __syncthreads();                          // every wave has read the partials
+            // the stopping test of step k - 1
+            if (k > 0 && !done) {
+                ++K;
+                if (!(res * inv_beta_prev >= tol)) done = true;
+            }
+            if (last || !__any(!done)) break;         // the same in every wave of the block
+
+            // fragments of v = A w for this quarter's tiles, read all at once
+            halfx8 f2[2 * NPP][RP];
+#pragma unroll
+            for (int s = 0; s < 2 * NPP; ++s)
+#pragma unroll
+                for (int rp = 0; rp < RP; ++rp) f2[s][rp] = H2[((2 * pp0 + s) * RP + rp) * 64];
+            __builtin_amdgcn_sched_barrier(0);
+            const float inv_beta = __builtin_amdgcn_rcpf(beta);
+            const float ib = done ? 0.0f : inv_beta;
+#pragma unroll
+            for (int mt = 0; mt < RT; ++mt)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) z[mt][v] = fmaf(W[mt][v], ib, z[mt][v]);
+
+            // w as the FP16 B operand of v = A w, rank-tile pairs
+            halfx8 wb[RP];
+#pragma unroll
+            for (int rp = 0; rp < RP; ++rp) {
+                float lo[4], hi[4];
+#pragma unroll
                 for (int v = 0; v < 4; ++v) {
-                    const int kk = 16 * mt + 4 * v + g;
-                    if (kk < r) Zout[kk + j * ldz] = z[mt][v];
+                    lo[v] = W[2 * rp][v];
+                    hi[v] = (2 * rp + 1 < RT) ? W[2 * rp + 1 < RT ? 2 * rp + 1 : 0][v] : 0.0f;
                 }
+                wb[rp] = pack8(lo, hi);
+            }
+            res_part = 0.0f;
+#pragma unroll
+            for (int s = 0; s < 2 * NPP; s += 2) {
+                floatx4 Va = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
+                floatx4 Vb = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+                for (int rp = 0; rp < RP; ++rp) {
+                    Va = mfma16h(f2[s][rp], wb[rp], Va);
+                    Vb = mfma16h(f2[s + 1][rp], wb[rp], Vb);
+                }
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    const floatx4 Vt = h ? Vb : Va;
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) {
+                        const float yo = y[s + h][v];
+                        const float gg = __builtin_amdgcn_fmed3f(fmaf(beta, u[s + h][v], yo), -1.0f, 1.0f);
+                        const float yn = gg - Vt[v];
+                        res_part = fmaxf(res_part, fabsf(yn - yo));
+                        u[s + h][v] = fmaf(-Vt[v], ib, u[s + h][v]);
+                        y[s + h][v] = yn;
+                    }
+                }
+            }
+            inv_beta_prev = inv_beta;
+            beta = fminf(L.c.rho * beta, beta_bar);
+
+            // FP32 residual refinement: u = x - A z from the input, two element
+            // tiles at a time (their fragments loaded together, two chains)
+            if (L.c.refresh > 0 && ((k + 1) % L.c.refresh) == 0) {
+#pragma unroll
+                for (int s = 0; s < 2 * NPP; s += 2) {
+                    const int t = 2 * pp0 + s;
+                    if (t < PT) {                     // wave-uniform
+                        const bool two = t + 1 < PT;
+                        floatx4 fa[2][RT];
+#pragma unroll
+                        for (int mt = 0; mt < RT; ++mt) {
+                            fa[0][mt] = F2[(t * RT + mt) * 64];
+                            fa[1][mt] = two ? F2[((t + 1) * RT + mt) * 64] : floatx4{0.0f, 0.0f, 0.0f, 0.0f};
+                        }
+                        floatx4 Az[2] = {floatx4{0.0f, 0.0f, 0.0f, 0.0f}, floatx4{0.0f, 0.0f, 0.0f, 0.0f}};
+#pragma unroll
+                        for (int mt = 0; mt < RT; ++mt)
+#pragma unroll
+                            for (int v = 0; v < 4; ++v)
+                                if (4 * mt + v < KS)
+#pragma unroll
+                                    for (int h = 0; h < 2; ++h) Az[h] = mfma4(fa[h][mt][v], z[mt][v], Az[h]);
+                        const floatx4 x0 = xtile[t * 64];
+#pragma unroll
+                        for (int v = 0; v < 4; ++v) u[s][v] = x0[v] - Az[0][v];
+                        if (two) {
+                            const floatx4 x1 = xtile[(t + 1) * 64];
+#pragma unroll
+                            for (int v = 0; v < 4; ++v) u[s + 1][v] = x1[v] - Az[1][v];
+                        }
+                    }
+                }
+            }
         }
-        if (iters && g == 0)
-            iters[j] = !valid ? INT_MIN : (done ? K : -L.c.max_iter);
+
+        if (wave == 0 && j < jend) {
+            if (valid) {
+#pragma unroll
+                for (int mt = 0; mt < RT; ++mt)
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) {
+                        const int kk = 16 * mt + 4 * v + g;
+                        if (kk < r) Zout[kk + j * ldz] = z[mt][v];
+                    }
+            }
+            if (iters && g == 0)
+                iters[j] = !valid ? INT_MIN : (done ? K : -L.c.max_iter);
+        }
     }
 }
 
@@ -1346,14 +1382,14 @@ int launch_pt_ks(rpca_ctx *ctx, const FilterLaunch &L, int nblocks, bool split, 
     if (split) return set_status(ctx, RPCA_ERR_UNSUPPORTED, "filter: split form not built for this class");
     if constexpr (half_form(PT)) {
         if (L.c.precision == 1) {
-            // half-tile variant: two tiles per workgroup, refresh fragments in HBM
-            const size_t lds = lds_bytes_f16h(PT, KS);
+            // quarter-tile persistent variant: refresh fragments in HBM
+            const size_t lds = lds_bytes_f16q(PT, KS);
             // once per process (thread-safe static initialisation), before any
             // launch can be captured in a graph
             static const hipError_t attr = hipFuncSetAttribute(
-                (const void *)l1_filter_kernel_f16h<PT, KS>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+                (const void *)l1_filter_kernel_f16q<PT, KS>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
             RPCA_HIP_TRY(ctx, attr);
-            hipLaunchKernelGGL((l1_filter_kernel_f16h<PT, KS>), dim3(nblocks), dim3(kWavesPerBlock * 64),
+            hipLaunchKernelGGL((l1_filter_kernel_f16q<PT, KS>), dim3(nblocks), dim3(kWavesPerBlock * 64),
                                lds, stream, L);
             RPCA_HIP_TRY(ctx, hipGetLastError());
             return RPCA_OK;

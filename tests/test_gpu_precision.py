@@ -100,14 +100,14 @@ def test_precision_ragged(R, ctx, m, n, r):
     assert relF(host_matrix(S, m), res.S) <= REL_TOL
 
 
-# p = 300, 410, 500 (PT = 19, 26, 32): the half-tile form (two waves per
-# 16-regression tile, two tiles per workgroup); an odd tile count leaves the
-# second tile of the last workgroup idle
+# p = 300, 410, 500 (PT = 19, 26, 32): the quarter-tile persistent form (four
+# waves per 16-regression tile, each workgroup taking the tiles of its side in
+# turn); ragged tile counts leave some workgroups one tile fewer
 @pytest.mark.parametrize("m,n,r", [(2100, 1900, 30), (2600, 2333, 41), (2700, 2517, 50)])
-def test_precision_half_tile_form(R, ctx, m, n, r):
+def test_precision_quarter_tile_form(R, ctx, m, n, r):
     import torch
     pr, I, J, res = small_case(m, n, r, 0.05, 7 + r)
-    say(f"precision half-tile form m={m} n={n} r={r} p={10 * r}")
+    say(f"precision quarter-tile form m={m} n={n} r={r} p={10 * r}")
     Md = dev_matrix(pr.M)
     L = torch.full_like(Md, float("nan"))
     S = torch.full_like(Md, float("nan"))
@@ -123,7 +123,7 @@ def test_precision_half_tile_form(R, ctx, m, n, r):
     # kernel); the step count is reported, not bounded
     its = info.filt_iters_total / ((m - 10 * r) + (n - 10 * r))
     k_or = np.concatenate([res.col_iters, res.row_iters]).mean()
-    say(f"precision half-tile form: mean steps {its:.2f}, oracle {k_or:.2f}")
+    say(f"precision quarter-tile form: mean steps {its:.2f}, oracle {k_or:.2f}")
 
 
 def test_precision_c3_full_size_sampled(R, ctx):
