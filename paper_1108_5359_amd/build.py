@@ -60,7 +60,12 @@ def build(jobs: int | None = None) -> pathlib.Path:
         for pt in sorted(FILTER_PT, reverse=True):     # largest first: they take longest
             obj = BUILD / f"filter_inst_pt{pt}.o"
             objs.append(obj)
-            futs.append(ex.submit(_compile, CSRC / "filter_inst.hip", obj, (f"-DRPCA_PT={pt}",)))
+            # MFMA results in arch VGPRs: the quarter-tile precision kernel
+            # otherwise keeps its accumulators in acc VGPRs and spends one
+            # VALU move per value reading them back (no other filter kernel
+            # changes: they already use arch VGPRs or need both files)
+            futs.append(ex.submit(_compile, CSRC / "filter_inst.hip", obj,
+                                  (f"-DRPCA_PT={pt}", "-mllvm", "-amdgpu-mfma-vgpr-form")))
         for s in SOURCES:
             obj = BUILD / (s.replace(".", "_") + ".o")
             objs.append(obj)

@@ -1048,7 +1048,10 @@ struct QuarterShape {
     static constexpr int NPP = (PP + 3) / 4;         // pairs per quarter (the last may pad)
     static constexpr int PPA = 4 * NPP;              // pairs staged (padded)
     static constexpr int TA = 2 * PPA;               // element tiles staged (padded)
-    static constexpr int NV = 4 * RT + 1;            // floats a lane publishes per step
+    // floats a lane publishes per step: its values of w for the real ranks
+    // (register v of rank tile mt holds rank 16 mt + 4 v + g: real while
+    // 4 mt + v < KS), then the residual
+    static constexpr int NV = KS + 1;
 };
 
 constexpr bool half_form(int PT) { return PT >= 19; }
@@ -1056,7 +1059,7 @@ constexpr bool half_form(int PT) { return PT >= 19; }
 inline size_t lds_bytes_f16q(int PT, int KS)
 {
     const int RT = (KS + 3) / 4, RP = (RT + 1) / 2, PP = (PT + 1) / 2, NPP = (PP + 3) / 4;
-    const int PPA = 4 * NPP, TA = 2 * PPA, NV = 4 * RT + 1;
+    const int PPA = 4 * NPP, TA = 2 * PPA, NV = KS + 1;
     return (size_t)PPA * RT * 512 * sizeof(_Float16) + (size_t)TA * RP * 512 * sizeof(_Float16) +
            (size_t)TA * 16 * sizeof(int64_t) + (size_t)kWavesPerBlock * NV * 64 * sizeof(float);
 }
@@ -1209,22 +1212,25 @@ l1_filter_kernel_f16q(FilterLaunch L)
             floatx4 Wp[RT];
 #pragma unroll
             for (int mt = 0; mt < RT; ++mt) Wp[mt] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
+            // g of this step, kept for the dual update (u, y do not change in between)
+            float gk[2 * NPP][4];
 #pragma unroll
             for (int q = 0; q < NPP; ++q) {
-                float glo[4], ghi[4];
 #pragma unroll
-                for (int v = 0; v < 4; ++v) {
-                    glo[v] = __builtin_amdgcn_fmed3f(fmaf(beta, u[2 * q][v], y[2 * q][v]), -1.0f, 1.0f);
-                    ghi[v] = __builtin_amdgcn_fmed3f(fmaf(beta, u[2 * q + 1][v], y[2 * q + 1][v]), -1.0f, 1.0f);
-                }
-                const halfx8 gb = pack8(glo, ghi);
+                for (int h = 0; h < 2; ++h)
+#pragma unroll
+                    for (int v = 0; v < 4; ++v)
+                        gk[2 * q + h][v] =
+                            __builtin_amdgcn_fmed3f(fmaf(beta, u[2 * q + h][v], y[2 * q + h][v]), -1.0f, 1.0f);
+                const halfx8 gb = pack8(gk[2 * q], gk[2 * q + 1]);
 #pragma unroll
                 for (int mt = 0; mt < RT; ++mt) Wp[mt] = mfma16h(f1[q][mt], gb, Wp[mt]);
             }
 #pragma unroll
             for (int mt = 0; mt < RT; ++mt)
 #pragma unroll
-                for (int v = 0; v < 4; ++v) mine[(4 * mt + v) * 64] = Wp[mt][v];
+                for (int v = 0; v < 4; ++v)
+                    if (4 * mt + v < KS) mine[(4 * mt + v) * 64] = Wp[mt][v];
             mine[(NV - 1) * 64] = res_part;
             __syncthreads();
             floatx4 W[RT];
@@ -1232,13 +1238,14 @@ l1_filter_kernel_f16q(FilterLaunch L)
 #pragma unroll
             for (int mt = 0; mt < RT; ++mt)
 #pragma unroll
-                for (int v = 0; v < 4; ++v) W[mt][v] = all[(4 * mt + v) * 64];
+                for (int v = 0; v < 4; ++v) W[mt][v] = (4 * mt + v < KS) ? all[(4 * mt + v) * 64] : 0.0f;
 #pragma unroll
             for (int w = 1; w < kWavesPerBlock; ++w) {
 #pragma unroll
                 for (int mt = 0; mt < RT; ++mt)
 #pragma unroll
-                    for (int v = 0; v < 4; ++v) W[mt][v] += all[(w * NV + 4 * mt + v) * 64];
+                    for (int v = 0; v < 4; ++v)
+                        if (4 * mt + v < KS) W[mt][v] += all[(w * NV + 4 * mt + v) * 64];
                 res = fmaxf(res, all[(w * NV + NV - 1) * 64]);
             }
             res = colmax(res);
@@ -1250,19 +1257,13 @@ l1_filter_kernel_f16q(FilterLaunch L)
             }
             if (last || !__any(!done)) break;         // the same in every wave of the block
 
-            // fragments of v = A w for this quarter's tiles, read all at once
-            halfx8 f2[2 * NPP][RP];
-#pragma unroll
-            for (int s = 0; s < 2 * NPP; ++s)
-#pragma unroll
-                for (int rp = 0; rp < RP; ++rp) f2[s][rp] = H2[((2 * pp0 + s) * RP + rp) * 64];
-            __builtin_amdgcn_sched_barrier(0);
             const float inv_beta = __builtin_amdgcn_rcpf(beta);
             const float ib = done ? 0.0f : inv_beta;
 #pragma unroll
             for (int mt = 0; mt < RT; ++mt)
 #pragma unroll
-                for (int v = 0; v < 4; ++v) z[mt][v] = fmaf(W[mt][v], ib, z[mt][v]);
+                for (int v = 0; v < 4; ++v)
+                    if (4 * mt + v < KS) z[mt][v] = fmaf(W[mt][v], ib, z[mt][v]);
 
             // w as the FP16 B operand of v = A w, rank-tile pairs
             halfx8 wb[RP];
@@ -1277,14 +1278,26 @@ l1_filter_kernel_f16q(FilterLaunch L)
                 wb[rp] = pack8(lo, hi);
             }
             res_part = 0.0f;
+            // fragments of v = A w, read from LDS in batches of KB tile pairs
+            constexpr int KB = NPP >= 4 ? NPP / 2 : NPP;
+            halfx8 f2[2 * KB][RP];
 #pragma unroll
             for (int s = 0; s < 2 * NPP; s += 2) {
+                if ((s / 2) % KB == 0) {
+#pragma unroll
+                    for (int b = 0; b < 2 * KB; ++b)
+#pragma unroll
+                        for (int rp = 0; rp < RP; ++rp)
+                            f2[b][rp] = (s + b < 2 * NPP) ? H2[((2 * pp0 + s + b) * RP + rp) * 64] : f2[b][rp];
+                    __builtin_amdgcn_sched_barrier(0);
+                }
+                const int sb = s % (2 * KB);
                 floatx4 Va = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
                 floatx4 Vb = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
                 for (int rp = 0; rp < RP; ++rp) {
-                    Va = mfma16h(f2[s][rp], wb[rp], Va);
-                    Vb = mfma16h(f2[s + 1][rp], wb[rp], Vb);
+                    Va = mfma16h(f2[sb][rp], wb[rp], Va);
+                    Vb = mfma16h(f2[sb + 1][rp], wb[rp], Vb);
                 }
 #pragma unroll
                 for (int h = 0; h < 2; ++h) {
@@ -1292,8 +1305,7 @@ l1_filter_kernel_f16q(FilterLaunch L)
 #pragma unroll
                     for (int v = 0; v < 4; ++v) {
                         const float yo = y[s + h][v];
-                        const float gg = __builtin_amdgcn_fmed3f(fmaf(beta, u[s + h][v], yo), -1.0f, 1.0f);
-                        const float yn = gg - Vt[v];
+                        const float yn = gk[s + h][v] - Vt[v];
                         res_part = fmaxf(res_part, fabsf(yn - yo));
                         u[s + h][v] = fmaf(-Vt[v], ib, u[s + h][v]);
                         y[s + h][v] = yn;
@@ -1394,8 +1406,7 @@ int launch_pt_ks(rpca_ctx *ctx, const FilterLaunch &L, int nblocks, bool split, 
             RPCA_HIP_TRY(ctx, hipGetLastError());
             return RPCA_OK;
         }
-    }
-    if (L.c.precision == 1) {
+    } else if (L.c.precision == 1) {
         // the FP32 refresh fragments live in HBM when the launcher prepared them
         const size_t lds = lds_bytes_f16(PT, KS, L.frag32[0] == nullptr);
         static const hipError_t attr = hipFuncSetAttribute(
