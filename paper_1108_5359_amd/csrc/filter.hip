@@ -74,7 +74,7 @@ bool filter_supported(rpca_ctx *ctx, int p, int r, int precision)
     const int PT = pick_pt(p, precision), KS = pick_ks(r);
     if (PT < 0 || KS < 0) return false;
     if (precision == 1)
-        return (half_form(PT) ? lds_bytes_f16q(PT, KS) : lds_bytes_f16(PT, KS, false)) <= lds_limit(ctx);
+        return (half_form(PT) ? lds_bytes_f16q(PT, KS, 1) : lds_bytes_f16(PT, KS, false)) <= lds_limit(ctx);
     return lds_bytes(PT, KS) <= lds_limit(ctx);
 }
 
@@ -160,10 +160,17 @@ int launch_filter(rpca_ctx *ctx, const FilterSide *sides, int nsides, const Filt
         }
     }
     // quarter-tile precision form: persistent, one workgroup per CU, the CUs
-    // shared between the sides in proportion to their tiles
+    // shared between the sides in proportion to their tiles; two tiles per
+    // workgroup where their LDS fits and the element indices fit 32 bits
     const bool quarter = c.precision == 1 && half_form(PT);
-    int64_t all_tiles = 0;
-    for (int s = 0; s < nsides; ++s) all_tiles += (sides[s].nreg + 15) / 16;
+    L.qtiles = 1;
+    if (quarter && lds_bytes_f16q(PT, KS, 2) <= lds_limit(ctx)) {
+        bool fits = true;
+        for (int s = 0; s < nsides; ++s) fits = fits && sides[s].elem_bound <= INT_MAX;
+        if (fits) L.qtiles = 2;
+    }
+    int64_t all_units = 0;
+    for (int s = 0; s < nsides; ++s) all_units += (sides[s].nreg + 16 * L.qtiles - 1) / (16 * L.qtiles);
     const int64_t ncu = ctx->num_cu > 0 ? ctx->num_cu : 256;
     int nblocks = 0;
     for (int s = 0; s < nsides; ++s) {
@@ -172,7 +179,9 @@ int launch_filter(rpca_ctx *ctx, const FilterSide *sides, int nsides, const Filt
         const int64_t tiles = (sides[s].nreg + 15) / 16;
         int64_t blocks;
         if (quarter) {
-            blocks = std::min<int64_t>(tiles, std::max<int64_t>(1, (ncu * tiles + all_tiles / 2) / std::max<int64_t>(all_tiles, 1)));
+            // units of qtiles tiles
+            const int64_t units = (sides[s].nreg + 16 * L.qtiles - 1) / (16 * L.qtiles);
+            blocks = std::min<int64_t>(units, std::max<int64_t>(1, (ncu * units + all_units / 2) / std::max<int64_t>(all_units, 1)));
         } else {
             // tiles per workgroup: 1 (split form) or 4
             const int64_t per = split ? 1 : kWavesPerBlock;

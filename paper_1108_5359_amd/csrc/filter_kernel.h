@@ -49,6 +49,7 @@ struct FilterLaunch {
     FilterSide side[2];
     const float *frag32[2];   // precision form: FP32 refresh fragments in HBM (or null = in LDS)
     int32_t nblocks0;         // blocks of side 0; the rest belong to side 1
+    int32_t qtiles;           // precision form, p > 288: tiles per workgroup (1 or 2)
     FilterConsts c;
 };
 
@@ -1028,8 +1029,9 @@ l1_filter_kernel_f16(FilterLaunch L)
 // wave holding all PT element tiles of its 16 regressions needs 8 PT floats of
 // u, y per lane (256 at p = 512: the whole register file, so the tile kernel
 // spills, and the basis fragments of a contraction cannot be kept in flight).
-// Here the four waves of a workgroup serve one 16-regression tile together,
-// each holding a quarter of the element-tile pairs.  The workgroup stages the
+// Here four waves serve one 16-regression tile together, each holding a
+// quarter of the element-tile pairs; a workgroup serves one or two tiles
+// (TPB, below) that step together.  The workgroup stages the
 // FP16 basis fragments in LDS once and then takes the tiles of its side in
 // turn (its index, plus the side's workgroup count, ...), so the staging is
 // paid once per workgroup, not once per tile.  Per step each wave contracts its
@@ -1038,7 +1040,8 @@ l1_filter_kernel_f16(FilterLaunch L)
 // in quarter order (identical w and z in all four waves, and the same bits for
 // a regression wherever it sits), and a second barrier frees the buffer.  The
 // stopping test of a step is taken one step later; a stopped regression only
-// stops moving z and u.  The refresh reads its FP32 fragments from HBM.
+// stops moving z and u, and a finished tile next to a moving one steps on
+// frozen.  The refresh reads its FP32 fragments from HBM.
 // ---------------------------------------------------------------------------
 template <int PT, int KS>
 struct QuarterShape {
@@ -1056,26 +1059,35 @@ struct QuarterShape {
 
 constexpr bool half_form(int PT) { return PT >= 19; }
 
-inline size_t lds_bytes_f16q(int PT, int KS)
+// TPB tiles per workgroup (4 TPB waves).  With two, each SIMD holds two
+// waves (of different tiles) that hide each other's latencies; the element
+// indices are then staged as 32-bit values so that the fragments, indices
+// and both tiles' exchange buffers fit in 160 KB.
+inline size_t lds_bytes_f16q(int PT, int KS, int TPB)
 {
     const int RT = (KS + 3) / 4, RP = (RT + 1) / 2, PP = (PT + 1) / 2, NPP = (PP + 3) / 4;
     const int PPA = 4 * NPP, TA = 2 * PPA, NV = KS + 1;
     return (size_t)PPA * RT * 512 * sizeof(_Float16) + (size_t)TA * RP * 512 * sizeof(_Float16) +
-           (size_t)TA * 16 * sizeof(int64_t) + (size_t)kWavesPerBlock * NV * 64 * sizeof(float);
+           (size_t)TA * 16 * (TPB == 2 ? sizeof(int32_t) : sizeof(int64_t)) +
+           (size_t)TPB * kWavesPerBlock * NV * 64 * sizeof(float);
 }
 
-template <int PT, int KS>
-__global__ void __launch_bounds__(kWavesPerBlock * 64)
+template <int PT, int KS, int TPB>
+__global__ void __launch_bounds__(TPB * kWavesPerBlock * 64)
 l1_filter_kernel_f16q(FilterLaunch L)
 {
     using Sh = QuarterShape<PT, KS>;
     constexpr int RT = Sh::RT, RP = Sh::RP, NPP = Sh::NPP, PPA = Sh::PPA, TA = Sh::TA;
     constexpr int NV = Sh::NV;
+    constexpr int NT = TPB * kWavesPerBlock * 64;    // threads of the workgroup
+    // element index of the gathered x: offset (TPB = 1) or 32-bit row/column
+    // index, scaled by the stride when read (TPB = 2)
+    using EIdx = typename std::conditional<TPB == 2, int32_t, int64_t>::type;
     extern __shared__ __align__(16) unsigned char lds_raw[];
     _Float16 *h1 = reinterpret_cast<_Float16 *>(lds_raw);              // [PPA][RT][64][8]
     _Float16 *h2 = h1 + PPA * RT * 512;                                  // [TA][RP][64][8]
-    int64_t *eoff = reinterpret_cast<int64_t *>(h2 + TA * RP * 512);    // [TA*16]
-    float *xch = reinterpret_cast<float *>(eoff + TA * 16);              // [4 waves][NV][64]
+    EIdx *eoff = reinterpret_cast<EIdx *>(h2 + TA * RP * 512);          // [TA*16]
+    float *xch = reinterpret_cast<float *>(eoff + TA * 16);              // [TPB][4 waves][NV][64]
 
     const bool second = (int)blockIdx.x >= L.nblocks0;
 #define SIDE(f) (second ? L.side[1].f : L.side[0].f)
@@ -1102,10 +1114,10 @@ l1_filter_kernel_f16q(FilterLaunch L)
         jend = range[1];
     }
     const float *f2glob = second ? L.frag32[1] : L.frag32[0];
-    if (jbeg + (int64_t)block_in_side * 16 >= jend) return;   // no tile for this block (before any barrier)
+    if (jbeg + (int64_t)block_in_side * TPB * 16 >= jend) return;   // no tile for this block (before any barrier)
 
     // ---- stage the basis once (padded pairs and tiles are zero) -----------
-    for (int idx = threadIdx.x; idx < PPA * RT * 512; idx += kWavesPerBlock * 64) {
+    for (int idx = threadIdx.x; idx < PPA * RT * 512; idx += NT) {
         const int i = idx & 7, ln = (idx >> 3) & 63, pm = idx >> 9;
         const int pp = pm / RT, mt = pm - pp * RT;
         const int g = ln >> 4, c = ln & 15;
@@ -1113,7 +1125,7 @@ l1_filter_kernel_f16q(FilterLaunch L)
         const int k = 16 * mt + 4 * (c & 3) + (c >> 2);
         h1[idx] = (_Float16)((e < p && k < r) ? A[e + (int64_t)k * lda] : 0.0);
     }
-    for (int idx = threadIdx.x; idx < TA * RP * 512; idx += kWavesPerBlock * 64) {
+    for (int idx = threadIdx.x; idx < TA * RP * 512; idx += NT) {
         const int i = idx & 7, ln = (idx >> 3) & 63, tr = idx >> 9;
         const int t = tr / RP, rp = tr - t * RP;
         const int g = ln >> 4, c = ln & 15;
@@ -1121,28 +1133,33 @@ l1_filter_kernel_f16q(FilterLaunch L)
         const int k = 16 * (2 * rp + (i >> 2)) + 4 * (i & 3) + g;
         h2[idx] = (_Float16)((e < p && k < r) ? A[e + (int64_t)k * lda] : 0.0);
     }
-    for (int e = threadIdx.x; e < TA * 16; e += kWavesPerBlock * 64) {
+    for (int e = threadIdx.x; e < TA * 16; e += NT) {
         int64_t off = -1;
         if (e < p) {
             const int64_t ei = elem_idx[e];
-            if (ei >= 0 && ei < elem_bound) off = ei * elem_stride;
+            // (TPB = 2: the launcher checked that the bound fits 32 bits)
+            if (ei >= 0 && ei < elem_bound) off = TPB == 2 ? ei : ei * elem_stride;
         }
-        eoff[e] = off;
+        eoff[e] = (EIdx)off;
     }
     __syncthreads();
 
     const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const int lane = threadIdx.x & 63;
     const int g = lane >> 4, c = lane & 15;
-    const int pp0 = wave * NPP;                       // this quarter's first pair
+    const int tl = wave / kWavesPerBlock;             // this wave's tile of the block
+    const int part = wave % kWavesPerBlock;           // its quarter
+    const int pp0 = part * NPP;                       // this quarter's first pair
     const halfx8 *H1 = reinterpret_cast<const halfx8 *>(h1) + lane;
     const halfx8 *H2 = reinterpret_cast<const halfx8 *>(h2) + lane;
     const floatx4 *F2 = reinterpret_cast<const floatx4 *>(f2glob) + lane;
     float *mine = xch + wave * NV * 64 + lane;
-    const float *all = xch + lane;
+    const float *all = xch + tl * kWavesPerBlock * NV * 64 + lane;   // this tile's quarters
 
 #pragma unroll 1
-    for (int64_t tile = block_in_side; jbeg + tile * 16 < jend; tile += side_blocks) {
+    for (int64_t tb = block_in_side; jbeg + tb * TPB * 16 < jend; tb += side_blocks) {
+        const int64_t tile = tb * TPB + tl;
+        const bool tile_in = jbeg + tile * 16 < jend;      // wave-uniform: the tile holds regressions
         const int64_t j = jbeg + tile * 16 + c;
         bool valid = j < jend;
         int64_t roff = 0;
@@ -1162,15 +1179,16 @@ l1_filter_kernel_f16q(FilterLaunch L)
             floatx4 xv;
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
-                const int64_t off = eoff[16 * t + 4 * g + v];
-                const float x = (valid && off >= 0) ? M[roff + off] : 0.0f;
+                const int64_t e = eoff[16 * t + 4 * g + v];
+                const int64_t off = TPB == 2 ? e * elem_stride : e;
+                const float x = (valid && e >= 0) ? M[roff + off] : 0.0f;
                 xv[v] = x;
                 u[s][v] = x;
                 y[s][v] = 0.0f;
                 xinf = fmaxf(xinf, fabsf(x));
                 xx = fmaf(x, x, xx);
             }
-            if (t < PT) xtile[t * 64] = xv;
+            if (t < PT && tile_in) xtile[t * 64] = xv;   // (no x slot for an idle tile)
         }
         // norms over the quarters, in quarter order
         mine[0] = xinf;
@@ -1231,7 +1249,10 @@ l1_filter_kernel_f16q(FilterLaunch L)
 #pragma unroll
                 for (int v = 0; v < 4; ++v)
                     if (4 * mt + v < KS) mine[(4 * mt + v) * 64] = Wp[mt][v];
-            mine[(NV - 1) * 64] = res_part;
+            // the residual partial, or -1 for a stopped regression (its
+            // residual is not used again): the sign tells the block which
+            // regressions were still moving after the previous test
+            mine[(NV - 1) * 64] = done ? -1.0f : res_part;
             __syncthreads();
             floatx4 W[RT];
             float res = all[(NV - 1) * 64];
@@ -1248,14 +1269,30 @@ l1_filter_kernel_f16q(FilterLaunch L)
                         if (4 * mt + v < KS) W[mt][v] += all[(w * NV + 4 * mt + v) * 64];
                 res = fmaxf(res, all[(w * NV + NV - 1) * 64]);
             }
+            // two tiles: whether any regression of the block was still moving
+            // after the previous test, from the flags both tiles published
+            // (every wave reads the same values: the same in every wave)
+            bool live_prev = true;
+            if constexpr (TPB == 2) {
+                const float f0 = xch[(NV - 1) * 64 + lane];
+                const float f1 = xch[(kWavesPerBlock * NV + NV - 1) * 64 + lane];
+                live_prev = __any(f0 >= 0.0f || f1 >= 0.0f);
+            }
             res = colmax(res);
-            __syncthreads();                          // every wave has read the partials
             // the stopping test of step k - 1
             if (k > 0 && !done) {
                 ++K;
                 if (!(res * inv_beta_prev >= tol)) done = true;
             }
-            if (last || !__any(!done)) break;         // the same in every wave of the block
+            __syncthreads();                          // every wave has read the partials
+            if constexpr (TPB == 1) {
+                if (last || !__any(!done)) break;     // the same in every wave of the block
+            } else {
+                // a finished tile keeps stepping frozen, as a finished
+                // regression does; the block stops one step after its last
+                // regression
+                if (last || !live_prev) break;
+            }
 
             const float inv_beta = __builtin_amdgcn_rcpf(beta);
             const float ib = done ? 0.0f : inv_beta;
@@ -1337,11 +1374,12 @@ l1_filter_kernel_f16q(FilterLaunch L)
                                 if (4 * mt + v < KS)
 #pragma unroll
                                     for (int h = 0; h < 2; ++h) Az[h] = mfma4(fa[h][mt][v], z[mt][v], Az[h]);
-                        const floatx4 x0 = xtile[t * 64];
+                        const floatx4 zero4 = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
+                        const floatx4 x0 = tile_in ? xtile[t * 64] : zero4;
 #pragma unroll
                         for (int v = 0; v < 4; ++v) u[s][v] = x0[v] - Az[0][v];
                         if (two) {
-                            const floatx4 x1 = xtile[(t + 1) * 64];
+                            const floatx4 x1 = tile_in ? xtile[(t + 1) * 64] : zero4;
 #pragma unroll
                             for (int v = 0; v < 4; ++v) u[s + 1][v] = x1[v] - Az[1][v];
                         }
@@ -1350,7 +1388,7 @@ l1_filter_kernel_f16q(FilterLaunch L)
             }
         }
 
-        if (wave == 0 && j < jend) {
+        if (part == 0 && j < jend) {
             if (valid) {
 #pragma unroll
                 for (int mt = 0; mt < RT; ++mt)
@@ -1394,17 +1432,23 @@ int launch_pt_ks(rpca_ctx *ctx, const FilterLaunch &L, int nblocks, bool split, 
     if (split) return set_status(ctx, RPCA_ERR_UNSUPPORTED, "filter: split form not built for this class");
     if constexpr (half_form(PT)) {
         if (L.c.precision == 1) {
-            // quarter-tile persistent variant: refresh fragments in HBM
-            const size_t lds = lds_bytes_f16q(PT, KS);
-            // once per process (thread-safe static initialisation), before any
-            // launch can be captured in a graph
-            static const hipError_t attr = hipFuncSetAttribute(
-                (const void *)l1_filter_kernel_f16q<PT, KS>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-            RPCA_HIP_TRY(ctx, attr);
-            hipLaunchKernelGGL((l1_filter_kernel_f16q<PT, KS>), dim3(nblocks), dim3(kWavesPerBlock * 64),
-                               lds, stream, L);
-            RPCA_HIP_TRY(ctx, hipGetLastError());
-            return RPCA_OK;
+            // quarter-tile persistent variant: refresh fragments in HBM; one
+            // or two tiles per workgroup (chosen by the launcher)
+            auto go = [&](auto tpb_tag) -> int {
+                constexpr int TPB = decltype(tpb_tag)::value;
+                const size_t lds = lds_bytes_f16q(PT, KS, TPB);
+                // once per process (thread-safe static initialisation), before
+                // any launch can be captured in a graph
+                static const hipError_t attr =
+                    hipFuncSetAttribute((const void *)l1_filter_kernel_f16q<PT, KS, TPB>,
+                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+                RPCA_HIP_TRY(ctx, attr);
+                hipLaunchKernelGGL((l1_filter_kernel_f16q<PT, KS, TPB>), dim3(nblocks),
+                                   dim3(TPB * kWavesPerBlock * 64), lds, stream, L);
+                RPCA_HIP_TRY(ctx, hipGetLastError());
+                return RPCA_OK;
+            };
+            return L.qtiles == 2 ? go(std::integral_constant<int, 2>{}) : go(std::integral_constant<int, 1>{});
         }
     } else if (L.c.precision == 1) {
         // the FP32 refresh fragments live in HBM when the launcher prepared them
