@@ -22,11 +22,15 @@ assemble_factors(int64_t first, int64_t end, const int64_t *__restrict__ seed_ro
                    U, sigma, V, r, Qt, Pt, m, n, R4, F, G);
 }
 
+// Ranks 33..52 hold 4 rows of F per lane (up to 256 VGPRs): ask for two
+// waves per SIMD, or the compiler may take a few acc VGPRs beyond 256 and
+// leave one.  (No __restrict__ on these arguments: with it the compiler keeps
+// two more values live at rank 52 and spills them.)
 template <int R4, bool VEC>
 __global__ void __launch_bounds__(64)
-reconstruct_kernel(const float *__restrict__ M, int64_t ldm, const float *__restrict__ F,
-                   const float *__restrict__ G, int64_t m, int64_t n, float *__restrict__ Lo,
-                   int64_t ldl, float *__restrict__ So, int64_t lds)
+__attribute__((amdgpu_waves_per_eu(R4 > 32 && rows_per_lane(R4) == 4 ? 2 : 1)))
+reconstruct_kernel(const float *M, int64_t ldm, const float *F, const float *G, int64_t m, int64_t n,
+                   float *Lo, int64_t ldl, float *So, int64_t lds)
 {
     recon_wave<R4, VEC>(M, ldm, F, G, m, n, Lo, ldl, So, lds, blockIdx.x, blockIdx.y, gridDim.y,
                         threadIdx.x);
@@ -36,11 +40,14 @@ template <int R4>
 int launch_r4(rpca_ctx *ctx, const ReconArgs &a, const float *F, const float *G, bool vec,
               hipStream_t stream)
 {
-    // ~recon_waves_per_cu waves per CU across the chip (32 measured best),
-    // at least one batch of 4 columns each
+    // ~recon_waves_per_cu waves per CU across the chip (32 measured best) for
+    // the column sweep (rank <= 32); twice as many above, where each wave takes
+    // a contiguous column range (shorter ranges balance the rounds of the grid
+    // better: measured at rank 50, 6.3 -> 5.9 ms at m = n = 50000); at least
+    // one batch of 4 columns each
     const int64_t row_blocks = (a.m + rows_per_wave(R4) - 1) / rows_per_wave(R4);
-    const int64_t target_waves =
-        (int64_t)(ctx->num_cu > 0 ? ctx->num_cu : 256) * ctx->recon_waves_per_cu;
+    const int64_t target_waves = (int64_t)(ctx->num_cu > 0 ? ctx->num_cu : 256) *
+                                 ctx->recon_waves_per_cu * (R4 > 32 ? 2 : 1);
     int64_t per_block = (target_waves + row_blocks - 1) / row_blocks;
     per_block = std::max<int64_t>(1, std::min<int64_t>(per_block, (a.n + 3) / 4));
     per_block = std::min<int64_t>(per_block, 65535);
