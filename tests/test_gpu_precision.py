@@ -176,3 +176,30 @@ def test_precision_c3_full_size_sampled(R, ctx):
     # exact recovery against the generating factors on the same entries
     L0 = (A0[rows] * B0[cols]).sum(1)
     assert relF(Lg, L0) <= 1e-5
+
+
+# r = 62 with 480 seed rows and columns (class PT = 32, KS = 16): two tiles'
+# exchange buffers no longer fit next to the basis fragments in LDS, so the
+# quarter-tile kernel serves one tile per workgroup.  The basis is an
+# orthonormal basis of the true factor on the seed rows (columns), so each
+# regression recovers its coefficients from x = U z* + sparse corruption;
+# the FP64 oracle runs Algorithm 1 on the same inputs.
+def test_precision_quarter_one_tile_class(R, ctx):
+    from test_gpu_parity import _filter_cols_gpu, _filter_rows_gpu
+    m, n, r, p = 1400, 1300, 62, 480
+    pr = synth.lowrank_plus_sparse(m, n, r, factor_std=np.sqrt(1.0 / max(m, n)), sparsity=0.05,
+                                   values="pm1", seed=21)
+    I, J = synth.seed_indices(m, n, p, p, seed=21)
+    Jc, Ic = oracle.complement(J, n), oracle.complement(I, m)
+    U, _ = np.linalg.qr(pr.A0[I])
+    V, _ = np.linalg.qr(pr.B0[J])
+    say(f"precision quarter-tile one-tile class: p = q = {p}, r = {r}")
+    st, Qt, itc = _filter_cols_gpu(R, ctx, pr, I, Jc, U, r, opts=_opts(R))
+    assert st == R.RPCA_OK, ctx.last_error()
+    Zc, _ = oracle.alg1_batch(pr.M[np.ix_(I, Jc)].astype(np.float64), U)
+    assert relF(U @ Qt, U @ Zc) <= REL_TOL
+    st, Pt, itr = _filter_rows_gpu(R, ctx, pr, J, Ic, V, r, opts=_opts(R))
+    assert st == R.RPCA_OK, ctx.last_error()
+    Zr, _ = oracle.alg1_batch(pr.M[np.ix_(Ic, J)].T.astype(np.float64), V)
+    assert relF(V @ Pt, V @ Zr) <= REL_TOL
+    assert (itc > 0).all() and (itr > 0).all()
