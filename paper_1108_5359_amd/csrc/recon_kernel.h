@@ -11,9 +11,13 @@
 // (The pseudo-inverse of L^s = U Sigma V^T is V Sigma^{-1} U^T, so the
 // Nystrom block needs only r FP64 reciprocals.)  The product is HBM bound
 // (12 bytes per element: read M, write L and S, for 2r flops), so one pass
-// streams M with non-temporal loads, keeps the row factor of 4 rows per lane
-// in VGPRs and the column factor in scalar registers (uniform across the
-// wave), and writes L and S with non-temporal stores.
+// streams M, keeps the row factor of 4 rows per lane in VGPRs and the column
+// factor in scalar registers (uniform across the wave), and writes L and S
+// with non-temporal stores (ordinary stores measured 8-12% slower on MI355X).
+// M is read with non-temporal loads, or with ordinary ones up to rank 8
+// (the batched form's ranks: completion 16.2 -> 15.6 ms over its 256
+// problems; at rank 50 ordinary loads cost 25%, 6.1 -> 7.6 ms, and at rank
+// 20 they made no difference in the whole step).
 #pragma once
 
 #include "rpca_internal.h"
@@ -216,12 +220,14 @@ __device__ __forceinline__ void recon_wave(const float *__restrict__ M, int64_t 
         load_f(row);
         auto load = [&](int64_t jj) -> vec {
             if constexpr (V) {
-                return __builtin_nontemporal_load(reinterpret_cast<const vec *>(M + jj * ldm + row(0)));
+                const vec *src = reinterpret_cast<const vec *>(M + jj * ldm + row(0));
+                if constexpr (R4 <= 8) return *src;
+                else return __builtin_nontemporal_load(src);
             } else {
                 vec mv;
 #pragma unroll
                 for (int rr = 0; rr < RPL; ++rr)
-                    mv[rr] = __builtin_nontemporal_load(M + jj * ldm + row(rr));
+                    mv[rr] = R4 <= 8 ? M[jj * ldm + row(rr)] : __builtin_nontemporal_load(M + jj * ldm + row(rr));
                 return mv;
             }
         };
