@@ -49,7 +49,7 @@ struct FilterLaunch {
     FilterSide side[2];
     const float *frag32[2];   // precision form: FP32 refresh fragments in HBM (or null = in LDS)
     int32_t nblocks0;         // blocks of side 0; the rest belong to side 1
-    int32_t qtiles;           // precision form, p > 288: tiles per workgroup (1 or 2)
+    int32_t qtiles;           // precision form, p > 256: tiles per workgroup (1 or 2)
     FilterConsts c;
 };
 
