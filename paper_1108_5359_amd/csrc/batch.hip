@@ -80,19 +80,42 @@ __device__ __forceinline__ void wave_lds_sync()
     asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
 }
 
-// Sum / max over the LPR lanes that share a regression (lanes reg, reg + 64/LPR, ...).
+// Sum / max over the LPR lanes that share a regression (lanes reg, reg + 64/LPR, ...):
+// v_permlane16_swap / v_permlane32_swap exchange rows of 16 (32) lanes inside
+// the VALU, giving each lane v of lane l ^ 16 (l ^ 32) next to its own, the
+// same two operands as an xor shuffle (same result), without its LDS round trip.
+__device__ __forceinline__ float xor16_sum(float v)
+{
+    auto a = __builtin_amdgcn_permlane16_swap(__float_as_uint(v), __float_as_uint(v), false, false);
+    return __uint_as_float(a[0]) + __uint_as_float(a[1]);
+}
+__device__ __forceinline__ float xor32_sum(float v)
+{
+    auto a = __builtin_amdgcn_permlane32_swap(__float_as_uint(v), __float_as_uint(v), false, false);
+    return __uint_as_float(a[0]) + __uint_as_float(a[1]);
+}
+__device__ __forceinline__ float xor16_max(float v)
+{
+    auto a = __builtin_amdgcn_permlane16_swap(__float_as_uint(v), __float_as_uint(v), false, false);
+    return fmaxf(__uint_as_float(a[0]), __uint_as_float(a[1]));
+}
+__device__ __forceinline__ float xor32_max(float v)
+{
+    auto a = __builtin_amdgcn_permlane32_swap(__float_as_uint(v), __float_as_uint(v), false, false);
+    return fmaxf(__uint_as_float(a[0]), __uint_as_float(a[1]));
+}
 template <int LPR>
 __device__ __forceinline__ float part_sum(float v)
 {
-    if constexpr (LPR >= 4) v += __shfl_xor(v, 16);
-    if constexpr (LPR >= 2) v += __shfl_xor(v, 32);
+    if constexpr (LPR >= 4) v = xor16_sum(v);
+    if constexpr (LPR >= 2) v = xor32_sum(v);
     return v;
 }
 template <int LPR>
 __device__ __forceinline__ float part_max(float v)
 {
-    if constexpr (LPR >= 4) v = fmaxf(v, __shfl_xor(v, 16));
-    if constexpr (LPR >= 2) v = fmaxf(v, __shfl_xor(v, 32));
+    if constexpr (LPR >= 4) v = xor16_max(v);
+    if constexpr (LPR >= 2) v = xor32_max(v);
     return v;
 }
 

@@ -111,19 +111,27 @@ __device__ __forceinline__ halfx8 pack8(const float *lo, const float *hi)
     return h;
 }
 
-// Max / sum over the four lanes that share a regression column (c, c+16, c+32, c+48).
+// Max / sum over the four lanes that share a regression column (c, c+16, c+32,
+// c+48).  v_permlane16_swap / v_permlane32_swap exchange rows of 16 (32)
+// lanes between two registers inside the VALU, with no LDS round trip as a
+// ds_bpermute shuffle takes; called with both registers holding v, they leave
+// v of lane l in one and v of lane l ^ 16 (l ^ 32) in the other, which are
+// then combined: the same two operands as the xor shuffle form, so the same
+// result bit for bit.
 __device__ __forceinline__ float colmax(float v)
 {
-    v = fmaxf(v, __shfl_xor(v, 16));
-    v = fmaxf(v, __shfl_xor(v, 32));
-    return v;
+    auto a = __builtin_amdgcn_permlane16_swap(__float_as_uint(v), __float_as_uint(v), false, false);
+    v = fmaxf(__uint_as_float(a[0]), __uint_as_float(a[1]));
+    auto b = __builtin_amdgcn_permlane32_swap(__float_as_uint(v), __float_as_uint(v), false, false);
+    return fmaxf(__uint_as_float(b[0]), __uint_as_float(b[1]));
 }
 
 __device__ __forceinline__ float colsum(float v)
 {
-    v += __shfl_xor(v, 16);
-    v += __shfl_xor(v, 32);
-    return v;
+    auto a = __builtin_amdgcn_permlane16_swap(__float_as_uint(v), __float_as_uint(v), false, false);
+    v = __uint_as_float(a[0]) + __uint_as_float(a[1]);
+    auto b = __builtin_amdgcn_permlane32_swap(__float_as_uint(v), __float_as_uint(v), false, false);
+    return __uint_as_float(b[0]) + __uint_as_float(b[1]);
 }
 
 template <int PT, int KS>
