@@ -4,9 +4,10 @@ rpca_filter followed by rpca_reconstruct gives (bit for bit: every regression
 and every element of L, S is computed by the same code; only the order of the
 launches and the stream they run on change), and therefore the oracle's
 result within the stated 1e-5.  Cases: the oracle-sized workload in both
-precision forms, chunk counts from 1 to 16, the full-size plain workload,
-ragged shapes with padded leading dimensions, slabs with no column
-regressions, a seed taking every row."""
+precision forms, the precision form's quarter-tile kernel (p = 300), chunk
+counts from 1 to 16, the full-size plain workload, ragged shapes with padded
+leading dimensions, slabs with no column regressions, a seed taking every
+row."""
 from __future__ import annotations
 
 import numpy as np
@@ -85,6 +86,18 @@ def test_overlapped_ragged(R, ctx, m, n, r, ld_pad, chunks):
     k = res.U.shape[1]
     say(f"overlap ragged m={m} n={n} r={r} ld+{ld_pad} chunks={chunks}")
     Lh, Sh = _run_both(R, ctx, pr, I, J, res.U, res.sigma, res.V, k, chunks, 0, ld=m + ld_pad)
+    assert relF(Lh, res.L) <= REL_TOL and relF(Sh, res.S) <= REL_TOL
+
+
+@pytest.mark.parametrize("chunks", [3, 8])
+def test_overlapped_quarter_tile_precision(R, ctx, chunks):
+    # p = q = 300 (class PT = 19): the precision form's quarter-tile kernel
+    # (persistent, two tiles per workgroup) reading its regression range from
+    # the device in every column slab; the results are those of one launch
+    pr, I, J, res = small_case(2100, 1900, 30, 0.05, 37)
+    k = res.U.shape[1]
+    say(f"overlap quarter-tile precision form chunks={chunks}")
+    Lh, Sh = _run_both(R, ctx, pr, I, J, res.U, res.sigma, res.V, k, chunks, 1)
     assert relF(Lh, res.L) <= REL_TOL and relF(Sh, res.S) <= REL_TOL
 
 
