@@ -379,13 +379,30 @@ __device__ __forceinline__ void lane_item(const LaneSide &s, int64_t first, int 
     }
 }
 
-#define LANE_CASE(ci, rb)                                                              \
-    case 2 * (ci) + (rb) - 1:                                                          \
-        lane_item<kLaneCls[ci].p4l, rb, kLaneCls[ci].lpr>(s, first, lane, w, restage, C); \
+// Register group of each class case (index 2 ci + rb - 1).  A kernel's
+// register budget is that of its largest branch: one kernel holding every
+// class needs all 256 VGPRs (two waves per SIMD) and spills a few.  Group 0
+// is a set of four-lane classes that compiled together fit 168 VGPRs without
+// spilling (three waves per SIMD): among them p4l 5 with two rank blocks, the
+// class of the longest regressions (p 65-80, r 5-8) and most of the batched
+// workload's work.  Each group has its own kernel and work queue.  (Larger
+// sets were tried: every one that fits 168 registers alone per class spilled
+// 17-75 registers once compiled together.)
+constexpr int8_t kLaneGroup[2 * kNumLaneCls] = {
+    1, 1,  1, 1,  1, 1,  1, 1,  1, 1,  1, 1,  1, 1,     // lpr 1: p4l 1 2 3 4 5 6 8
+    1, 1,  1, 1,  1, 1,  1, 1,  1, 1,  1, 1,  1, 1,     // lpr 2: p4l 2 3 4 5 6 7 8
+    1, 1,  1, 0,  1, 0,  0, 0,  1, 0,                   // lpr 4: p4l 1 2 3 4 5
+};
+
+#define LANE_CASE(ci, rb)                                                                  \
+    case 2 * (ci) + (rb) - 1:                                                              \
+        if constexpr (kLaneGroup[2 * (ci) + (rb) - 1] == G)                                \
+            lane_item<kLaneCls[ci].p4l, rb, kLaneCls[ci].lpr>(s, first, lane, w, restage, C); \
         break;
 #define LANE_CASES(ci) LANE_CASE(ci, 1) LANE_CASE(ci, 2)
 
-__global__ void __launch_bounds__(kWaves * 64) __attribute__((amdgpu_waves_per_eu(2)))
+template <int G>
+__global__ void __launch_bounds__(kWaves * 64) __attribute__((amdgpu_waves_per_eu(G == 0 ? 3 : 2)))
 lane_filter_kernel(const LaneSide *__restrict__ sides, const int32_t *__restrict__ items,
                    int32_t nitems, uint32_t *counter, FilterConsts C)
 {
@@ -409,7 +426,7 @@ lane_filter_kernel(const LaneSide *__restrict__ sides, const int32_t *__restrict
             LANE_CASES(12) LANE_CASES(13) LANE_CASES(14) LANE_CASES(15) LANE_CASES(16)
             LANE_CASES(17) LANE_CASES(18)
         default: break;                                  // rejected on the host
-        }
+        }                                                // (other group: never queued here)
     }
 }
 #undef LANE_CASES
@@ -418,7 +435,7 @@ static_assert(kNumLaneCls == 19, "LANE_CASES list covers every class");
 
 __global__ void reset_counters(uint32_t *counter)
 {
-    if (threadIdx.x == 0) counter[0] = 0u;
+    if (threadIdx.x < 2) counter[threadIdx.x] = 0u;
 }
 
 // ---------------------------------------------------------------- completion
@@ -466,16 +483,25 @@ int lane_class(int p, int r, int lpr)
 
 int lane_regs_per_item(int cls) { return 64 / kLaneCls[cls / 2].lpr; }
 
+int lane_group(int cls) { return kLaneGroup[cls]; }
+
 int launch_lane_filter(rpca_ctx *ctx, const BatchTables &t, const FilterConsts &c,
                        hipStream_t stream)
 {
     hipLaunchKernelGGL(reset_counters, dim3(1), dim3(64), 0, stream, t.counter);
     RPCA_HIP_TRY(ctx, hipGetLastError());
-    if (t.nitems == 0) return RPCA_OK;
-    const int blocks = (t.grid_waves + kWaves - 1) / kWaves;
-    hipLaunchKernelGGL(lane_filter_kernel, dim3((unsigned)blocks), dim3(kWaves * 64), 0, stream,
-                       t.sides, t.items, t.nitems, t.counter, c);
-    RPCA_HIP_TRY(ctx, hipGetLastError());
+    if (t.nitems0 > 0) {
+        const int blocks = (t.grid_waves[0] + kWaves - 1) / kWaves;
+        hipLaunchKernelGGL(lane_filter_kernel<0>, dim3((unsigned)blocks), dim3(kWaves * 64), 0, stream,
+                           t.sides, t.items, t.nitems0, t.counter, c);
+        RPCA_HIP_TRY(ctx, hipGetLastError());
+    }
+    if (t.nitems > t.nitems0) {
+        const int blocks = (t.grid_waves[1] + kWaves - 1) / kWaves;
+        hipLaunchKernelGGL(lane_filter_kernel<1>, dim3((unsigned)blocks), dim3(kWaves * 64), 0, stream,
+                           t.sides, t.items + 2 * (int64_t)t.nitems0, t.nitems - t.nitems0, t.counter + 1, c);
+        RPCA_HIP_TRY(ctx, hipGetLastError());
+    }
     return RPCA_OK;
 }
 

@@ -232,16 +232,21 @@ int build_tables(rpca_batch *b)
     if (b->tun.order == 0)
         std::stable_sort(order.begin(), order.end(),
                          [&](int32_t x, int32_t y) { return side_cost[x] > side_cost[y]; });
-    std::vector<int32_t> items;
+    // (one queue per register group: the classes whose kernel fits three waves
+    // per SIMD, then the rest)
+    std::vector<int32_t> items, items1;
     for (int32_t sidx : order) {
         const int64_t nreg = sides[sidx].nreg;
         const int64_t per = lane_regs_per_item(sides[sidx].cls);
+        std::vector<int32_t> &q = lane_group(sides[sidx].cls) == 0 ? items : items1;
         for (int64_t f = 0; f < nreg; f += per) {
             if (f > INT32_MAX) return set_status(ctx, RPCA_ERR_UNSUPPORTED, "batch: too many regressions in one side");
-            items.push_back(sidx);
-            items.push_back((int32_t)f);
+            q.push_back(sidx);
+            q.push_back((int32_t)f);
         }
     }
+    const int64_t nitems0 = (int64_t)items.size() / 2;
+    items.insert(items.end(), items1.begin(), items1.end());
     const int64_t nitems = (int64_t)items.size() / 2;
     if (nitems > INT32_MAX) return set_status(ctx, RPCA_ERR_UNSUPPORTED, "batch: too many work items");
 
@@ -295,9 +300,14 @@ int build_tables(rpca_batch *b)
     t.sides = reinterpret_cast<const LaneSide *>(base + o_sides);
     t.items = reinterpret_cast<const int32_t *>(base + o_items);
     t.nitems = (int32_t)nitems;
+    t.nitems0 = (int32_t)nitems0;
     t.counter = reinterpret_cast<uint32_t *>(base + o_ctr);
+    // filter_waves_per_cu: persistent waves per CU at two waves per SIMD; the
+    // three-wave group gets half as many again
     const int64_t wpc = b->tun.filter_waves_per_cu > 0 ? b->tun.filter_waves_per_cu : 8;
-    t.grid_waves = (int32_t)std::max<int64_t>(1, std::min<int64_t>(nitems, wpc * std::max(1, ctx->num_cu)));
+    const int64_t ncu = std::max(1, ctx->num_cu);
+    t.grid_waves[0] = (int32_t)std::max<int64_t>(1, std::min<int64_t>(nitems0, (3 * wpc + 1) / 2 * ncu));
+    t.grid_waves[1] = (int32_t)std::max<int64_t>(1, std::min<int64_t>(nitems - nitems0, wpc * ncu));
     t.jobs = reinterpret_cast<const ReconJob *>(base + o_jobs);
     t.asm_block_job = reinterpret_cast<const int32_t *>(base + o_aj);
     t.asm_block_first = reinterpret_cast<const int64_t *>(base + o_af);

@@ -215,10 +215,12 @@ struct ReconJob {
 // The device tables of a batched run.
 struct BatchTables {
     const LaneSide *sides;
-    const int32_t *items;        // 2 per item: side index, first regression
+    const int32_t *items;        // 2 per item: side index, first regression; the
+                                 // items of register group 0 first, then group 1
     int32_t nitems;
-    uint32_t *counter;           // work-queue head (reset by the launch itself)
-    int32_t grid_waves;          // persistent waves of the lane filter
+    int32_t nitems0;             // items of group 0
+    uint32_t *counter;           // work-queue heads of the two groups (reset by the launch)
+    int32_t grid_waves[2];       // persistent waves of each group's lane filter
     const ReconJob *jobs;
     const int32_t *asm_block_job;    // job of each workgroup of the factor assembly
     const int64_t *asm_block_first;  // the job's thread index of that workgroup's thread 0
@@ -228,6 +230,10 @@ struct BatchTables {
     int32_t rec_blocks;
     int32_t rec_lds_bytes;           // LDS reserved per completion wave (caps residency), 0 = none
 };
+
+// Register group of a lane class (lane_class() value): 0 = three waves per
+// SIMD, 1 = two.
+int lane_group(int cls);
 
 // Enqueue the lane-form filter over every item (queue reset included).
 int launch_lane_filter(rpca_ctx *ctx, const BatchTables &t, const FilterConsts &c,
