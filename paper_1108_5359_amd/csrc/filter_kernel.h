@@ -1361,35 +1361,40 @@ l1_filter_kernel_f16q(FilterLaunch L)
             beta = fminf(L.c.rho * beta, beta_bar);
 
             // FP32 residual refinement: u = x - A z from the input, two element
-            // tiles at a time (their fragments loaded together, two chains)
+            // tiles at a time: their fragments are loaded from HBM (L2) in one
+            // batch before any of their MFMAs, so the load latency is paid once
+            // per batch (the compiler's own order waited once per rank tile)
             if (L.c.refresh > 0 && ((k + 1) % L.c.refresh) == 0) {
+                constexpr int QB = 2;
 #pragma unroll
-                for (int s = 0; s < 2 * NPP; s += 2) {
-                    const int t = 2 * pp0 + s;
-                    if (t < PT) {                     // wave-uniform
-                        const bool two = t + 1 < PT;
-                        floatx4 fa[2][RT];
+                for (int s0 = 0; s0 < 2 * NPP; s0 += QB) {
+                    const int t0 = 2 * pp0 + s0;
+                    if (t0 < PT) {                    // wave-uniform
+                        floatx4 fa[QB][RT];
+                        const floatx4 zero4 = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
-                        for (int mt = 0; mt < RT; ++mt) {
-                            fa[0][mt] = F2[(t * RT + mt) * 64];
-                            fa[1][mt] = two ? F2[((t + 1) * RT + mt) * 64] : floatx4{0.0f, 0.0f, 0.0f, 0.0f};
-                        }
-                        floatx4 Az[2] = {floatx4{0.0f, 0.0f, 0.0f, 0.0f}, floatx4{0.0f, 0.0f, 0.0f, 0.0f}};
+                        for (int h = 0; h < QB; ++h)
+#pragma unroll
+                            for (int mt = 0; mt < RT; ++mt)
+                                fa[h][mt] = (s0 + h < 2 * NPP && t0 + h < PT) ? F2[((t0 + h) * RT + mt) * 64] : zero4;
+                        __builtin_amdgcn_sched_barrier(0);
+                        floatx4 Az[QB];
+#pragma unroll
+                        for (int h = 0; h < QB; ++h) Az[h] = zero4;
 #pragma unroll
                         for (int mt = 0; mt < RT; ++mt)
 #pragma unroll
                             for (int v = 0; v < 4; ++v)
                                 if (4 * mt + v < KS)
 #pragma unroll
-                                    for (int h = 0; h < 2; ++h) Az[h] = mfma4(fa[h][mt][v], z[mt][v], Az[h]);
-                        const floatx4 zero4 = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
-                        const floatx4 x0 = tile_in ? xtile[t * 64] : zero4;
+                                    for (int h = 0; h < QB; ++h) Az[h] = mfma4(fa[h][mt][v], z[mt][v], Az[h]);
 #pragma unroll
-                        for (int v = 0; v < 4; ++v) u[s][v] = x0[v] - Az[0][v];
-                        if (two) {
-                            const floatx4 x1 = tile_in ? xtile[(t + 1) * 64] : zero4;
+                        for (int h = 0; h < QB; ++h) {
+                            if (s0 + h < 2 * NPP && t0 + h < PT) {
+                                const floatx4 xv = tile_in ? xtile[(t0 + h) * 64] : zero4;
 #pragma unroll
-                            for (int v = 0; v < 4; ++v) u[s + 1][v] = x1[v] - Az[1][v];
+                                for (int v = 0; v < 4; ++v) u[s0 + h][v] = xv[v] - Az[h][v];
+                            }
                         }
                     }
                 }

@@ -41,14 +41,15 @@ int launch_r4(rpca_ctx *ctx, const ReconArgs &a, const float *F, const float *G,
               hipStream_t stream)
 {
     // ~recon_waves_per_cu waves per CU across the chip (32 measured best) for
-    // the column sweep (rank <= 32); four times as many above, where each wave
-    // takes a contiguous column range and two waves per SIMD are resident:
-    // shorter ranges balance the many rounds of the grid better (measured at
-    // rank 50, m = n = 50000: 6.40, 6.24, 6.12, 6.05 ms at 48, 64, 96, 128
-    // waves per CU); at least one batch of 4 columns each
+    // the column sweep (rank <= 32); eight times as many above, where each
+    // wave takes a contiguous column range and two waves per SIMD are
+    // resident: shorter ranges balance the many rounds of the grid better
+    // (measured at rank 50, m = n = 50000: 6.40, 6.24, 6.12, 6.05, 6.01, 5.95,
+    // 6.06 ms at 48, 64, 96, 128, 192, 256, 384 waves per CU); at least one
+    // batch of 4 columns each
     const int64_t row_blocks = (a.m + rows_per_wave(R4) - 1) / rows_per_wave(R4);
     const int64_t target_waves = (int64_t)(ctx->num_cu > 0 ? ctx->num_cu : 256) *
-                                 ctx->recon_waves_per_cu * (R4 > 32 ? 4 : 1);
+                                 ctx->recon_waves_per_cu * (R4 > 32 ? 8 : 1);
     int64_t per_block = (target_waves + row_blocks - 1) / row_blocks;
     per_block = std::max<int64_t>(1, std::min<int64_t>(per_block, (a.n + 3) / 4));
     per_block = std::min<int64_t>(per_block, 65535);
