@@ -47,15 +47,19 @@ constexpr int kMaxRB = kLaneMaxR / 4;   // 2 rank blocks
 constexpr int kWaves = 4;               // waves per workgroup
 constexpr int kVC = 4;                  // element quads per chunk of v = A w
 
-// Per-wave LDS slice: the basis in the two operand orders and the element
-// offsets.
+// Per-wave LDS slice: the basis in the two operand orders, the element
+// offsets, and the lanes' x (XQ element quads per lane) for the refresh, which
+// then reads x back from LDS instead of gathering it from M again.
 // a1[(4 rb + i) S1 + e] = A[e][4 rb + i] with an odd number S1/4 of float4 per
 // row (conflict-free ds_read_b128 of 4 rows); a2[e RR + k] = A[e][k] with
 // RR = 4 RB.
+template <int XQ>
 struct WaveLds {
+    static constexpr int kXQ = XQ;
     float a1[kMaxRB * 4 * 4 * (kMaxP4 | 1)];
     float a2[kMaxP4 * 4 * 4 * kMaxRB];
     int64_t eoff[kMaxP4 * 4];            // element offsets in M (floats), -1 = padding
+    floatx4 xc[XQ][64];                  // x of lane l's quad t at xc[t][l]
 };
 
 // Built classes (P4L element quads per lane, LPR lanes per regression); the
@@ -149,10 +153,11 @@ __device__ __forceinline__ float load_x(const float *M, const int64_t *eoff, int
 // refresh).  The lanes of one 4x4 MFMA block always belong to one part, so
 // the K-step element is common to the block; partial w and the residual are
 // summed / maxed over the parts with xor shuffles.
-template <int P4L, int RB, int LPR>
-__device__ __forceinline__ void lane_item(const LaneSide &s, int64_t first, int lane, WaveLds &w,
+template <int P4L, int RB, int LPR, class WL>
+__device__ __forceinline__ void lane_item(const LaneSide &s, int64_t first, int lane, WL &w,
                                           bool restage, const FilterConsts &C)
 {
+    static_assert(P4L <= WL::kXQ, "the wave's x cache holds every quad of the class");
     constexpr int NR = 64 / LPR;        // regressions per item
     constexpr int PL = 4 * P4L;         // elements per lane
     constexpr int PP = LPR * PL;        // padded p
@@ -203,14 +208,17 @@ __device__ __forceinline__ void lane_item(const LaneSide &s, int64_t first, int 
     float xinf = 0.0f, xx = 0.0f;
 #pragma unroll
     for (int t = 0; t < P4L; ++t) {
+        floatx4 xq;
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
             const float x = load_x<LPR == 1>(M, eoff, 4 * t + i, voff, valid);
+            xq[i] = x;
             u[t][i] = x;
             y[t][i] = 0.0f;
             xinf = fmaxf(xinf, fabsf(x));
             xx = fmaf(x, x, xx);
         }
+        w.xc[t][lane] = xq;
         __builtin_amdgcn_sched_barrier(0);
     }
     xinf = part_max<LPR>(xinf);
@@ -355,9 +363,9 @@ __device__ __forceinline__ void lane_item(const LaneSide &s, int64_t first, int 
                 for (int c = 0; c < kVC; ++c) {
                     const int t = t0 + c;
                     if (t < P4L) {
+                        const floatx4 xq = w.xc[t][lane];
 #pragma unroll
-                        for (int i = 0; i < 4; ++i)
-                            u[t][i] = load_x<LPR == 1>(M, eoff, 4 * t + i, voff, valid) - D[c][i];
+                        for (int i = 0; i < 4; ++i) u[t][i] = xq[i] - D[c][i];
                     }
                 }
                 __builtin_amdgcn_sched_barrier(0);
@@ -406,9 +414,11 @@ __global__ void __launch_bounds__(kWaves * 64) __attribute__((amdgpu_waves_per_e
 lane_filter_kernel(const LaneSide *__restrict__ sides, const int32_t *__restrict__ items,
                    int32_t nitems, uint32_t *counter, FilterConsts C)
 {
-    __shared__ WaveLds lds[kWaves];
+    // x cache: the largest class of the group (5 quads per lane in group 0, 8 in 1)
+    typedef WaveLds<G == 0 ? 5 : 8> Lds;
+    __shared__ Lds lds[kWaves];
     const int lane = threadIdx.x & 63;
-    WaveLds &w = lds[threadIdx.x >> 6];
+    Lds &w = lds[threadIdx.x >> 6];
     int cached = -1;
     for (;;) {
         uint32_t it = 0;
