@@ -1361,22 +1361,24 @@ l1_filter_kernel_f16q(FilterLaunch L)
             beta = fminf(L.c.rho * beta, beta_bar);
 
             // FP32 residual refinement: u = x - A z from the input, two element
-            // tiles at a time: their fragments are loaded from HBM (L2) in one
-            // batch before any of their MFMAs, so the load latency is paid once
-            // per batch (the compiler's own order waited once per rank tile)
+            // tiles at a time: their fragments and x are loaded from HBM (L2) in
+            // one batch before any of their MFMAs, so the load latency is paid
+            // once per batch (the compiler's own order waited once per rank tile)
             if (L.c.refresh > 0 && ((k + 1) % L.c.refresh) == 0) {
                 constexpr int QB = 2;
 #pragma unroll
                 for (int s0 = 0; s0 < 2 * NPP; s0 += QB) {
                     const int t0 = 2 * pp0 + s0;
                     if (t0 < PT) {                    // wave-uniform
-                        floatx4 fa[QB][RT];
+                        floatx4 fa[QB][RT], xq[QB];
                         const floatx4 zero4 = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
-                        for (int h = 0; h < QB; ++h)
+                        for (int h = 0; h < QB; ++h) {
+                            const bool on = s0 + h < 2 * NPP && t0 + h < PT;
 #pragma unroll
-                            for (int mt = 0; mt < RT; ++mt)
-                                fa[h][mt] = (s0 + h < 2 * NPP && t0 + h < PT) ? F2[((t0 + h) * RT + mt) * 64] : zero4;
+                            for (int mt = 0; mt < RT; ++mt) fa[h][mt] = on ? F2[((t0 + h) * RT + mt) * 64] : zero4;
+                            xq[h] = (on && tile_in) ? xtile[(t0 + h) * 64] : zero4;
+                        }
                         __builtin_amdgcn_sched_barrier(0);
                         floatx4 Az[QB];
 #pragma unroll
@@ -1391,9 +1393,8 @@ l1_filter_kernel_f16q(FilterLaunch L)
 #pragma unroll
                         for (int h = 0; h < QB; ++h) {
                             if (s0 + h < 2 * NPP && t0 + h < PT) {
-                                const floatx4 xv = tile_in ? xtile[(t0 + h) * 64] : zero4;
 #pragma unroll
-                                for (int v = 0; v < 4; ++v) u[s0 + h][v] = xv[v] - Az[h][v];
+                                for (int v = 0; v < 4; ++v) u[s0 + h][v] = xq[h][v] - Az[h][v];
                             }
                         }
                     }
