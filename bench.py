@@ -96,7 +96,8 @@ def source_digest(paths) -> str:
 
 # filter kernel forms (rpca_filter_form): names, kernels, counter summary keys
 FORM_NAMES = {0: "fp16", 1: "tile", 2: "split"}
-FORM_KERNELS = {0: "l1_filter_kernel_f16 (fp16 MFMA)", 1: "l1_filter_kernel (fp32 MFMA, tile form)",
+FORM_KERNELS = {0: "l1_filter_kernel_f16 / _f16q (fp16 MFMA; the latter above p = 256)",
+                1: "l1_filter_kernel (fp32 MFMA, tile form)",
                 2: "l1_filter_split_kernel (fp32 MFMA, split form)"}
 FORM_KEYS = {0: "l1_filter", 1: "l1_filter", 2: "l1_filter_split"}
 
