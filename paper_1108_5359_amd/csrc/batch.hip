@@ -163,7 +163,8 @@ __device__ __forceinline__ void lane_item(const LaneSide &s, int64_t first, int 
     constexpr int PP = LPR * PL;        // padded p
     constexpr int S1 = 4 * ((PP / 4) | 1);   // a1 row stride
     constexpr int RR = 4 * RB;          // padded r
-    constexpr int NCH = 4 / RB;         // accumulator chains per rank block of w
+    constexpr int NCH = 1;              // accumulator chains per rank block of w (one: the adds
+                                        // joining more cost more than the latency they hide)
     const int p = s.p, r = s.r;
     const int q4 = lane & 3;
     const int reg = lane % NR, part = lane / NR;

@@ -400,11 +400,14 @@ struct SplitShape {
     // holds one or two (NQ <= 2), its part of w = A^T g runs on
     // v_mfma_f32_4x4x1_16b_f32 (a quarter of the cycles of a 16x16x4 per quad)
     // instead of a padded 16x16x4 tile; with three the saving is small and the
-    // accumulators do not fit.  NCH independent chains per quad.
+    // accumulators do not fit.  NCH accumulator chains per quad: one (measured
+    // at r = 20: filter 0.306 ms with four chains, 0.301 with two, 0.298 with
+    // one -- the adds that join the chains cost more than the 4x4x1 latency
+    // they hide).
     static constexpr int LT = RT - 1;
     static constexpr int NQ = KS - 4 * LT;
     static constexpr bool kQuad = NQ <= 2;
-    static constexpr int NCH = NQ == 1 ? 4 : 2;
+    static constexpr int NCH = 1;
     static constexpr int FT = kQuad ? LT : RT;   // rank tiles of w on 16x16x4
     // floats a lane publishes per step: w partials, residual
     static constexpr int NV = 4 * FT + (kQuad ? 4 * NQ : 0) + 1;
