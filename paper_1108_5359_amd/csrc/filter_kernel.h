@@ -409,8 +409,10 @@ struct SplitShape {
     static constexpr bool kQuad = NQ <= 2;
     static constexpr int NCH = 1;
     static constexpr int FT = kQuad ? LT : RT;   // rank tiles of w on 16x16x4
-    // floats a lane publishes per step: w partials, residual
-    static constexpr int NV = 4 * FT + (kQuad ? 4 * NQ : 0) + 1;
+    // floats a lane publishes per step: w partials (of the quad part only the
+    // lane's own rank, summed over the four g lanes before the exchange),
+    // residual
+    static constexpr int NV = 4 * FT + (kQuad ? NQ : 0) + 1;
     // three waves per SIMD (168 VGPRs) where the loop fits them without
     // spilling (checked at build time for every class), else two
     static constexpr int kWavesPerEU = (KS <= 5 && PTW <= 4) ? 3 : 2;
@@ -598,14 +600,19 @@ l1_filter_split_kernel(FilterLaunch L)
                 for (int v = 0; v < 4; ++v) xch[buf][wave][4 * mt + v][lane] = Wa[mt][v] + Wb[mt][v];
             if constexpr (kQuad) {
                 // lane (g, c) register i: ranks 16 LT + 4 q + i of regression c,
-                // summed over this lane's elements (rows 4 g .. 4 g + 3 of each tile)
+                // summed over this lane's elements (rows 4 g .. 4 g + 3 of each
+                // tile); summed over the four g lanes of the regression here,
+                // lane (g, c) publishes rank 16 LT + 4 q + g, the layout of the
+                // 16x16 tiles
 #pragma unroll
                 for (int q = 0; q < NQ; ++q) {
                     floatx4 wq = Wq[q][0];
 #pragma unroll
                     for (int h = 1; h < NCH; ++h) wq += Wq[q][h];
+                    float t4[4];
 #pragma unroll
-                    for (int i = 0; i < 4; ++i) xch[buf][wave][4 * FT + 4 * q + i][lane] = wq[i];
+                    for (int i = 0; i < 4; ++i) t4[i] = colsum(wq[i]);
+                    xch[buf][wave][4 * FT + q][lane] = g == 0 ? t4[0] : g == 1 ? t4[1] : g == 2 ? t4[2] : t4[3];
                 }
             }
             xch[buf][wave][NV - 1][lane] = res_part;
@@ -629,16 +636,9 @@ l1_filter_split_kernel(FilterLaunch L)
 #pragma unroll
                     for (int v = 0; v < 4; ++v) W[mt][v] = ws[4 * mt + v];
                 if constexpr (kQuad) {
-                    // sum over the four g lanes of the regression, then lane (g, c)
-                    // keeps rank 16 LT + 4 q + g, the layout of the 16x16 tiles
                     W[LT] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
-                    for (int q = 0; q < NQ; ++q) {
-                        float t4[4];
-#pragma unroll
-                        for (int i = 0; i < 4; ++i) t4[i] = colsum(ws[4 * FT + 4 * q + i]);
-                        W[LT][q] = g == 0 ? t4[0] : g == 1 ? t4[1] : g == 2 ? t4[2] : t4[3];
-                    }
+                    for (int q = 0; q < NQ; ++q) W[LT][q] = ws[4 * FT + q];
                 }
             }
 #pragma unroll
