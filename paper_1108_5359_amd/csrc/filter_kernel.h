@@ -134,6 +134,22 @@ __device__ __forceinline__ float colsum(float v)
     return __uint_as_float(b[0]) + __uint_as_float(b[1]);
 }
 
+// Column sums of four values, scattered by row: lane (g, c) receives the sum
+// of t_g over lanes c, c+16, c+32, c+48.  The first swap pairs rows 0/1 and
+// 2/3 of t0 with t1 (and of t2 with t3) so that one add forms the row-pair
+// sums of both values; the second pairs rows 0/1 with 2/3 across the two
+// results.  Three swaps and three adds instead of four column sums and a
+// selection, with the same operands in the same order (the same result).
+__device__ __forceinline__ float colsum4_scatter(float t0, float t1, float t2, float t3)
+{
+    auto a = __builtin_amdgcn_permlane16_swap(__float_as_uint(t0), __float_as_uint(t1), false, false);
+    const float s01 = __uint_as_float(a[0]) + __uint_as_float(a[1]);
+    auto b = __builtin_amdgcn_permlane16_swap(__float_as_uint(t2), __float_as_uint(t3), false, false);
+    const float s23 = __uint_as_float(b[0]) + __uint_as_float(b[1]);
+    auto c = __builtin_amdgcn_permlane32_swap(__float_as_uint(s01), __float_as_uint(s23), false, false);
+    return __uint_as_float(c[0]) + __uint_as_float(c[1]);
+}
+
 template <int PT, int KS>
 __global__ void __launch_bounds__(kWavesPerBlock * 64)
 __attribute__((amdgpu_waves_per_eu(PT <= 13 ? 2 : 1)))
@@ -609,10 +625,7 @@ l1_filter_split_kernel(FilterLaunch L)
                     floatx4 wq = Wq[q][0];
 #pragma unroll
                     for (int h = 1; h < NCH; ++h) wq += Wq[q][h];
-                    float t4[4];
-#pragma unroll
-                    for (int i = 0; i < 4; ++i) t4[i] = colsum(wq[i]);
-                    xch[buf][wave][4 * FT + q][lane] = g == 0 ? t4[0] : g == 1 ? t4[1] : g == 2 ? t4[2] : t4[3];
+                    xch[buf][wave][4 * FT + q][lane] = colsum4_scatter(wq[0], wq[1], wq[2], wq[3]);
                 }
             }
             xch[buf][wave][NV - 1][lane] = res_part;
