@@ -628,7 +628,9 @@ l1_filter_split_kernel(FilterLaunch L)
                     xch[buf][wave][4 * FT + q][lane] = colsum4_scatter(wq[0], wq[1], wq[2], wq[3]);
                 }
             }
-            xch[buf][wave][NV - 1][lane] = res_part;
+            // the residual partial, its maximum over the four g lanes taken
+            // here (before the barrier, off the step's critical path)
+            xch[buf][wave][NV - 1][lane] = colmax(res_part);
             __syncthreads();
             // w = sum of the partials in part order
             floatx4 W[RT];
@@ -656,7 +658,6 @@ l1_filter_split_kernel(FilterLaunch L)
             }
 #pragma unroll
             for (int w = 0; w < kWavesPerBlock; ++w) res = fmaxf(res, xch[buf][w][NV - 1][lane]);
-            res = colmax(res);
             // the stopping test of step k - 1
             if (k > 0 && !done) {
                 ++K;
