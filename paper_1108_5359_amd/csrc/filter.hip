@@ -98,6 +98,19 @@ int launch_filter(rpca_ctx *ctx, const FilterSide *sides, int nsides, const Filt
                   hipStream_t stream)
 {
     if (nsides < 1 || nsides > 2) return set_status(ctx, RPCA_ERR_ARG, "filter: bad side count");
+    // Two sides in one launch: the side whose tiles hold neighbouring
+    // regressions (row regressions: 16 adjacent rows, so each gathered line
+    // serves a whole tile) takes the low workgroup indices, which start first.
+    // The first round of workgroups then waits on the cheap gather, and the
+    // scattered one (a line per element of a column regression) runs beside
+    // work already in progress.  Each side carries its own outputs, and a
+    // result does not depend on where its tile sits in the grid.
+    FilterSide ord[2];
+    if (nsides == 2 && sides[1].reg_stride < sides[0].reg_stride) {
+        ord[0] = sides[1];
+        ord[1] = sides[0];
+        sides = ord;
+    }
     // FP16 contractions only where they keep the FP32 accuracy (p >= kMinPHalf);
     // smaller regressions stay FP32 in the precision form too.
     FilterConsts c = c_in;
