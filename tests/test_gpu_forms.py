@@ -12,8 +12,9 @@ P~^T V^T, and on L and S); the iteration counts, which FP32 rounding decides
 near the stopping threshold, are compared through their means.  Cases: the
 oracle-sized workload, every split tile class from p = 64 (one tile per wave) to p = 300 (five),
 ragged shapes, zero regressions, the iteration cap and a few steps against
-the oracle's same steps, repeated regressions, a chunked launch (device
-range) of the overlapped form.
+the oracle's same steps, repeated regressions, both sides in one launch
+against each side alone (bitwise), a chunked launch (device range) of the
+overlapped form.
 """
 from __future__ import annotations
 
@@ -114,6 +115,39 @@ def test_split_form_zero_regressions_cap_and_repeats(R, ctx):
     for a in range(5):
         for b in range(a + 5, 35, 5):
             assert np.array_equal(Qt[:, a], Qt[:, b])     # same regression, same bits
+
+
+@pytest.mark.parametrize("form", FORMS)
+def test_fused_sides_equal_separate_launches(R, ctx, form):
+    # One launch of both sides (the row regressions take the first
+    # workgroups) gives every regression the bits and the step count that
+    # its own side's launch gives it.
+    import torch
+    pr, r, I, J, res = case("c1", 1)
+    k = res.U.shape[1]
+    m, n = pr.m, pr.n
+    Ic, Jc = oracle.complement(I, m), oracle.complement(J, n)
+    Md = dev_matrix(pr.M)
+    L = torch.empty_like(Md)
+    S = torch.empty_like(Md)
+    Qt = torch.zeros((len(Jc), k), device="cuda")
+    Pt = torch.zeros((len(Ic), k), device="cuda")
+    kc = torch.zeros(len(Jc), dtype=torch.int32, device="cuda")
+    kr = torch.zeros(len(Ic), dtype=torch.int32, device="cuda")
+    say(f"fused sides, form {form}")
+    st = R.rpca_filter_complete(ctx, Md, m, n, m, dev_i64(I), len(I), dev_i64(J), len(J), dev_i64(Jc),
+                                dev_i64(Ic), dev_f64_colmajor(res.U),
+                                torch.as_tensor(res.sigma).cuda(), dev_f64_colmajor(res.V), k,
+                                _opts(R, form), Qt, kc, Pt, kr, L, m, S, m)
+    torch.cuda.synchronize()
+    assert st == R.RPCA_OK, ctx.last_error()
+    say(f"separate sides, form {form}")
+    st_c, Qs, ks_c = _filter_cols_gpu(R, ctx, pr, I, Jc, res.U, k, _opts(R, form))
+    st_r, Ps, ks_r = _filter_rows_gpu(R, ctx, pr, J, Ic, res.V, k, _opts(R, form))
+    assert st_c == R.RPCA_OK and st_r == R.RPCA_OK
+    assert np.array_equal(Qt.double().cpu().numpy().T, Qs)
+    assert np.array_equal(Pt.double().cpu().numpy().T, Ps)
+    assert np.array_equal(kc.cpu().numpy(), ks_c) and np.array_equal(kr.cpu().numpy(), ks_r)
 
 
 @pytest.mark.parametrize("chunks", [3, 16])
