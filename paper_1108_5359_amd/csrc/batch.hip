@@ -501,6 +501,19 @@ int launch_lane_filter(rpca_ctx *ctx, const BatchTables &t, const FilterConsts &
 {
     hipLaunchKernelGGL(reset_counters, dim3(1), dim3(64), 0, stream, t.counter);
     RPCA_HIP_TRY(ctx, hipGetLastError());
+    // With both groups present, the second runs on the second stream, so its
+    // waves take the CUs that the first group's waves leave as its queue
+    // drains.  The queues have counters of their own and no wave waits on
+    // another, so the two grids finish in any order of residency.
+    const bool both = t.nitems0 > 0 && t.nitems > t.nitems0;
+    hipStream_t s1 = stream;
+    if (both) {
+        int st = ensure_aux(ctx);
+        if (st != RPCA_OK) return st;
+        RPCA_HIP_TRY(ctx, hipEventRecord(ctx->pev[0], stream));
+        RPCA_HIP_TRY(ctx, hipStreamWaitEvent(ctx->aux, ctx->pev[0], 0));
+        s1 = ctx->aux;
+    }
     if (t.nitems0 > 0) {
         const int blocks = (t.grid_waves[0] + kWaves - 1) / kWaves;
         hipLaunchKernelGGL(lane_filter_kernel<0>, dim3((unsigned)blocks), dim3(kWaves * 64), 0, stream,
@@ -509,9 +522,13 @@ int launch_lane_filter(rpca_ctx *ctx, const BatchTables &t, const FilterConsts &
     }
     if (t.nitems > t.nitems0) {
         const int blocks = (t.grid_waves[1] + kWaves - 1) / kWaves;
-        hipLaunchKernelGGL(lane_filter_kernel<1>, dim3((unsigned)blocks), dim3(kWaves * 64), 0, stream,
+        hipLaunchKernelGGL(lane_filter_kernel<1>, dim3((unsigned)blocks), dim3(kWaves * 64), 0, s1,
                            t.sides, t.items + 2 * (int64_t)t.nitems0, t.nitems - t.nitems0, t.counter + 1, c);
         RPCA_HIP_TRY(ctx, hipGetLastError());
+    }
+    if (both) {
+        RPCA_HIP_TRY(ctx, hipEventRecord(ctx->pev[1], ctx->aux));
+        RPCA_HIP_TRY(ctx, hipStreamWaitEvent(stream, ctx->pev[1], 0));
     }
     return RPCA_OK;
 }

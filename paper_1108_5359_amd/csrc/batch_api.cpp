@@ -698,9 +698,13 @@ int rpca_batch_destroy(rpca_batch_t b)
     for (DevBuf *d : {&b->ws, &b->tables, &b->seed_ws})
         if (d->ptr) (void)hipFree(d->ptr);
     if (b->wctx) {
+        if (b->wctx->aux) (void)hipStreamSynchronize(b->wctx->aux);
         for (DevBuf *d : {&b->wctx->factors, &b->wctx->xbuf_ws, &b->wctx->frag_ws, &b->wctx->scratch,
                           &b->wctx->solve_ws, &b->wctx->seed_ws})
             if (d->ptr) (void)hipFree(d->ptr);
+        for (auto &e : b->wctx->pev)
+            if (e) (void)hipEventDestroy(e);
+        if (b->wctx->aux) (void)hipStreamDestroy(b->wctx->aux);
         delete b->wctx;
     }
     for (auto &e : b->ev)

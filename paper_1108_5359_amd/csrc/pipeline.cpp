@@ -35,6 +35,8 @@ __global__ void slab_ranges(const int64_t *__restrict__ seed_cols, int64_t q, in
     ranges[k] = jk - lo;
 }
 
+} // namespace
+
 int ensure_aux(rpca_ctx *ctx)
 {
     if (ctx->aux) return RPCA_OK;
@@ -43,8 +45,6 @@ int ensure_aux(rpca_ctx *ctx)
         RPCA_HIP_TRY(ctx, hipEventCreateWithFlags(&e, hipEventDisableTiming));
     return RPCA_OK;
 }
-
-} // namespace
 
 int launch_filter_complete(rpca_ctx *ctx, const PipelineArgs &pa, const FilterConsts &c,
                            int chunks, hipStream_t stream)

@@ -37,6 +37,9 @@ struct rpca_ctx {
 // Set ctx->last_error and return status.
 int set_status(rpca_ctx *ctx, int status, const std::string &msg);
 
+// Create ctx->aux (default priority) and its events on first use.
+int ensure_aux(rpca_ctx *ctx);
+
 // Make sure buf holds at least `bytes`; returns RPCA_OK or RPCA_ERR_NOMEM.
 int ensure_buf(rpca_ctx *ctx, DevBuf &buf, size_t bytes);
 
