@@ -359,6 +359,9 @@ rpca_batch *batch_new(rpca_ctx *ctx, const rpca_opts &o, const rpca_batch_tuning
     b->wctx->recon_waves_per_cu = ctx->recon_waves_per_cu;
     bool ok = hipStreamCreateWithFlags(&b->bs, hipStreamNonBlocking) == hipSuccess;
     for (auto &e : b->ev) ok = ok && hipEventCreate(&e) == hipSuccess;
+    // the second stream of the lane filter, made here and not on first use,
+    // so that no run, captured or not, creates a stream
+    ok = ok && ensure_aux(b->wctx) == RPCA_OK;
     if (!ok) {
         *status = set_status(ctx, RPCA_ERR_DEVICE, "batch: stream or event creation failed");
         rpca_batch_destroy(b);
