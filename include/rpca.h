@@ -61,6 +61,17 @@ enum {
     RPCA_ERR_UNSUPPORTED = -6    /* shape outside what the kernels were built for        */
 };
 
+/* Codes a filter call writes to iters[k] in place of an iteration count:
+ *   RPCA_ITERS_BAD_INDEX  the regression index cols[k] / rows[k] is outside M;
+ *                         Qt[:, k] / Pt[:, k] is not written.
+ *   RPCA_ITERS_NONFINITE  the regression's input x holds an Inf or NaN (or
+ *                         ||x||_2^2 overflows FP32): no iteration runs and the
+ *                         output column is NaN.  The synchronous calls
+ *                         (rpca_solve, rpca_solve_factored, rpca_batch_job_info,
+ *                         served requests) then return RPCA_ERR_NUMERIC. */
+#define RPCA_ITERS_BAD_INDEX (-2147483647 - 1)
+#define RPCA_ITERS_NONFINITE (-2147483647)
+
 /*
  * Constants of the method.  The paper fixes s_r = s_c = 10 (Sec. 3.1) and
  * lambda~ = 1/sqrt(max(p, q)) (eq. SPCP); it leaves eps, rho, beta_0 and
@@ -184,7 +195,9 @@ int rpca_seed(rpca_ctx_t ctx, const float *M, int64_t m, int64_t n, int64_t ldm,
  *   Qt         device FP32 output, r x nc, ld r.
  *   iters      device int32[nc] output or NULL: iterations used; -filt_max_iter
  *              when the stopping test was not met (then Qt holds the last
- *              iterate); 0 for an all-zero column.
+ *              iterate); 0 for an all-zero column; RPCA_ITERS_NONFINITE for a
+ *              column holding Inf or NaN, RPCA_ITERS_BAD_INDEX for an index
+ *              outside M.
  * Asynchronous on `stream`.  Returns RPCA_ERR_UNSUPPORTED for p or r beyond
  * the built kernel classes (p <= 304, r <= 64 with p*r bounded by LDS).
  */
@@ -270,7 +283,9 @@ int rpca_filter_complete(rpca_ctx_t ctx, const float *M, int64_t m, int64_t n, i
  * seed_rows / seed_cols: device int64 arrays of os_r*r and os_c*r sorted
  * indices, or both NULL to draw them with rpca_sample_indices(opts->rng_seed).
  * L, S: device FP32 outputs.  info (host, may be NULL) receives the summary.
- * Synchronous.  Returns the most severe status of the steps.
+ * Synchronous.  Returns the most severe status of the steps; RPCA_ERR_NUMERIC
+ * when M^s or the input of some regression holds an Inf or NaN.  (An Inf or
+ * NaN in M[I_c, J_c], which no regression reads, only passes into S there.)
  */
 int rpca_solve(rpca_ctx_t ctx, const float *M, int64_t m, int64_t n, int64_t ldm, int32_t r,
                const rpca_opts *opts, const int64_t *seed_rows, const int64_t *seed_cols,
@@ -371,6 +386,9 @@ int rpca_batch_run(rpca_batch_t batch, hipStream_t stream);
  * iterations, filter iteration statistics; t_seed_ms is the job's seed wall
  * time, t_filter_ms / t_reconstruct_ms the device time of the whole batch's
  * filter / completion phase of the last run.  Synchronizes with the last run.
+ * Returns the job's seed warning, RPCA_WARN_NOT_CONVERGED, or
+ * RPCA_ERR_NUMERIC when one of its regressions read an Inf or NaN of M (its
+ * L and S then hold NaN in that row or column).
  */
 int rpca_batch_job_info(rpca_batch_t batch, int64_t job, rpca_info *info);
 

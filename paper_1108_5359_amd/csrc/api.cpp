@@ -133,6 +133,21 @@ FilterConsts consts_of(const rpca_opts &o)
     return c;
 }
 
+IterSummary summarize_iters(const int32_t *its, size_t n)
+{
+    IterSummary s;
+    for (size_t i = 0; i < n; ++i) {
+        const int32_t k = its[i];
+        if (k == RPCA_ITERS_BAD_INDEX) { ++s.bad_index; continue; }
+        if (k == RPCA_ITERS_NONFINITE) { ++s.nonfinite; continue; }
+        if (k < 0) ++s.not_converged;
+        const int32_t ak = k < 0 ? -k : k;
+        s.total += ak;
+        s.max = std::max(s.max, ak);
+    }
+    return s;
+}
+
 int set_status(rpca_ctx *ctx, int status, const std::string &msg)
 {
     if (ctx) ctx->last_error = msg;
@@ -606,14 +621,9 @@ int rpca_solve(rpca_ctx_t ctx, const float *M, int64_t m, int64_t n, int64_t ldm
     if (!its.empty())
         RPCA_HIP_TRY(ctx, hipMemcpyAsync(its.data(), dit, its.size() * 4, hipMemcpyDeviceToHost, sm));
     RPCA_HIP_TRY(ctx, hipStreamSynchronize(sm));
-    int64_t total = 0, bad = 0;
-    int32_t kmax = 0;
-    for (int32_t k : its) {
-        if (k < 0) ++bad;
-        const int32_t ak = k < 0 ? -k : k;
-        total += ak;
-        kmax = std::max(kmax, ak);
-    }
+    const IterSummary is = summarize_iters(its.data(), its.size());
+    const int64_t total = is.total, bad = is.not_converged;
+    const int32_t kmax = is.max;
     if (info) {
         float tf = 0, tr = 0;
         (void)hipEventElapsedTime(&tf, ctx->ev[0], ctx->ev[1]);
@@ -628,6 +638,9 @@ int rpca_solve(rpca_ctx_t ctx, const float *M, int64_t m, int64_t n, int64_t ldm
         info->t_filter_ms = tf;
         info->t_reconstruct_ms = tr;
     }
+    if (is.nonfinite)
+        return set_status(ctx, RPCA_ERR_NUMERIC, std::to_string(is.nonfinite) +
+                                                     " regressions read a non-finite entry of M");
     if (seed_st > 0) return set_status(ctx, seed_st, seed_msg);
     if (bad) return set_status(ctx, RPCA_WARN_NOT_CONVERGED, std::to_string(bad) + " regressions missed filt_eps");
     return RPCA_OK;

@@ -227,7 +227,8 @@ __device__ __forceinline__ void lane_item(const LaneSide &s, int64_t first, int 
     float beta = xx > 0.0f ? C.beta0_scale / sqrtf(xx) : 1.0f;
     const float beta_bar = C.beta_max_scale * beta;
     const float tol = C.eps * xinf;
-    bool done = !(valid && xinf > 0.0f);
+    const bool bad = valid && nonfinite_norm(xx);     // x holds Inf / NaN
+    bool done = !(valid && xinf > 0.0f) || bad;
     int K = 0;
     floatx4 z[RB];
 #pragma unroll
@@ -381,10 +382,11 @@ __device__ __forceinline__ void lane_item(const LaneSide &s, int64_t first, int 
 #pragma unroll
                 for (int i = 0; i < 4; ++i) {
                     const int kk = 4 * rb + i;
-                    if (kk < r) s.Z[kk + j * s.ldz] = z[rb][i];
+                    if (kk < r) s.Z[kk + j * s.ldz] = bad ? __builtin_nanf("") : z[rb][i];
                 }
         }
-        if (j < s.nreg && s.iters) s.iters[j] = !valid ? INT_MIN : (done ? K : -C.max_iter);
+        if (j < s.nreg && s.iters) s.iters[j] = !valid ? RPCA_ITERS_BAD_INDEX
+                                                : (bad ? RPCA_ITERS_NONFINITE : (done ? K : -C.max_iter));
     }
 }
 

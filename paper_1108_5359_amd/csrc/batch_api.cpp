@@ -645,18 +645,14 @@ int rpca_batch_job_info(rpca_batch_t b, int64_t job, rpca_info *info)
     RPCA_HIP_TRY(ctx, hipStreamSynchronize(b->bs));
     const BatchJobState &S = b->js[job];
     std::vector<int32_t> its((size_t)(S.nc + S.mc));
-    int64_t total = 0, bad = 0;
-    int32_t kmax = 0;
+    IterSummary is;
     if (b->runs > 0 && !its.empty()) {
         RPCA_HIP_TRY(ctx, hipMemcpyAsync(its.data(), b->at(S.o_it), its.size() * 4, hipMemcpyDeviceToHost, b->bs));
         RPCA_HIP_TRY(ctx, hipStreamSynchronize(b->bs));
-        for (int32_t k : its) {
-            if (k < 0) ++bad;
-            const int32_t ak = k < 0 ? -k : k;
-            total += ak;
-            kmax = std::max(kmax, ak);
-        }
+        is = summarize_iters(its.data(), its.size());
     }
+    const int64_t total = is.total, bad = is.not_converged;
+    const int32_t kmax = is.max;
     float tf = 0, tr = 0;
     if (b->runs > 0) {
         (void)hipEventElapsedTime(&tf, b->ev[0], b->ev[1]);
@@ -671,6 +667,10 @@ int rpca_batch_job_info(rpca_batch_t b, int64_t job, rpca_info *info)
     info->t_seed_ms = S.t_seed_ms;
     info->t_filter_ms = tf;
     info->t_reconstruct_ms = tr;
+    if (is.nonfinite)
+        return set_status(ctx, RPCA_ERR_NUMERIC, "job " + std::to_string(job) + ": " +
+                                                     std::to_string(is.nonfinite) +
+                                                     " regressions read a non-finite entry of M");
     return S.seed_status > 0 ? S.seed_status : (bad ? RPCA_WARN_NOT_CONVERGED : RPCA_OK);
 }
 

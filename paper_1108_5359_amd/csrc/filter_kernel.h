@@ -253,7 +253,8 @@ l1_filter_kernel(FilterLaunch L)
     float beta = xx > 0.0f ? L.c.beta0_scale / sqrtf(xx) : 1.0f;
     const float beta_bar = L.c.beta_max_scale * beta;
     const float tol = L.c.eps * xinf;
-    bool done = !(valid && xinf > 0.0f);
+    const bool bad = valid && nonfinite_norm(xx);     // x holds Inf / NaN
+    bool done = !(valid && xinf > 0.0f) || bad;
     int K = 0;
 
     floatx4 z[RT];
@@ -375,11 +376,12 @@ l1_filter_kernel(FilterLaunch L)
 #pragma unroll
                 for (int v = 0; v < 4; ++v) {
                     const int kk = 16 * mt + 4 * v + g;
-                    if (kk < r) Zout[kk + j * ldz] = z[mt][v];
+                    if (kk < r) Zout[kk + j * ldz] = bad ? __builtin_nanf("") : z[mt][v];
                 }
         }
         if (iters && g == 0)
-            iters[j] = !valid ? INT_MIN : (done ? K : -L.c.max_iter);
+            iters[j] = !valid ? RPCA_ITERS_BAD_INDEX
+                               : (bad ? RPCA_ITERS_NONFINITE : (done ? K : -L.c.max_iter));
     }
 }
 
@@ -559,7 +561,8 @@ l1_filter_split_kernel(FilterLaunch L)
     float beta = xx > 0.0f ? L.c.beta0_scale / sqrtf(xx) : 1.0f;
     const float beta_bar = L.c.beta_max_scale * beta;
     const float tol = L.c.eps * xinf;
-    bool done = !(valid && xinf > 0.0f);
+    const bool bad = valid && nonfinite_norm(xx);     // x holds Inf / NaN
+    bool done = !(valid && xinf > 0.0f) || bad;
     int K = 0;
     float inv_beta_prev = 0.0f, res_part = 0.0f;
     floatx4 z[RT];
@@ -751,11 +754,12 @@ l1_filter_split_kernel(FilterLaunch L)
 #pragma unroll
                 for (int v = 0; v < 4; ++v) {
                     const int kk = 16 * mt + 4 * v + g;
-                    if (kk < r) Zout[kk + j * ldz] = z[mt][v];
+                    if (kk < r) Zout[kk + j * ldz] = bad ? __builtin_nanf("") : z[mt][v];
                 }
         }
         if (iters && g == 0)
-            iters[j] = !valid ? INT_MIN : (done ? K : -L.c.max_iter);
+            iters[j] = !valid ? RPCA_ITERS_BAD_INDEX
+                               : (bad ? RPCA_ITERS_NONFINITE : (done ? K : -L.c.max_iter));
     }
 }
 
@@ -906,7 +910,8 @@ l1_filter_kernel_f16(FilterLaunch L)
     float beta = xx > 0.0f ? L.c.beta0_scale / sqrtf(xx) : 1.0f;
     const float beta_bar = L.c.beta_max_scale * beta;
     const float tol = L.c.eps * xinf;
-    bool done = !(valid && xinf > 0.0f);
+    const bool bad = valid && nonfinite_norm(xx);     // x holds Inf / NaN
+    bool done = !(valid && xinf > 0.0f) || bad;
     int K = 0;
 
     floatx4 z[RT];
@@ -1041,11 +1046,12 @@ l1_filter_kernel_f16(FilterLaunch L)
 #pragma unroll
                 for (int v = 0; v < 4; ++v) {
                     const int kk = 16 * mt + 4 * v + g;
-                    if (kk < r) Zout[kk + j * ldz] = z[mt][v];
+                    if (kk < r) Zout[kk + j * ldz] = bad ? __builtin_nanf("") : z[mt][v];
                 }
         }
         if (iters && g == 0)
-            iters[j] = !valid ? INT_MIN : (done ? K : -L.c.max_iter);
+            iters[j] = !valid ? RPCA_ITERS_BAD_INDEX
+                               : (bad ? RPCA_ITERS_NONFINITE : (done ? K : -L.c.max_iter));
     }
 }
 
@@ -1233,7 +1239,8 @@ l1_filter_kernel_f16q(FilterLaunch L)
         float beta = xx > 0.0f ? L.c.beta0_scale / sqrtf(xx) : 1.0f;
         const float beta_bar = L.c.beta_max_scale * beta;
         const float tol = L.c.eps * xinf;
-        bool done = !(valid && xinf > 0.0f);
+        const bool bad = valid && nonfinite_norm(xx);     // x holds Inf / NaN
+        bool done = !(valid && xinf > 0.0f) || bad;
         int K = 0;
         float inv_beta_prev = 0.0f, res_part = 0.0f;
         floatx4 z[RT];
@@ -1426,11 +1433,12 @@ l1_filter_kernel_f16q(FilterLaunch L)
 #pragma unroll
                     for (int v = 0; v < 4; ++v) {
                         const int kk = 16 * mt + 4 * v + g;
-                        if (kk < r) Zout[kk + j * ldz] = z[mt][v];
+                        if (kk < r) Zout[kk + j * ldz] = bad ? __builtin_nanf("") : z[mt][v];
                     }
             }
             if (iters && g == 0)
-                iters[j] = !valid ? INT_MIN : (done ? K : -L.c.max_iter);
+                iters[j] = !valid ? RPCA_ITERS_BAD_INDEX
+                               : (bad ? RPCA_ITERS_NONFINITE : (done ? K : -L.c.max_iter));
         }
     }
 }

@@ -73,9 +73,16 @@ int launch_reconstruct(rpca_ctx *ctx, const ReconArgs &a, hipStream_t stream)
     const size_t fbytes = (size_t)(a.m + a.n) * R4 * sizeof(float);
     int st = ensure_buf(ctx, ctx->factors, fbytes);
     if (st != RPCA_OK) return st;
-    float *F = static_cast<float *>(ctx->factors.ptr);
+    return launch_reconstruct_with(ctx, a, static_cast<float *>(ctx->factors.ptr), stream);
+}
+
+int launch_reconstruct_with(rpca_ctx *ctx, const ReconArgs &a, float *factors, hipStream_t stream)
+{
+    const int R4 = (a.r + 3) / 4 * 4;
+    if (R4 > 64) return set_status(ctx, RPCA_ERR_UNSUPPORTED, "reconstruct: rank above 64");
+    float *F = factors;
     float *G = F + (size_t)a.m * R4;
-    st = launch_assemble_range(ctx, a, R4, F, G, 0, a.m + a.n, stream);
+    int st = launch_assemble_range(ctx, a, R4, F, G, 0, a.m + a.n, stream);
     if (st != RPCA_OK) return st;
     return launch_complete_slab(ctx, a, R4, F, G, 0, a.n, stream);
 }

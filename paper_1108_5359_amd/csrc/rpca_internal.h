@@ -43,6 +43,15 @@ int ensure_aux(rpca_ctx *ctx);
 // Make sure buf holds at least `bytes`; returns RPCA_OK or RPCA_ERR_NOMEM.
 int ensure_buf(rpca_ctx *ctx, DevBuf &buf, size_t bytes);
 
+// Summary of per-regression iteration codes (see RPCA_ITERS_*): total of
+// |count|, regressions that missed the stopping test, largest count, and
+// regressions with a bad index or a non-finite input.
+struct IterSummary {
+    int64_t total = 0, not_converged = 0, bad_index = 0, nonfinite = 0;
+    int32_t max = 0;
+};
+IterSummary summarize_iters(const int32_t *its, size_t n);
+
 struct FilterConsts;
 // Range checks of the options (RPCA_ERR_ARG with a message on failure).
 int check_opts(rpca_ctx *ctx, const rpca_opts &o);
@@ -126,6 +135,9 @@ struct ReconArgs {
 };
 
 int launch_reconstruct(rpca_ctx *ctx, const ReconArgs &a, hipStream_t stream);
+// The same into caller-provided factor storage ((m + n) * R4 floats, R4 = r
+// rounded up to 4); allocates nothing.
+int launch_reconstruct_with(rpca_ctx *ctx, const ReconArgs &a, float *factors, hipStream_t stream);
 
 // Pieces of the completion for the overlapped form: assemble rows
 // [first_row, end_row) of the stacked factors (F rows are [0, m), G row j is
@@ -181,6 +193,11 @@ int run_seed_small(rpca_ctx *ctx, const SmallSeedArgs *args, int n, const rpca_o
 // they mean in FilterSide; cls is the compiled (P4, RB) class index.
 constexpr int kLaneMaxP = 80;
 constexpr int kLaneMaxR = 8;
+
+// A regression whose input holds an Inf or NaN: its sum of squares ||x||_2^2
+// is NaN or +Inf (so is one that overflows FP32).  Costs nothing per element:
+// every filter kernel forms that sum for beta_0 anyway.
+__device__ __forceinline__ bool nonfinite_norm(float xx) { return !(xx <= 3.40282347e38f); }
 
 struct LaneSide {
     const float *M;

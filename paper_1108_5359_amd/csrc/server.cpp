@@ -97,7 +97,8 @@ int run_batch(rpca_batch *b, rpca_ctx *ctx, const std::vector<rpca_job> &jobs,
     if (st < 0) return st;
     for (int64_t k = 0; k < n; ++k) {
         status[k] = rpca_batch_job_info(b, k, &info[k]);
-        if (status[k] < 0) return status[k];
+        // a job whose input holds Inf / NaN fails alone; the others stand
+        if (status[k] < 0 && status[k] != RPCA_ERR_NUMERIC) return status[k];
     }
     (void)ctx;
     return RPCA_OK;

@@ -31,6 +31,8 @@ RPCA_ERR_DEVICE = -3
 RPCA_ERR_SEED = -4
 RPCA_ERR_NUMERIC = -5
 RPCA_ERR_UNSUPPORTED = -6
+RPCA_ITERS_BAD_INDEX = -2147483648
+RPCA_ITERS_NONFINITE = -2147483647
 
 
 class rpca_opts(ctypes.Structure):

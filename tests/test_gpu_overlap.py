@@ -15,7 +15,8 @@ import pytest
 
 import oracle
 import synth
-from gpu_util import REL_TOL, dev_f64_colmajor, dev_i64, dev_matrix, host_matrix, relF, say
+from gpu_util import (REL_TOL, dev_f64_colmajor, dev_i64, dev_matrix, host_matrix, relF, say,
+                      support_mismatch)
 from test_gpu_parity import R, case, ctx, small_case  # noqa: F401  (fixtures and cached cases)
 
 pytestmark = pytest.mark.gpu
@@ -69,11 +70,21 @@ def test_overlapped_equals_sequential_c1(R, ctx, seed, chunks, precision):
 
 
 def test_overlapped_equals_sequential_c2_full_size(R, ctx):
+    # m = n = 10000: the two forms agree bit for bit (checked in _run_both);
+    # the overlapped result against the oracle on 200000 sampled entries
     pr, r, I, J, res = case("c2", 1)
     k = res.U.shape[1]
     say("overlap c2 full size")
     Lh, Sh = _run_both(R, ctx, pr, I, J, res.U, res.sigma, res.V, k, 4, 0)
-    assert relF(Lh, res.L if res.L is not None else Lh) <= REL_TOL
+    rng = np.random.default_rng(1)
+    rows = rng.integers(0, pr.m, 200000)
+    cols = rng.integers(0, pr.n, 200000)
+    Lref = oracle.complete_entries(rows, cols, I, J, pr.m, pr.n, res.U, res.sigma, res.V, res.Qt,
+                                   res.Pt)
+    Sref = pr.M[rows, cols].astype(np.float64) - Lref
+    assert relF(Lh[rows, cols], Lref) <= REL_TOL
+    assert relF(Sh[rows, cols], Sref) <= REL_TOL
+    assert support_mismatch(Sh[rows, cols], Sref, float(np.abs(pr.M).max())) == 0
 
 
 @pytest.mark.parametrize("m,n,r,ld_pad,chunks", [(333, 517, 3, 5, 4), (1200, 700, 1, 0, 9),

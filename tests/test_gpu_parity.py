@@ -225,11 +225,35 @@ def test_solve_matches_oracle_c2_sampled(R, ctx):
     assert relF(Lg, Lref) <= REL_TOL
     assert relF(Sg, Sref) <= REL_TOL
     assert support_mismatch(Sg, Sref, float(np.abs(pr.M).max())) == 0
-    # every regression against the oracle, through the blocks it defines
+    # mean iteration count within 10% of the oracle's (FP32 vs FP64 stopping test)
     its = info.filt_iters_total / (len(res.col_iters) + len(res.row_iters))
     k_or = np.concatenate([res.col_iters, res.row_iters]).mean()
     assert abs(its - k_or) <= 0.1 * k_or
     assert info.filt_not_converged == 0
+
+
+def test_filter_every_regression_c2(R, ctx):
+    # m = n = 10000, r = 20: all 9800 column and 9800 row regressions of the
+    # benchmarked workload, each against the oracle's through the block it
+    # defines (U q~_j = L[I_s, j], p~_i^T V^T = L[i, J_s]), per regression and
+    # over the whole block
+    pr, r, I, J, res = case("c2", 1)
+    k = res.U.shape[1]
+    Jc, Ic = oracle.complement(J, pr.n), oracle.complement(I, pr.m)
+    say("filter c2 every regression")
+    st, Qt, itc = _filter_cols_gpu(R, ctx, pr, I, Jc, res.U, k)
+    assert st == R.RPCA_OK and (itc > 0).all()
+    Lc, Lc_ref = res.U @ Qt, res.U @ res.Qt
+    assert relF(Lc, Lc_ref) <= REL_TOL
+    per = np.linalg.norm(Lc - Lc_ref, axis=0) / np.linalg.norm(Lc_ref, axis=0)
+    assert per.max() <= 10 * REL_TOL, (per.argmax(), per.max())
+    st, Pt, itr = _filter_rows_gpu(R, ctx, pr, J, Ic, res.V, k)
+    assert st == R.RPCA_OK and (itr > 0).all()
+    Lr, Lr_ref = Pt.T @ res.V.T, res.Pt.T @ res.V.T
+    assert relF(Lr, Lr_ref) <= REL_TOL
+    per = np.linalg.norm(Lr - Lr_ref, axis=1) / np.linalg.norm(Lr_ref, axis=1)
+    assert per.max() <= 10 * REL_TOL, (per.argmax(), per.max())
+    say(f"  relF(L^c)={relF(Lc, Lc_ref):.2e} relF(L^r)={relF(Lr, Lr_ref):.2e}")
 
 
 def test_seed_matches_oracle(R, ctx):
@@ -368,3 +392,37 @@ def test_argument_errors(R, ctx):
     with pytest.raises(R.RpcaError) as e:
         R.rpca_solve(ctx, Mbad, pr.m, pr.n, pr.m, r, o, dev_i64(I), dev_i64(J), L, pr.m, S, pr.m)
     assert e.value.status == R.RPCA_ERR_NUMERIC
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_nonfinite_regression_input(R, ctx, precision):
+    # NaN in M[I_s, j] (read by column regression j only) and +Inf in M[i, J_s]
+    # (row regression i only): those regressions report RPCA_ITERS_NONFINITE
+    # and a NaN output; every other regression is untouched; rpca_solve
+    # returns RPCA_ERR_NUMERIC
+    import torch
+    pr, r, I, J, res = case("c1", 1)
+    Jc, Ic = oracle.complement(J, pr.n), oracle.complement(I, pr.m)
+    M2 = pr.M.copy(order="F")
+    M2[I[3], Jc[5]] = np.nan
+    M2[Ic[7], J[2]] = np.inf
+    pr2 = synth.Problem(M=M2, A0=pr.A0, B0=pr.B0, support=None, m=pr.m, n=pr.n, r=r, seed=0)
+    o = R.rpca_opts_default(precision=precision)
+    say(f"non-finite regression inputs precision={precision}")
+    st, Qt, itc = _filter_cols_gpu(R, ctx, pr2, I, Jc, res.U, 10, opts=o)
+    assert itc[5] == R.RPCA_ITERS_NONFINITE and np.isnan(Qt[:, 5]).all()
+    keep = np.arange(len(Jc)) != 5
+    assert (itc[keep] > 0).all() and np.isfinite(Qt[:, keep]).all()
+    assert relF(res.U @ Qt[:, keep], res.U @ res.Qt[:, keep]) <= REL_TOL
+    st, Pt, itr = _filter_rows_gpu(R, ctx, pr2, J, Ic, res.V, 10, opts=o)
+    assert itr[7] == R.RPCA_ITERS_NONFINITE and np.isnan(Pt[:, 7]).all()
+    keep = np.arange(len(Ic)) != 7
+    assert (itr[keep] > 0).all()
+    assert relF(Pt[:, keep].T @ res.V.T, res.Pt[:, keep].T @ res.V.T) <= REL_TOL
+    Md = dev_matrix(M2)
+    L = torch.zeros_like(Md)
+    S = torch.zeros_like(Md)
+    with pytest.raises(R.RpcaError) as e:
+        R.rpca_solve(ctx, Md, pr.m, pr.n, pr.m, r, o, dev_i64(I), dev_i64(J), L, pr.m, S, pr.m)
+    assert e.value.status == R.RPCA_ERR_NUMERIC
+    assert "non-finite" in ctx.last_error()
