@@ -257,6 +257,30 @@ int rpca_reconstruct(rpca_ctx_t ctx, const float *M, int64_t m, int64_t n, int64
                      float *S, int64_t lds, hipStream_t stream);
 
 /*
+ * rpca_reconstruct for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc).  Same arguments, same kernels and the same results, bit for
+ * bit, as rpca_reconstruct; the assembled factors (the only scratch of the
+ * completion) go to a fixed device array of RPCA_NOALLOC_SCRATCH_BYTES per
+ * device, which the library holds from its first context on that device until
+ * the process ends, instead of the context's workspace.  The call allocates
+ * nothing (no hipMalloc, no library allocator).
+ * Limit: (m + n) * 4 * ceil4(r) bytes <= RPCA_NOALLOC_SCRATCH_BYTES, i.e.
+ * (m + n) * ceil4(r) <= 8388608 (m = n = 50000 at r = 50 fits); larger
+ * problems get RPCA_ERR_ARG, and ranks above 64 RPCA_ERR_UNSUPPORTED.
+ * Every call on one device shares that device's array: calls that overlap on
+ * one device (two streams, two host threads) race and give wrong results, so
+ * order them on one stream.  Nothing in the array needs clearing: every call
+ * writes all the factor rows it reads.  Asynchronous on `stream`.
+ */
+#define RPCA_NOALLOC_SCRATCH_BYTES ((size_t)32 << 20)
+int rpca_reconstruct_noalloc(rpca_ctx_t ctx, const float *M, int64_t m, int64_t n, int64_t ldm,
+                             const int64_t *seed_rows, int64_t p, const int64_t *seed_cols,
+                             int64_t q, const double *U, const double *sigma, const double *V,
+                             int32_t r, const float *Qt, const float *Pt, float *L, int64_t ldl,
+                             float *S, int64_t lds, hipStream_t stream);
+
+/*
  * Steps 3, 4 and 5 together (Sec. 3.2-3.3; eqs. l1c', l1r', l1s'): what
  * rpca_filter followed by rpca_reconstruct computes, with the completion of
  * L and S overlapped with the filtering when opts->overlap_chunks > 0: the

@@ -254,6 +254,12 @@ int rpca_ctx_create(int device, rpca_ctx_t *out)
             return RPCA_ERR_DEVICE;
         }
     }
+    // device address of the no-allocation form's scratch (once per device)
+    if (noalloc_scratch_setup(device) != RPCA_OK) {
+        g_create_error = "hipGetSymbolAddress of the completion scratch failed";
+        rpca_ctx_destroy(ctx);
+        return RPCA_ERR_DEVICE;
+    }
     *out = ctx;
     return RPCA_OK;
 }
@@ -452,6 +458,41 @@ int rpca_reconstruct(rpca_ctx_t ctx, const float *M, int64_t m, int64_t n, int64
     RPCA_HIP_TRY(ctx, hipSetDevice(ctx->device));
     ReconArgs a{M, m, n, ldm, seed_rows, p, seed_cols, q, U, sigma, V, r, Qt, Pt, L, ldl, S, lds};
     return launch_reconstruct(ctx, a, stream);
+}
+
+int rpca_reconstruct_noalloc(rpca_ctx_t ctx, const float *M, int64_t m, int64_t n, int64_t ldm,
+                             const int64_t *seed_rows, int64_t p, const int64_t *seed_cols,
+                             int64_t q, const double *U, const double *sigma, const double *V,
+                             int32_t r, const float *Qt, const float *Pt, float *L, int64_t ldl,
+                             float *S, int64_t lds, hipStream_t stream)
+{
+    if (!ctx) return RPCA_ERR_ARG;
+    ctx->last_error.clear();
+    int st;
+    if ((st = check_matrix(ctx, M, m, n, ldm, "M")) != RPCA_OK) return st;
+    if ((st = check_matrix(ctx, L, m, n, ldl, "L")) != RPCA_OK) return st;
+    if ((st = check_matrix(ctx, S, m, n, lds, "S")) != RPCA_OK) return st;
+    if (!seed_rows || !seed_cols || !U || !sigma || !V || (n > q && !Qt) || (m > p && !Pt))
+        return set_status(ctx, RPCA_ERR_ARG, "reconstruct_noalloc: NULL argument");
+    if (p < 1 || q < 1 || p > m || q > n || r < 1 || r > std::min(p, q))
+        return set_status(ctx, RPCA_ERR_ARG, "reconstruct_noalloc: need 1 <= r <= min(p, q), p <= m, q <= n");
+    if (r > 64) return set_status(ctx, RPCA_ERR_UNSUPPORTED, "reconstruct_noalloc: rank above 64");
+    const int64_t R4 = (r + 3) / 4 * 4;
+    const double need = (double)(m + n) * (double)R4 * sizeof(float);
+    if (need > (double)RPCA_NOALLOC_SCRATCH_BYTES)
+        return set_status(ctx, RPCA_ERR_ARG,
+                          "reconstruct_noalloc: the factors need (m + n) * 4 * ceil4(r) = " +
+                              std::to_string((long long)need) + " bytes, above the " +
+                              std::to_string((long long)RPCA_NOALLOC_SCRATCH_BYTES) +
+                              "-byte scratch; use rpca_reconstruct");
+    if ((const void *)L == (const void *)S || (const void *)L == (const void *)M ||
+        (const void *)S == (const void *)M)
+        return set_status(ctx, RPCA_ERR_ARG, "reconstruct_noalloc: L, S and M must be distinct buffers");
+    RPCA_HIP_TRY(ctx, hipSetDevice(ctx->device));
+    float *factors = static_cast<float *>(noalloc_scratch(ctx->device));
+    if (!factors) return set_status(ctx, RPCA_ERR_DEVICE, "reconstruct_noalloc: scratch not set up on this device");
+    ReconArgs a{M, m, n, ldm, seed_rows, p, seed_cols, q, U, sigma, V, r, Qt, Pt, L, ldl, S, lds};
+    return launch_reconstruct_with(ctx, a, factors, stream);
 }
 
 int rpca_filter_complete(rpca_ctx_t ctx, const float *M, int64_t m, int64_t n, int64_t ldm,

@@ -4,6 +4,7 @@
 
 #include <algorithm>
 #include <climits>
+#include <mutex>
 
 using namespace reconk;
 
@@ -85,6 +86,44 @@ int launch_reconstruct_with(rpca_ctx *ctx, const ReconArgs &a, float *factors, h
     int st = launch_assemble_range(ctx, a, R4, F, G, 0, a.m + a.n, stream);
     if (st != RPCA_OK) return st;
     return launch_complete_slab(ctx, a, R4, F, G, 0, a.n, stream);
+}
+
+// ---------------------------------------------------------------- no-allocation form
+// The factors F and G of rpca_reconstruct_noalloc live in this file-scope
+// device array instead of the context's workspace.  Each device that loads
+// the library holds its own copy (kNoAllocScratchBytes, until the process
+// ends); in host code `scratch` names a host-side stand-in, so kernels get
+// the device address taken once per device by noalloc_scratch_setup.
+namespace {
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+} // namespace
+
+int noalloc_scratch_setup(int device)
+{
+    if (device < 0 || device >= kMaxDevices) return RPCA_ERR_ARG;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (g_scratch_ptr[device]) return RPCA_OK;
+    int cur = -1;
+    if (hipGetDevice(&cur) != hipSuccess || cur != device) return RPCA_ERR_DEVICE;
+    void *ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr) {
+        (void)hipGetLastError();
+        return RPCA_ERR_DEVICE;
+    }
+    g_scratch_ptr[device] = ptr;
+    return RPCA_OK;
+}
+
+void *noalloc_scratch(int device)
+{
+    if (device < 0 || device >= kMaxDevices) return nullptr;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    return g_scratch_ptr[device];
 }
 
 int launch_assemble_range(rpca_ctx *ctx, const ReconArgs &a, int R4, float *F, float *G,

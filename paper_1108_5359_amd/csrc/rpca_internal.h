@@ -139,6 +139,13 @@ int launch_reconstruct(rpca_ctx *ctx, const ReconArgs &a, hipStream_t stream);
 // rounded up to 4); allocates nothing.
 int launch_reconstruct_with(rpca_ctx *ctx, const ReconArgs &a, float *factors, hipStream_t stream);
 
+// Scratch of the no-allocation completion: a file-scope device array of this
+// size per device.  noalloc_scratch_setup takes its device address once per
+// device (that device current); noalloc_scratch returns it (null before).
+constexpr size_t kNoAllocScratchBytes = RPCA_NOALLOC_SCRATCH_BYTES;
+int noalloc_scratch_setup(int device);
+void *noalloc_scratch(int device);
+
 // Pieces of the completion for the overlapped form: assemble rows
 // [first_row, end_row) of the stacked factors (F rows are [0, m), G row j is
 // m + j) and complete the column slab [j0, j1) of L and S.

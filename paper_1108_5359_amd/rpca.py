@@ -87,6 +87,9 @@ lib.rpca_filter.argtypes = [_vp, _vp, _i64, _i64, _i64, _vp, _i64, _vp, _i64, _v
                             _vp, _vp, _i32, ctypes.POINTER(rpca_opts), _vp, _vp, _vp, _vp, _vp]
 lib.rpca_reconstruct.argtypes = [_vp, _vp, _i64, _i64, _i64, _vp, _i64, _vp, _i64, _vp, _vp,
                                  _vp, _i32, _vp, _vp, _vp, _i64, _vp, _i64, _vp]
+lib.rpca_reconstruct_noalloc.argtypes = lib.rpca_reconstruct.argtypes
+lib.rpca_reconstruct_noalloc.restype = ctypes.c_int
+RPCA_NOALLOC_SCRATCH_BYTES = 32 << 20
 lib.rpca_filter_complete.argtypes = [_vp, _vp, _i64, _i64, _i64, _vp, _i64, _vp, _i64, _vp, _vp,
                                      _vp, _vp, _vp, _i32, ctypes.POINTER(rpca_opts), _vp, _vp,
                                      _vp, _vp, _vp, _i64, _vp, _i64, _vp]
@@ -223,6 +226,14 @@ def rpca_reconstruct(ctx: Context, M, m, n, ldm, seed_rows, p, seed_cols, q, U, 
                                           _ptr(seed_cols), q, _ptr(U), _ptr(sigma), _ptr(V), r,
                                           _ptr(Qt), _ptr(Pt), _ptr(L), ldl, _ptr(S), lds,
                                           _stream(stream)))
+
+
+def rpca_reconstruct_noalloc(ctx: Context, M, m, n, ldm, seed_rows, p, seed_cols, q, U, sigma, V,
+                             r, Qt, Pt, L, ldl, S, lds, stream=None):
+    return ctx.check(lib.rpca_reconstruct_noalloc(ctx.handle, _ptr(M), m, n, ldm, _ptr(seed_rows), p,
+                                                  _ptr(seed_cols), q, _ptr(U), _ptr(sigma), _ptr(V),
+                                                  r, _ptr(Qt), _ptr(Pt), _ptr(L), ldl, _ptr(S), lds,
+                                                  _stream(stream)))
 
 
 def rpca_solve(ctx: Context, M, m, n, ldm, r, opts, seed_rows, seed_cols, L, ldl, S, lds,
