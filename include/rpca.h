@@ -316,6 +316,107 @@ int rpca_solve(rpca_ctx_t ctx, const float *M, int64_t m, int64_t n, int64_t ldm
                float *L, int64_t ldl, float *S, int64_t lds, rpca_info *info,
                hipStream_t stream);
 
+/*
+ * Algorithm 2, steps 2-4, stopping at the factored form of the low-rank part
+ * (Sec. 3.4: apart from M, l1 filtering needs only O(r(m + n)) storage):
+ *   L = [ U Sigma V^T   U Q~               ]   rows I_s
+ *       [ P~^T V^T      P~^T Sigma^-1 Q~   ]   rows I_c     (eqs. partition, l1s')
+ * with columns J_s on the left and J_c on the right.  No m x n output is
+ * written; rpca_reconstruct turns the factors into L and S when wanted, and
+ * rpca_filter_new_cols completes columns that arrive later.
+ *   seed_rows  device int64[p], seed_cols device int64[q]: sorted, distinct,
+ *              in range (any p, q with r <= min(p, q); normally os_r*r, os_c*r).
+ *   r          target rank: U (p x r, ld p), sigma (r), V (q x r, ld q) are
+ *              device FP64 outputs (columns beyond the rank used are zero).
+ *   Qt, Pt     device FP32 buffers of r * (n-q) and r * (m-p) floats: the
+ *              filtering of the sorted complements J_c and I_c, written as
+ *              r_used x (n-q) and r_used x (m-p) with ld r_used, where r_used
+ *              (info->r_used, <= r) is the rank of the seed that was used;
+ *              pass r_used as the rank to rpca_reconstruct and
+ *              rpca_filter_new_cols.
+ *   col_iters  device int32[n-q] or NULL, row_iters device int32[m-p] or NULL
+ *              (codes as for rpca_filter_cols).
+ *   info       host, may be NULL (t_reconstruct_ms = 0).
+ * Synchronous.  Status as rpca_solve's.
+ */
+int rpca_solve_factored(rpca_ctx_t ctx, const float *M, int64_t m, int64_t n, int64_t ldm,
+                        int32_t r, const rpca_opts *opts, const int64_t *seed_rows, int64_t p,
+                        const int64_t *seed_cols, int64_t q, double *U, double *sigma, double *V,
+                        float *Qt, int32_t *col_iters, float *Pt, int32_t *row_iters,
+                        rpca_info *info, hipStream_t stream);
+
+/*
+ * Online column filtering (Sec. 3.2, eq. l1c', applied to columns that arrive
+ * after the fit, e.g. the frames of a video in background modelling, Sec. 4.3):
+ * with the row factors of an earlier fit of the same m rows fixed, each new
+ * column j < nnew of Mnew is filtered against U (Algorithm 1 on
+ * x = Mnew[seed_rows, j]) into Qt_new[:, j], and only these columns are
+ * completed:
+ *   L[I_s, j] = U q~_j,   L[I_c, j] = P~^T Sigma^-1 q~_j   (eq. l1s'),
+ *   S[:, j] = Mnew[:, j] - L[:, j].
+ * The cost is O(r m) per column; the fitted matrix is not touched again.
+ *   Mnew        device FP32, m x nnew, ld ldm >= m (the new columns).
+ *   seed_rows   device int64[p]: the fit's sorted seed rows I_s.
+ *   U, sigma    device FP64 seed factors of the fit (p x r ld p, r), sigma > 0;
+ *               r is the rank the fit used.
+ *   Pt          device FP32 r x (m-p), ld r: the fit's row filtering over the
+ *               sorted I_c (as rpca_solve_factored writes it).
+ *   Qt_new      device FP32 output r x nnew, ld r; iters device int32[nnew] or
+ *               NULL (codes as for rpca_filter_cols).
+ *   L, S        device FP32 outputs m x nnew (ld ldl, lds >= m), distinct from
+ *               Mnew and from each other.
+ * Asynchronous on `stream`.  Errors: RPCA_ERR_ARG, RPCA_ERR_UNSUPPORTED (p, r
+ * outside the kernel classes), RPCA_ERR_NOMEM.  A column whose seed rows hold
+ * an Inf or NaN gets iters = RPCA_ITERS_NONFINITE and NaN in L and S.
+ */
+int rpca_filter_new_cols(rpca_ctx_t ctx, const float *Mnew, int64_t m, int64_t nnew, int64_t ldm,
+                         const int64_t *seed_rows, int64_t p, const double *U, const double *sigma,
+                         int32_t r, const float *Pt, const rpca_opts *opts, float *Qt_new,
+                         int32_t *iters, float *L, int64_t ldl, float *S, int64_t lds,
+                         hipStream_t stream);
+
+/*
+ * Target-rank estimation (Sec. 3.6, eqs. rank_test and rank_test1) for when
+ * r is not known.  Starting from the guess r0, the seed PCP (eq. SPCP) is
+ * solved on an m' x n' = (os_r r_k) x (os_c r_k) block and the rank r' of L^s
+ * is read off (as rpca_seed counts it, before any truncation).  If
+ * m'/r' >= os_r and n'/r' >= os_c (eq. rank_test) the seed is accepted and
+ * r' is the estimate; otherwise the block grows to (os_r r') x (os_c r') and
+ * the test repeats, unless the grown block would exceed half of M in either
+ * direction (eq. rank_test1): then the data are not low rank enough for
+ * l1 filtering and the loop stops (accepted = 0).  The blocks grow as
+ * prefixes of two caller-given orders, so each block contains the previous
+ * one: the seed rows of a block of p rows are row_order[0..p) sorted.  With
+ * cross_validate, one more block of the accepted size, disjoint from it
+ * (row_order[p..2p), col_order[q..2q)), is solved and its rank reported
+ * (Sec. 3.6, last paragraph); it runs only when 2p <= m and 2q <= n.
+ *   row_order   HOST int64[m], a permutation of 0..m-1 (checked).
+ *   col_order   HOST int64[n], a permutation of 0..n-1 (checked).
+ *   r0          initial guess, >= 1, with os_r r0 <= m/2 and os_c r0 <= n/2.
+ *   info        host output.
+ * The accepted seed's factors are those rpca_seed (or rpca_solve_factored)
+ * returns for the block's sorted indices and r = r_est (same arithmetic).
+ * Synchronous.  Returns RPCA_OK when eq. rank_test held (and the
+ * cross-validation block, if run, has the same rank); RPCA_WARN_RANK when
+ * the loop stopped at eq. rank_test1 or the cross-validation rank differs;
+ * RPCA_ERR_SEED when a seed has rank 0; RPCA_ERR_ARG, RPCA_ERR_NUMERIC as
+ * rpca_seed.
+ */
+#define RPCA_RANK_MAX_ROUNDS 16
+typedef struct {
+    int32_t r_est;                         /* rank of the last seed solved             */
+    int32_t accepted;                      /* 1: eq. rank_test held; 0: stopped        */
+    int32_t rounds;                        /* seed PCPs of the growing loop            */
+    int32_t cv_rank;                       /* rank of the cross-validation block, or -1 */
+    int64_t p, q;                          /* size of the last seed block solved        */
+    int32_t ranks[RPCA_RANK_MAX_ROUNDS];   /* r' found in each round                    */
+    int64_t ps[RPCA_RANK_MAX_ROUNDS];      /* block size of each round                  */
+    int64_t qs[RPCA_RANK_MAX_ROUNDS];
+} rpca_rank_info;
+int rpca_estimate_rank(rpca_ctx_t ctx, const float *M, int64_t m, int64_t n, int64_t ldm,
+                       int32_t r0, const rpca_opts *opts, const int64_t *row_order,
+                       const int64_t *col_order, int32_t cross_validate, rpca_rank_info *info);
+
 /* ------------------------------------------------------------------------
  * Batched form: steps 2-5 of Algorithm 2 for many independent problems
  * ("jobs") of uneven sizes.  The regressions of every job are independent

@@ -341,6 +341,85 @@ def complete_entries(rows, cols, seed_rows, seed_cols, m, n, U, sigma, V, Qt, Pt
     return out
 
 
+def complete_new_cols(Mnew: np.ndarray, seed_rows, U, sigma, Pt, Qt_new):
+    """L and S of columns that arrive after a fit (Sec. 3.2): every new column
+    j is a non-seed column, so by eq. l1c' its seed rows are ``U q~_j`` and by
+    eq. l1s' its other rows are ``P~^T Sigma^{-1} q~_j``, where ``q~_j`` is
+    the column filtering of ``Mnew[seed_rows, j]`` against U (Algorithm 1;
+    ``filter_cols``) and ``P~`` the fit's row filtering over the sorted
+    complement of the seed rows.  ``S = Mnew - L``."""
+    m = Mnew.shape[0]
+    I = np.asarray(seed_rows)
+    Ic = complement(I, m)
+    L = np.zeros(Mnew.shape)
+    L[I, :] = U @ Qt_new
+    L[Ic, :] = (Pt.T / sigma) @ Qt_new
+    S = np.asarray(Mnew, dtype=np.float64) - L
+    return L, S
+
+
+@dataclasses.dataclass
+class RankEstimate:
+    r_est: int          # rank of the last seed solved
+    accepted: bool      # eq. rank_test held (False: stopped by eq. rank_test1)
+    ranks: list         # r' of each round
+    sizes: list         # (p, q) of each round
+    cv_rank: int        # rank of the cross-validation block, -1 if not run
+
+    @property
+    def p(self):
+        return self.sizes[-1][0]
+
+    @property
+    def q(self):
+        return self.sizes[-1][1]
+
+
+def estimate_rank(M: np.ndarray, r0: int, row_order, col_order, os_r: int = 10, os_c: int = 10,
+                  cross_validate: bool = True, params: SeedParams = SeedParams(),
+                  max_rounds: int = 16) -> RankEstimate:
+    """Target-rank estimation of Sec. 3.6.
+
+    Solve the seed PCP on a (os_r r_k) x (os_c r_k) block and take the rank r'
+    of its L^s.  Accept when m'/r' >= os_r and n'/r' >= os_c (eq. rank_test);
+    otherwise grow the block to (os_r r') x (os_c r') and repeat, unless that
+    block exceeds half of M in either direction (eq. rank_test1), where the
+    loop stops unaccepted.  Readings: the blocks are prefixes of the given
+    row / column orders (so each contains the previous one; its indices are
+    the prefix, sorted); the cross-validation block is the next disjoint
+    block of the accepted size, solved only when it fits.
+    """
+    m, n = M.shape
+    row_order = np.asarray(row_order, dtype=np.int64)
+    col_order = np.asarray(col_order, dtype=np.int64)
+
+    def rank_of(r_first, p, c_first, q):
+        I = np.sort(row_order[r_first:r_first + p])
+        J = np.sort(col_order[c_first:c_first + q])
+        return seed_pcp(np.asarray(M[np.ix_(I, J)], dtype=np.float64), params).rank
+
+    p, q = os_r * r0, os_c * r0
+    ranks, sizes = [], []
+    accepted = False
+    for _ in range(max_rounds):
+        rk = rank_of(0, p, 0, q)
+        ranks.append(rk)
+        sizes.append((p, q))
+        if rk == 0:
+            break
+        if p / rk >= os_r and q / rk >= os_c:        # eq. rank_test
+            accepted = True
+            break
+        p2, q2 = os_r * rk, os_c * rk
+        if max(p2 / m, q2 / n) > 0.5:                # eq. rank_test1
+            break
+        p, q = p2, q2
+    cv = -1
+    if accepted and cross_validate and 2 * p <= m and 2 * q <= n:
+        cv = rank_of(p, p, q, q)
+    return RankEstimate(r_est=ranks[-1], accepted=accepted, ranks=ranks, sizes=sizes, cv_rank=cv)
+
+
 @dataclasses.dataclass
 class SolveResult:
     L: np.ndarray | None

@@ -269,7 +269,8 @@ int rpca_ctx_destroy(rpca_ctx_t ctx)
     if (!ctx) return RPCA_ERR_ARG;
     (void)hipSetDevice(ctx->device);
     (void)hipDeviceSynchronize();
-    for (DevBuf *b : {&ctx->seed_ws, &ctx->factors, &ctx->solve_ws, &ctx->scratch, &ctx->frag_ws})
+    for (DevBuf *b : {&ctx->seed_ws, &ctx->factors, &ctx->solve_ws, &ctx->scratch, &ctx->frag_ws,
+                      &ctx->iota_ws, &ctx->rank_ws})
         if (b->ptr) (void)hipFree(b->ptr);
     for (auto &e : ctx->ev)
         if (e) (void)hipEventDestroy(e);
@@ -685,6 +686,140 @@ int rpca_solve(rpca_ctx_t ctx, const float *M, int64_t m, int64_t n, int64_t ldm
     if (seed_st > 0) return set_status(ctx, seed_st, seed_msg);
     if (bad) return set_status(ctx, RPCA_WARN_NOT_CONVERGED, std::to_string(bad) + " regressions missed filt_eps");
     return RPCA_OK;
+}
+
+int rpca_solve_factored(rpca_ctx_t ctx, const float *M, int64_t m, int64_t n, int64_t ldm,
+                        int32_t r, const rpca_opts *opts, const int64_t *seed_rows, int64_t p,
+                        const int64_t *seed_cols, int64_t q, double *U, double *sigma, double *V,
+                        float *Qt, int32_t *col_iters, float *Pt, int32_t *row_iters,
+                        rpca_info *info, hipStream_t stream)
+{
+    if (!ctx) return RPCA_ERR_ARG;
+    ctx->last_error.clear();
+    int st;
+    if ((st = check_matrix(ctx, M, m, n, ldm, "M")) != RPCA_OK) return st;
+    if (!opts) return set_status(ctx, RPCA_ERR_ARG, "solve_factored: NULL opts");
+    if ((st = check_opts(ctx, *opts)) != RPCA_OK) return st;
+    if (!seed_rows || !seed_cols || !U || !sigma || !V || (q < n && !Qt) || (p < m && !Pt))
+        return set_status(ctx, RPCA_ERR_ARG, "solve_factored: NULL argument");
+    if (r < 1 || p < 1 || q < 1 || p > m || q > n || r > std::min(p, q))
+        return set_status(ctx, RPCA_ERR_ARG, "solve_factored: need 1 <= r <= min(p, q), p <= m, q <= n");
+    if (p > INT32_MAX || q > INT32_MAX) return set_status(ctx, RPCA_ERR_ARG, "solve_factored: seed too large");
+    if ((q < n && !filter_supported(ctx, (int)p, r, opts->precision)) ||
+        (p < m && !filter_supported(ctx, (int)q, r, opts->precision)))
+        return set_status(ctx, RPCA_ERR_UNSUPPORTED, "solve_factored: seed size outside the built kernel classes");
+    RPCA_HIP_TRY(ctx, hipSetDevice(ctx->device));
+    std::vector<int64_t> I, J;
+    if ((st = check_sorted_indices(ctx, seed_rows, p, m, "seed_rows", &I)) != RPCA_OK) return st;
+    if ((st = check_sorted_indices(ctx, seed_cols, q, n, "seed_cols", &J)) != RPCA_OK) return st;
+    const std::vector<int64_t> Ic = complement_of(I, m), Jc = complement_of(J, n);
+    const int64_t mc = (int64_t)Ic.size(), nc = (int64_t)Jc.size();
+    // workspace: Ic, Jc (int64) | iteration codes (nc + mc, int32)
+    const size_t bytes = (size_t)(mc + nc) * 8 + (size_t)(nc + mc) * 4 + 256;
+    if ((st = ensure_buf(ctx, ctx->solve_ws, bytes)) != RPCA_OK) return st;
+    int64_t *dIc = static_cast<int64_t *>(ctx->solve_ws.ptr), *dJc = dIc + mc;
+    int32_t *dit = reinterpret_cast<int32_t *>(dJc + nc);
+    hipStream_t sm = stream;
+    if (mc) RPCA_HIP_TRY(ctx, hipMemcpyAsync(dIc, Ic.data(), mc * 8, hipMemcpyHostToDevice, sm));
+    if (nc) RPCA_HIP_TRY(ctx, hipMemcpyAsync(dJc, Jc.data(), nc * 8, hipMemcpyHostToDevice, sm));
+
+    // Step 2: seed, straight into the caller's factor buffers.
+    const auto t0 = std::chrono::steady_clock::now();
+    SeedOut so;
+    const int seed_st = run_seed(ctx, M, ldm, seed_rows, p, seed_cols, q, r, *opts, U, sigma, V, &so, sm);
+    const auto t1 = std::chrono::steady_clock::now();
+    if (seed_st < 0) return seed_st;
+    const std::string seed_msg = ctx->last_error;
+    const int ru = so.r_used;
+
+    // Steps 3 and 4 (one launch when both families share a class); outputs
+    // packed with leading dimension r_used.
+    FilterSide sides[2]{};
+    int ns = 0;
+    if (nc) sides[ns++] = FilterSide{M, seed_rows, dJc, 1, ldm, m, n, U, (int32_t)p, (int32_t)p, ru, nc, Qt, ru, dit};
+    if (mc) sides[ns++] = FilterSide{M, seed_cols, dIc, ldm, 1, n, m, V, (int32_t)q, (int32_t)q, ru, mc, Pt, ru, dit + nc};
+    FilterConsts c = consts_of(*opts);
+    c.plan_regs = nc + mc;
+    RPCA_HIP_TRY(ctx, hipEventRecord(ctx->ev[0], sm));
+    if (ns == 2 && !filter_same_class(sides[0].p, sides[0].r, sides[1].p, sides[1].r)) {
+        if ((st = launch_filter(ctx, &sides[0], 1, c, sm)) != RPCA_OK) return st;
+        if ((st = launch_filter(ctx, &sides[1], 1, c, sm)) != RPCA_OK) return st;
+    } else if (ns > 0) {
+        if ((st = launch_filter(ctx, sides, ns, c, sm)) != RPCA_OK) return st;
+    }
+    RPCA_HIP_TRY(ctx, hipEventRecord(ctx->ev[1], sm));
+    if (col_iters && nc) RPCA_HIP_TRY(ctx, hipMemcpyAsync(col_iters, dit, nc * 4, hipMemcpyDeviceToDevice, sm));
+    if (row_iters && mc) RPCA_HIP_TRY(ctx, hipMemcpyAsync(row_iters, dit + nc, mc * 4, hipMemcpyDeviceToDevice, sm));
+    std::vector<int32_t> its((size_t)(nc + mc));
+    if (!its.empty())
+        RPCA_HIP_TRY(ctx, hipMemcpyAsync(its.data(), dit, its.size() * 4, hipMemcpyDeviceToHost, sm));
+    RPCA_HIP_TRY(ctx, hipStreamSynchronize(sm));
+    const IterSummary is = summarize_iters(its.data(), its.size());
+    if (info) {
+        float tf = 0;
+        (void)hipEventElapsedTime(&tf, ctx->ev[0], ctx->ev[1]);
+        info->r_used = ru;
+        info->seed_iters = so.iters;
+        info->seed_converged = so.converged;
+        info->filt_iters_max = is.max;
+        info->filt_iters_total = is.total;
+        info->filt_not_converged = is.not_converged;
+        info->t_seed_ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
+        info->t_filter_ms = tf;
+        info->t_reconstruct_ms = 0.0;
+    }
+    if (is.nonfinite)
+        return set_status(ctx, RPCA_ERR_NUMERIC, std::to_string(is.nonfinite) +
+                                                     " regressions read a non-finite entry of M");
+    if (seed_st > 0) return set_status(ctx, seed_st, seed_msg);
+    if (is.not_converged)
+        return set_status(ctx, RPCA_WARN_NOT_CONVERGED,
+                          std::to_string(is.not_converged) + " regressions missed filt_eps");
+    return RPCA_OK;
+}
+
+int rpca_filter_new_cols(rpca_ctx_t ctx, const float *Mnew, int64_t m, int64_t nnew, int64_t ldm,
+                         const int64_t *seed_rows, int64_t p, const double *U, const double *sigma,
+                         int32_t r, const float *Pt, const rpca_opts *opts, float *Qt_new,
+                         int32_t *iters, float *L, int64_t ldl, float *S, int64_t lds,
+                         hipStream_t stream)
+{
+    if (!ctx) return RPCA_ERR_ARG;
+    ctx->last_error.clear();
+    int st;
+    if ((st = check_matrix(ctx, Mnew, m, nnew, ldm, "Mnew")) != RPCA_OK) return st;
+    if ((st = check_matrix(ctx, L, m, nnew, ldl, "L")) != RPCA_OK) return st;
+    if ((st = check_matrix(ctx, S, m, nnew, lds, "S")) != RPCA_OK) return st;
+    if (!opts) return set_status(ctx, RPCA_ERR_ARG, "filter_new_cols: NULL opts");
+    if ((st = check_opts(ctx, *opts)) != RPCA_OK) return st;
+    if (!seed_rows || !U || !sigma || !Qt_new || (p < m && !Pt))
+        return set_status(ctx, RPCA_ERR_ARG, "filter_new_cols: NULL argument");
+    if (p < 1 || p > m || r < 1 || r > p || p > INT32_MAX)
+        return set_status(ctx, RPCA_ERR_ARG, "filter_new_cols: need 1 <= r <= p <= m");
+    if ((const void *)L == (const void *)S || (const void *)L == (const void *)Mnew ||
+        (const void *)S == (const void *)Mnew)
+        return set_status(ctx, RPCA_ERR_ARG, "filter_new_cols: L, S and Mnew must be distinct buffers");
+    if (!filter_supported(ctx, (int)p, r, opts->precision))
+        return set_status(ctx, RPCA_ERR_UNSUPPORTED, "filter_new_cols: p = " + std::to_string(p) +
+                                                         ", r = " + std::to_string(r) +
+                                                         " outside the built kernel classes");
+    if (r > 64) return set_status(ctx, RPCA_ERR_UNSUPPORTED, "filter_new_cols: rank above 64");
+    RPCA_HIP_TRY(ctx, hipSetDevice(ctx->device));
+    if ((st = ensure_buf(ctx, ctx->iota_ws, (size_t)nnew * sizeof(int64_t))) != RPCA_OK) return st;
+    int64_t *cols = static_cast<int64_t *>(ctx->iota_ws.ptr);
+    if ((st = launch_iota(ctx, cols, nnew, stream)) != RPCA_OK) return st;
+    // Step 3 on the new columns (every column of Mnew is a J_c column) ...
+    FilterSide s{Mnew, seed_rows, cols, 1, ldm, m, nnew, U, (int32_t)p, (int32_t)p, r, nnew, Qt_new,
+                 r, iters, nullptr, nullptr};
+    FilterConsts c = consts_of(*opts);
+    c.plan_regs = nnew;
+    if ((st = launch_filter(ctx, &s, 1, c, stream)) != RPCA_OK) return st;
+    // ... and the completion of those columns only: F from the fit's rows
+    // (U Sigma on I_s, P~^T on I_c), G = Q~_new^T Sigma^-1 (no seed columns
+    // among them, q = 0).
+    ReconArgs a{Mnew, m, nnew, ldm, seed_rows, p, nullptr, 0, U, sigma, nullptr, r, Qt_new, Pt,
+                L, ldl, S, lds};
+    return launch_reconstruct(ctx, a, stream);
 }
 
 } // extern "C"

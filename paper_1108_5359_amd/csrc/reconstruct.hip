@@ -37,6 +37,12 @@ reconstruct_kernel(const float *M, int64_t ldm, const float *F, const float *G, 
                         threadIdx.x);
 }
 
+__global__ void iota_kernel(int64_t *__restrict__ dst, int64_t count)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < count) dst[t] = t;
+}
+
 template <int R4>
 int launch_r4(rpca_ctx *ctx, const ReconArgs &a, const float *F, const float *G, bool vec,
               hipStream_t stream)
@@ -75,6 +81,15 @@ int launch_reconstruct(rpca_ctx *ctx, const ReconArgs &a, hipStream_t stream)
     int st = ensure_buf(ctx, ctx->factors, fbytes);
     if (st != RPCA_OK) return st;
     return launch_reconstruct_with(ctx, a, static_cast<float *>(ctx->factors.ptr), stream);
+}
+
+int launch_iota(rpca_ctx *ctx, int64_t *dst, int64_t count, hipStream_t stream)
+{
+    if (count <= 0) return RPCA_OK;
+    hipLaunchKernelGGL(iota_kernel, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, stream, dst,
+                       count);
+    RPCA_HIP_TRY(ctx, hipGetLastError());
+    return RPCA_OK;
 }
 
 int launch_reconstruct_with(rpca_ctx *ctx, const ReconArgs &a, float *factors, hipStream_t stream)

@@ -32,6 +32,8 @@ struct rpca_ctx {
     DevBuf scratch;     // small reductions / flags
     DevBuf frag_ws;     // FP32 refresh fragments of the precision form (large p)
     DevBuf xbuf_ws;     // the regressions' x in fragment order (read by the refresh)
+    DevBuf iota_ws;     // column indices 0..n-1 of the online column filter
+    DevBuf rank_ws;     // indices and factors of the rank-estimation seeds
 };
 
 // Set ctx->last_error and return status.
@@ -135,6 +137,8 @@ struct ReconArgs {
 };
 
 int launch_reconstruct(rpca_ctx *ctx, const ReconArgs &a, hipStream_t stream);
+// dst[k] = k for k < count (device int64).
+int launch_iota(rpca_ctx *ctx, int64_t *dst, int64_t count, hipStream_t stream);
 // The same into caller-provided factor storage ((m + n) * R4 floats, R4 = r
 // rounded up to 4); allocates nothing.
 int launch_reconstruct_with(rpca_ctx *ctx, const ReconArgs &a, float *factors, hipStream_t stream);

@@ -467,3 +467,60 @@ def rpca_filter_complete(ctx: Context, M, m, n, ldm, seed_rows, p, seed_cols, q,
                                               _ptr(sigma), _ptr(V), r, ctypes.byref(opts), _ptr(Qt),
                                               _ptr(col_iters), _ptr(Pt), _ptr(row_iters), _ptr(L),
                                               ldl, _ptr(S), lds, _stream(stream)))
+
+
+# ---------------------------------------------------------------- factored output, new columns
+lib.rpca_solve_factored.argtypes = [_vp, _vp, _i64, _i64, _i64, _i32, ctypes.POINTER(rpca_opts),
+                                    _vp, _i64, _vp, _i64, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
+                                    ctypes.POINTER(rpca_info), _vp]
+lib.rpca_solve_factored.restype = ctypes.c_int
+lib.rpca_filter_new_cols.argtypes = [_vp, _vp, _i64, _i64, _i64, _vp, _i64, _vp, _vp, _i32, _vp,
+                                     ctypes.POINTER(rpca_opts), _vp, _vp, _vp, _i64, _vp, _i64, _vp]
+lib.rpca_filter_new_cols.restype = ctypes.c_int
+
+
+def rpca_solve_factored(ctx: Context, M, m, n, ldm, r, opts, seed_rows, p, seed_cols, q, U, sigma,
+                        V, Qt, col_iters, Pt, row_iters, stream=None):
+    """Returns (status, rpca_info); Qt / Pt hold r_used rows (ld r_used)."""
+    info = rpca_info()
+    st = ctx.check(lib.rpca_solve_factored(ctx.handle, _ptr(M), m, n, ldm, r, ctypes.byref(opts),
+                                           _ptr(seed_rows), p, _ptr(seed_cols), q, _ptr(U),
+                                           _ptr(sigma), _ptr(V), _ptr(Qt), _ptr(col_iters), _ptr(Pt),
+                                           _ptr(row_iters), ctypes.byref(info), _stream(stream)))
+    return st, info
+
+
+def rpca_filter_new_cols(ctx: Context, Mnew, m, nnew, ldm, seed_rows, p, U, sigma, r, Pt, opts,
+                         Qt_new, iters, L, ldl, S, lds, stream=None):
+    return ctx.check(lib.rpca_filter_new_cols(ctx.handle, _ptr(Mnew), m, nnew, ldm, _ptr(seed_rows),
+                                              p, _ptr(U), _ptr(sigma), r, _ptr(Pt),
+                                              ctypes.byref(opts), _ptr(Qt_new), _ptr(iters), _ptr(L),
+                                              ldl, _ptr(S), lds, _stream(stream)))
+
+
+# ---------------------------------------------------------------- target-rank estimation
+RPCA_RANK_MAX_ROUNDS = 16
+
+
+class rpca_rank_info(ctypes.Structure):
+    _fields_ = [("r_est", _i32), ("accepted", _i32), ("rounds", _i32), ("cv_rank", _i32),
+                ("p", _i64), ("q", _i64), ("ranks", _i32 * RPCA_RANK_MAX_ROUNDS),
+                ("ps", _i64 * RPCA_RANK_MAX_ROUNDS), ("qs", _i64 * RPCA_RANK_MAX_ROUNDS)]
+
+
+lib.rpca_estimate_rank.argtypes = [_vp, _vp, _i64, _i64, _i64, _i32, ctypes.POINTER(rpca_opts),
+                                   _vp, _vp, _i32, ctypes.POINTER(rpca_rank_info)]
+lib.rpca_estimate_rank.restype = ctypes.c_int
+
+
+def rpca_estimate_rank(ctx: Context, M, m, n, ldm, r0, opts, row_order, col_order,
+                       cross_validate=True):
+    """row_order / col_order: host permutations (int64 numpy).  Returns
+    (status, rpca_rank_info)."""
+    ro = np.ascontiguousarray(row_order, dtype=np.int64)
+    co = np.ascontiguousarray(col_order, dtype=np.int64)
+    info = rpca_rank_info()
+    st = ctx.check(lib.rpca_estimate_rank(ctx.handle, _ptr(M), m, n, ldm, r0, ctypes.byref(opts),
+                                          ro.ctypes.data, co.ctypes.data, int(bool(cross_validate)),
+                                          ctypes.byref(info)))
+    return st, info

@@ -166,3 +166,48 @@ def test_generator_matches_table1_magnitudes():
     nuc = np.linalg.svd(pr.L0(), compute_uv=False).sum()
     assert abs(nuc - 40000) / 40000 <= 0.02
     assert pr.support.sum() == 40000
+
+
+# ----------------------------------------------------------------- new columns (online filtering)
+def _appended_problem(seed):
+    # one low-rank model for 1200 columns: the first 1000 are fitted, the last
+    # 200 arrive afterwards (c1 shapes and corruption law)
+    pr = synth.lowrank_plus_sparse(1000, 1200, 10, factor_std=np.sqrt(1.0 / 1000), sparsity=0.10,
+                                   values="pm1", seed=seed, exact_count=True)
+    return pr, pr.M[:, :1000], np.asfortranarray(pr.M[:, 1000:])
+
+
+@pytest.mark.parametrize("seed", [1, 2])
+def test_new_columns_recover_the_low_rank_part(seed):
+    # The paper's exact recoverability (Sec. 3.5): with the seed recovered,
+    # each new column's filtering returns the true coefficients, so the
+    # completed columns equal L0's new columns and S their corruptions.
+    pr, M0, Mnew = _appended_problem(seed)
+    I, J = synth.seed_indices(1000, 1000, 100, 100, seed=seed)
+    fit = oracle.solve(M0, 10, I, J, assemble=False)
+    assert fit.seed.rank == 10
+    Qn, kn = oracle.filter_cols(Mnew, I, np.arange(200), fit.U)
+    assert (kn > 0).all()
+    L, S = oracle.complete_new_cols(Mnew, I, fit.U, fit.sigma, fit.Pt, Qn)
+    L0 = pr.L0()[:, 1000:]
+    assert oracle.relerr(L, L0) <= 1e-6
+    tau = 1e-3 * np.abs(pr.M).max()
+    assert np.array_equal(np.abs(S) > tau, pr.support[:, 1000:])
+
+
+def test_new_columns_match_the_whole_matrix_fit():
+    # Filtering a column later gives what the fit of the whole matrix gives
+    # it: with the seed columns among the first 1000, the last 200 columns of
+    # the 1200-column solve are non-seed columns completed by eq. l1s'.
+    pr, M0, Mnew = _appended_problem(3)
+    I, J = synth.seed_indices(1000, 1000, 100, 100, seed=3)
+    fit = oracle.solve(M0, 10, I, J, assemble=False)
+    Qn, _ = oracle.filter_cols(Mnew, I, np.arange(200), fit.U)
+    L, S = oracle.complete_new_cols(Mnew, I, fit.U, fit.sigma, fit.Pt, Qn)
+    whole = oracle.solve(pr.M, 10, I, J)
+    assert np.abs(whole.L[:, 1000:] - L).max() <= 1e-12 * np.abs(L).max()
+    # a planted mistake (Sigma instead of Sigma^-1 on the Nystrom rows) is seen
+    Lbad = L.copy()
+    Ic = oracle.complement(I, 1000)
+    Lbad[Ic, :] = (fit.Pt.T * fit.sigma) @ Qn
+    assert oracle.relerr(Lbad, pr.L0()[:, 1000:]) > 1e-2
