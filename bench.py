@@ -1,47 +1,52 @@
-"""Benchmark: l1-filter solves/s on one MI355X.
+"""Benchmark: l1-filter solves/s on one MI355X, with HBM / MFMA roofline
+fractions, the FP64 oracle timed on the host cores, each result's error
+against that oracle, and served-vs-plain latency.
 
-Default workload (``--config c2``, the plain FP32 form): M = L0 + S0 with
-m = n = 10000, rank r = 20 (Gaussian factors N(0, 1/10000)), 10% +-1
-corruptions at uniformly random positions, seed block 200 x 200 at random
-rows/columns.  One "step" is the whole hot path of l1 filtering over that
-matrix: the 9800 column and 9800 row l1 regressions (Algorithm 1, one fused
-launch) and the completion of L and S = M - L over all 10^8 entries.  The
-seed PCP (a separate support stage) runs once before the timed region and is
-reported as ``t_seed_ms``.  Inputs are resident in HBM when timing starts.
-The precision form (FP16 contractions + FP32 refinement) is timed on the same
-matrix and reported under ``detail.precision_form`` with its difference from
-the FP32 result.
+The default run (``--config all``) prints ONE JSON line whose headline is the
+plain FP32 form at m = n = 10000 (``c2``): M = L0 + S0 with rank r = 20
+(Gaussian factors N(0, 1/10000)), 10% +-1 corruptions at uniformly random
+positions, seed block 200 x 200 at random rows/columns.  One "step" is the
+whole hot path of l1 filtering over that matrix: the 9800 column and 9800 row
+l1 regressions (Algorithm 1, one fused launch) and the completion of L and
+S = M - L over all 10^8 entries.  The seed PCP (a separate support stage)
+runs once before the timed region and is reported as ``t_seed_ms``.  Inputs
+are resident in HBM when timing starts.  The other workloads are measured in
+the same run and nested under ``detail`` with their own roofline, CPU
+baseline and error:
 
-``--config c3``: m = n = 50000, r = 50, N(0, 2e-5) factors, 5% corruptions
-uniform in [-1, 1], 500 x 500 seed, precision form (M: 10 GB).
+* ``detail.c3`` -- precision form: m = n = 50000, r = 50, N(0, 2e-5) factors,
+  5% corruptions uniform in [-1, 1], 500 x 500 seed (FP64), FP16 MFMA
+  contractions with FP32 refinement (M: 10 GB).
+* ``detail.c4`` -- batched form: 256 independent problems shaped like video
+  background modelling (m ~ U{2048..76800} pixels, n ~ U{100..1000} frames,
+  r ~ U{1..8}, N(0, 1/m) factors, 5-15% block foregrounds U[0, 1], 10r x 10r
+  seeds; M: 22 GB).  One step is one ``rpca_batch_run`` (every regression of
+  every problem in the persistent filter kernels, then every completion);
+  the plain leg runs the same steps problem after problem (rpca_filter +
+  rpca_reconstruct on each, same seeds).
+* ``detail.c5`` -- served form: a Poisson stream of requests drawn from a mix
+  (60% m = n = 2000, r = 5; 30% 20000 x 500, r = 10; 10% 20000 x 20000,
+  r = 30; N(0, 1/max(m, n)) factors, 10% +-1 corruptions, 10r x 10r seeds,
+  precision form) through the request loop (rpca_server_*, HBM budget
+  200 GB), against the plain form (rpca_solve on one request after another):
+  solves/s at saturation and p50 / p99 latency at 50%, 80%, 100% and 200% of
+  the plain rate.
 
-``--config c5``: the served form.  A Poisson stream of requests drawn from a
-mix (60% m = n = 2000, r = 5; 30% m = 20000 x n = 500, r = 10; 10% m = n =
-20000, r = 30; N(0, 1/max(m, n)) factors, 10% +-1 corruptions, 10r x 10r
-seeds, precision form) goes through the request loop (rpca_server_*, HBM
-budget 200 GB).  Inputs are synthesised on the device before the clock runs
-(a pool of instances per class that requests reuse).  Reported: the plain
-GPU form's rate (rpca_solve on one request after another), the server's
-rate at saturation (``value``), and p50 / p99 latency at 50%, 80%, 100% and
-200% of the plain rate.
-
-``--config c4``: the batched form, 256 independent problems shaped like video
-background modelling (m ~ U{2048..76800} pixels, n ~ U{100..1000} frames,
-r ~ U{1..8}, N(0, 1/m) factors, 5-15% block foregrounds U[0, 1], 10r x 10r
-seeds; M: 22 GB).  One step is one ``rpca_batch_run``: every regression of
-every problem in the persistent filter kernels, then every completion.
-
-Prints ONE JSON line.  ``value`` = (column + row regressions) per second of
-step time.  ``roofline`` describes the dominant kernel: algorithmic bytes or
-flops per launch over its mean duration measured with HIP events on the launch
-stream.  ``cpu_baseline`` times the FP64 reference (oracle) on a bounded
-sample of the same workload on the host cores.
+``--config c2|c3|c4|c5`` runs one workload alone as the headline (for
+profiling).  ``value`` = (column + row regressions) per second of step time
+(served form: solves per second).  ``roofline`` describes the dominant kernel:
+algorithmic bytes or flops per launch over its mean duration, measured with
+HIP events on the launch stream.  ``cpu_baseline`` times the FP64 oracle on a
+bounded sample of the same workload on the host cores (all of them, and one),
+and the same leg measures the GPU results' error against the oracle on that
+sample (``error_vs_oracle``).
 """
 from __future__ import annotations
 
 import argparse
 import hashlib
 import json
+import os
 import pathlib
 import sys
 import time
@@ -57,23 +62,21 @@ PEAK_FP16_MFMA_TFLOPS = 2500.0  # MI355X dense FP16/BF16 matrix
 
 WORKLOADS = {
     "c2": dict(m=10000, n=10000, r=20, factor_std=np.sqrt(1e-4), sparsity=0.10, values="pm1",
-               precision=0,
+               precision=0, cpu_sample=0, err_cross=1000,
                text="plain form: m=n=10000, r=20, N(0,1e-4) factors, 10% +-1 corruptions, 200x200 "
                     "seed, 9800 column + 9800 row regressions of length 200, L and S over all 1e8 "
                     "entries"),
     "c3": dict(m=50000, n=50000, r=50, factor_std=np.sqrt(2e-5), sparsity=0.05, values="unif11",
-               precision=1,
+               precision=1, cpu_sample=8000, err_cross=1000,
                text="precision form: m=n=50000, r=50, N(0,2e-5) factors, 5% U[-1,1] corruptions, "
                     "500x500 seed (FP64), 49500 column + 49500 row regressions of length 500 with "
                     "FP16 MFMA contractions and FP32 refinement, L and S over all 2.5e9 entries"),
 }
 
-
 BATCH = {"c4": dict(njobs=256, precision=0,
                    text="batched form: 256 problems, m ~ U{2048..76800}, n ~ U{100..1000}, "
                         "r ~ U{1..8}, N(0,1/m) factors, 5-15% U[0,1] block foregrounds, 10r x 10r "
                         "seeds; ~1.0e7 regressions of length 10-80; L and S over 5.6e9 entries")}
-
 
 SERVE = {"c5": dict(classes=[("A", 2000, 2000, 5, 0.6, 6), ("B", 20000, 500, 10, 0.3, 4),
                             ("C", 20000, 20000, 30, 0.1, 2)],
@@ -81,6 +84,13 @@ SERVE = {"c5": dict(classes=[("A", 2000, 2000, 5, 0.6, 6), ("B", 20000, 500, 10,
                    text="served form: Poisson requests, 60% 2000x2000 r=5, 30% 20000x500 r=10, "
                         "10% 20000x20000 r=30, N(0,1/max(m,n)) factors, 10% +-1 corruptions, 10r x 10r "
                         "seeds, precision form, HBM budget 200 GB")}
+
+# filter kernel forms (rpca_filter_form): names, kernels, counter summary keys
+FORM_NAMES = {0: "fp16", 1: "tile", 2: "split"}
+FORM_KERNELS = {0: "l1_filter_kernel_f16 / _f16q (fp16 MFMA; the latter above p = 256)",
+                1: "l1_filter_kernel (fp32 MFMA, tile form)",
+                2: "l1_filter_split_kernel (fp32 MFMA, split form)"}
+FORM_KEYS = {0: "l1_filter", 1: "l1_filter", 2: "l1_filter_split"}
 
 
 def log(*a):
@@ -92,14 +102,6 @@ def source_digest(paths) -> str:
     for p in paths:
         h.update((ROOT / p).read_bytes())
     return h.hexdigest()[:16]
-
-
-# filter kernel forms (rpca_filter_form): names, kernels, counter summary keys
-FORM_NAMES = {0: "fp16", 1: "tile", 2: "split"}
-FORM_KERNELS = {0: "l1_filter_kernel_f16 / _f16q (fp16 MFMA; the latter above p = 256)",
-                1: "l1_filter_kernel (fp32 MFMA, tile form)",
-                2: "l1_filter_split_kernel (fp32 MFMA, split form)"}
-FORM_KEYS = {0: "l1_filter", 1: "l1_filter", 2: "l1_filter_split"}
 
 
 def counter_traffic(kernel_key: str, digest: str):
@@ -114,6 +116,60 @@ def counter_traffic(kernel_key: str, digest: str):
     return d.get("hbm_bytes_per_launch")
 
 
+_ORACLE_THREADS = [0]
+
+
+def oracle_threads() -> int:
+    """Threads of the oracle's OpenMP loops: the host's count, read once
+    before any one-thread run (which leaves OpenMP set to one thread)."""
+    import oracle
+    if not _ORACLE_THREADS[0]:
+        oracle.build()
+        _ORACLE_THREADS[0] = oracle.num_threads(0)
+    return _ORACLE_THREADS[0]
+
+
+def cpu_model() -> str:
+    try:
+        for line in pathlib.Path("/proc/cpuinfo").read_text().splitlines():
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def relF(a, b) -> float:
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    nb = np.linalg.norm(b)
+    return float(np.linalg.norm(a - b) / nb) if nb > 0 else float(np.linalg.norm(a - b))
+
+
+def supp_mismatch(S_test, S_ref, tau) -> int:
+    """Entries whose membership in {|S| > tau} differs, ignoring those whose
+    reference value lies within a factor 4 of tau."""
+    ref = np.abs(S_ref)
+    away = (ref < tau / 4) | (ref > 4 * tau)
+    return int(((np.abs(S_test) > tau) != (ref > tau))[away].sum())
+
+
+def gather(Mt, rows, cols):
+    """M[rows][:, cols] (FP64 host) from a (n, ld) device tensor."""
+    import torch
+    dr = torch.as_tensor(np.asarray(rows, dtype=np.int64)).to(Mt.device)
+    dc = torch.as_tensor(np.asarray(cols, dtype=np.int64)).to(Mt.device)
+    return Mt.index_select(0, dc).index_select(1, dr).double().cpu().numpy().T
+
+
+def free_device(torch):
+    import gc
+    gc.collect()
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+
+
+# =========================================================================== plain forms (c2, c3)
 class Workload:
     """Device-resident inputs and outputs of one l1-filtering run."""
 
@@ -155,7 +211,8 @@ class Workload:
             R.rpca_opts_default(), self.U, self.sg, self.V)
         torch.cuda.synchronize()
         self.t_seed_ms = (time.perf_counter() - t0) * 1e3
-        log(f"bench: seed status={R.rpca_status_string(st)} r_used={self.r_used} "
+        self.seed_status = R.rpca_status_string(st)
+        log(f"bench: seed status={self.seed_status} r_used={self.r_used} "
             f"iters={self.seed_iters} t={self.t_seed_ms:.1f} ms")
 
     def step_overlapped(self, opts, stream):
@@ -182,9 +239,9 @@ class Workload:
             evs[2].record(stream)
 
     def timed(self, opts, steps, warmup):
-        """Headline: `steps` overlapped steps between two synchronisations.
-        Then as many sequential steps with events around each kernel launch
-        (the per-kernel durations of the roofline)."""
+        """Headline: `steps` steps between two synchronisations.  Then as many
+        steps with events around each kernel launch (the per-kernel durations
+        of the roofline)."""
         torch = self.torch
         stream = torch.cuda.current_stream()
         overlap = opts.overlap_chunks > 0
@@ -202,11 +259,267 @@ class Workload:
         torch.cuda.synchronize()
         filt_ms = float(np.mean([e[0].elapsed_time(e[1]) for e in events]))
         recon_ms = float(np.mean([e[1].elapsed_time(e[2]) for e in events]))
-        K = np.abs(np.concatenate([self.kc.cpu().numpy(), self.kr.cpu().numpy()]).astype(np.int64))
-        unconv = int((np.concatenate([self.kc.cpu().numpy(), self.kr.cpu().numpy()]) < 0).sum())
+        kk = np.concatenate([self.kc.cpu().numpy(), self.kr.cpu().numpy()])
+        K = np.abs(kk.astype(np.int64))
+        unconv = int((kk < 0).sum())
         return elapsed, filt_ms, recon_ms, K, unconv
 
+    def sample_plan(self, sample, cross, seed=12345):
+        """Regressions of the CPU-baseline sample (positions in the sorted
+        complements; all of them when ``sample`` is 0) and the rows / columns
+        of the entry cross on which L and S are compared."""
+        rng = np.random.default_rng(seed)
+        if sample and sample < self.nc + self.mr:
+            cpos = np.sort(rng.choice(self.nc, sample // 2, replace=False))
+            rpos = np.sort(rng.choice(self.mr, sample - sample // 2, replace=False))
+        else:
+            cpos, rpos = np.arange(self.nc), np.arange(self.mr)
+        xc = np.sort(rng.choice(cpos, min(cross, cpos.size), replace=False))
+        xr = np.sort(rng.choice(rpos, min(cross, rpos.size), replace=False))
+        return dict(cpos=cpos, rpos=rpos, xcpos=xc, xrpos=xr)
 
+    def snapshot(self, plan):
+        """The GPU's results on the sample: factors, the sampled regressions'
+        outputs and L, S on the entry cross (host FP64)."""
+        ru = self.r_used
+        rows = np.concatenate([self.I, self.Ic[plan["xrpos"]]])
+        cols = np.concatenate([self.J, self.Jc[plan["xcpos"]]])
+        Qt = self.Qt.view(-1)[: self.nc * ru].view(self.nc, ru)     # written with ld r_used
+        Pt = self.Pt.view(-1)[: self.mr * ru].view(self.mr, ru)
+        return dict(U=self.U.cpu().numpy().T[:, :ru], sg=self.sg.cpu().numpy()[:ru],
+                    V=self.V.cpu().numpy().T[:, :ru],
+                    Q=Qt[plan["cpos"]].double().cpu().numpy().T,
+                    P=Pt[plan["rpos"]].double().cpu().numpy().T,
+                    L=gather(self.L, rows, cols), S=gather(self.S, rows, cols))
+
+    def free(self):
+        self.ctx.close()
+        for a in ("Md", "L", "S", "Qt", "Pt", "kc", "kr", "U", "V", "sg", "dI", "dJ", "dIc", "dJc"):
+            setattr(self, a, None)
+
+
+def run_plain(name, args, R, torch, steps, warmup, overlap=0, filter_form=0, precision=None):
+    wl = Workload(name, args.seed, R, torch)
+    wl.seed()
+    w = WORKLOADS[name]
+    precision = w["precision"] if precision is None else precision
+    opts = R.rpca_opts_default(precision=precision, overlap_chunks=overlap, filter_form=filter_form)
+    form = R.rpca_filter_form(wl.ctx, wl.p, wl.r_used, wl.nc + wl.mr, opts)
+    if args.calibrate_copy:
+        calibrate_copy(torch, wl.dev)
+    plan = wl.sample_plan(w["cpu_sample"] if args.cpu_sample is None else args.cpu_sample,
+                          w["err_cross"])
+
+    elapsed, filt_ms, recon_ms, K, unconv = wl.timed(opts, steps, warmup)
+    ms_per_step = elapsed * 1e3 / steps
+    regs = wl.nc + wl.mr
+    value = regs * steps / elapsed
+    log(f"bench: {name} precision={precision} form={FORM_NAMES[form]} {ms_per_step:.3f} ms/step "
+        f"(kernels one after the other: filter {filt_ms:.3f} ms + reconstruct {recon_ms:.3f} ms)  "
+        f"K mean {K.mean():.1f} max {K.max()} unconverged {unconv}")
+    snaps = {}
+    if not args.no_cpu_baseline:
+        snaps[f"precision={precision}"] = wl.snapshot(plan)
+
+    # Algorithmic work per launch: the filter's two contractions per iteration
+    # (A^T g and A w: 4 p r flops per regression), the completion's 12 bytes
+    # per element (read M, write L, write S).
+    filt_flops = float(4.0 * wl.p * wl.r_used * K.sum())
+    recon_bytes = float(12.0 * wl.m * wl.n)
+    filt_tflops = filt_flops / (filt_ms * 1e-3) / 1e12
+    recon_gbs = recon_bytes / (recon_ms * 1e-3) / 1e9
+    stage_gbs = (recon_bytes + 4.0 * (wl.p * wl.nc + wl.q * wl.mr)) / (ms_per_step * 1e-3) / 1e9
+    if filt_ms >= recon_ms:
+        digest = source_digest(["paper_1108_5359_amd/csrc/filter_kernel.h"])
+        peak = PEAK_FP16_MFMA_TFLOPS if form == 0 else PEAK_FP32_MFMA_TFLOPS
+        roofline = {"bound": "mfma", "kernel": FORM_KERNELS[form],
+                    "achieved": round(filt_tflops, 3), "peak": peak, "unit": "TFLOP/s",
+                    "frac": round(filt_tflops / peak, 4),
+                    "traffic": counter_traffic(f"{FORM_KEYS[form]}_{name}", digest)}
+    else:
+        digest = source_digest(["paper_1108_5359_amd/csrc/reconstruct.hip",
+                                "paper_1108_5359_amd/csrc/recon_kernel.h"])
+        roofline = {"bound": "hbm", "kernel": "reconstruct_kernel (+ assemble_factors)",
+                    "achieved": round(recon_gbs, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                    "frac": round(recon_gbs / PEAK_HBM_GBS, 4),
+                    "traffic": counter_traffic(f"reconstruct_{name}", digest)}
+    detail = {"filter_form": FORM_NAMES[form], "precision": precision,
+              "filter_ms": round(filt_ms, 4), "reconstruct_ms": round(recon_ms, 4),
+              "sequential_ms_per_step": round(filt_ms + recon_ms, 4),
+              "filter_tflops_contraction": round(filt_tflops, 3),
+              "filter_frac_of_peak": round(filt_tflops / (PEAK_FP16_MFMA_TFLOPS if form == 0
+                                                          else PEAK_FP32_MFMA_TFLOPS), 4),
+              "reconstruct_gbs": round(recon_gbs, 1),
+              "reconstruct_frac_of_hbm_peak": round(recon_gbs / PEAK_HBM_GBS, 4),
+              "stage_gbs_algorithmic": round(stage_gbs, 1),
+              "iters_mean": round(float(K.mean()), 2), "iters_max": int(K.max()),
+              "unconverged": unconv, "t_seed_ms": round(wl.t_seed_ms, 1),
+              "seed_iters": wl.seed_iters, "seed_status": wl.seed_status, "r_used": wl.r_used}
+
+    if not args.no_compare:
+        # the other precision form on the same matrix
+        other = 1 - precision
+        key = "precision_form" if other == 1 else "plain_fp32_form"
+        o2 = R.rpca_opts_default(precision=other)
+        try:
+            e2, f2, r2, K2, u2 = wl.timed(o2, steps, 1)
+        except R.RpcaError as err:
+            detail[key] = {"unsupported": str(err)}
+        else:
+            detail[key] = {"value": round(regs * steps / e2, 1),
+                           "ms_per_step": round(e2 * 1e3 / steps, 4), "filter_ms": round(f2, 4),
+                           "reconstruct_ms": round(r2, 4), "iters_mean": round(float(K2.mean()), 2),
+                           "unconverged": u2,
+                           "filter_form": FORM_NAMES[R.rpca_filter_form(wl.ctx, wl.p, wl.r_used,
+                                                                        regs, o2)]}
+            log(f"bench: {name} precision={other} {e2 * 1e3 / steps:.3f} ms/step  filter {f2:.3f} ms")
+            if not args.no_cpu_baseline:
+                snaps[f"precision={other}"] = wl.snapshot(plan)
+        if form in (1, 2):
+            # the other FP32 kernel form on the same matrix
+            other_form = 3 - form
+            o3 = R.rpca_opts_default(precision=precision, filter_form=other_form)
+            if R.rpca_filter_form(wl.ctx, wl.p, wl.r_used, regs, o3) == other_form:
+                e3, f3, r3, K3, u3 = wl.timed(o3, steps, 1)
+                detail[f"{FORM_NAMES[other_form]}_form"] = {
+                    "ms_per_step": round(e3 * 1e3 / steps, 4), "filter_ms": round(f3, 4),
+                    "iters_mean": round(float(K3.mean()), 2), "unconverged": u3}
+                log(f"bench: {name} form={FORM_NAMES[other_form]} {e3 * 1e3 / steps:.3f} ms/step  "
+                    f"filter {f3:.3f} ms")
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        if not args.no_compare:
+            wl.timed(opts, 1, 0)          # leave the headline form's outputs in place
+        cpu, errs = cpu_baseline_plain(wl, plan, snaps, args.cpu_seconds, args.cpu_seconds_1t)
+        for k, e in errs.items():
+            if k == f"precision={precision}":
+                detail["error_vs_oracle"] = e
+            else:
+                key = "precision_form" if k.endswith("=1") else "plain_fp32_form"
+                detail.setdefault(key, {})["error_vs_oracle"] = e
+    out = {
+        "metric": "l1-filter solves/s (column + row l1 regressions, with completion of L and S)",
+        "value": round(value, 1),
+        "unit": "regressions/s",
+        "ms_per_step": round(ms_per_step, 4),
+        "steps": steps,
+        "dtype": "f32" if precision == 0 else "f16 contractions / f32 state",
+        "config": {"workload": w["text"], "name": name, "m": wl.m, "n": wl.n, "r": wl.r,
+                   "seed_block": [wl.p, wl.q], "regressions": regs},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "detail": detail,
+    }
+    wl.free()
+    del wl
+    free_device(torch)
+    return out
+
+
+def _oracle_cross_L(I_pos, J_pos, nrow, ncol, U, sg, V, Q, P):
+    """The oracle's L on an entry cross whose first len(I) rows are the seed
+    rows and first len(J) columns the seed columns (eqs. partition, l1s')."""
+    import oracle
+    Msub = np.zeros((nrow, ncol))
+    L, _ = oracle.complete(Msub, I_pos, J_pos, U, sg, V, Q, P)
+    return L
+
+
+def cpu_baseline_plain(wl, plan, snaps, seconds, seconds_1t):
+    """The FP64 oracle as it stands on the host cores: its seed PCP on the same
+    seed block, then Algorithm 1 (literal form, OpenMP over regressions) on the
+    sample of column and row regressions (all of them at m*n <= 1e8, where the
+    four-block completion of every entry is added), repeated until
+    ``seconds`` of oracle time; then the regressions again on one thread for
+    ``seconds_1t``.  On the same sample, the GPU results (one snapshot per
+    precision form) are compared with the oracle's: the blocks U Q~ and
+    P~^T V^T of the sampled regressions, and L, S on an entry cross (every
+    seed row and column plus sampled others)."""
+    import oracle
+    threads = oracle_threads()
+    I, J = wl.I, wl.J
+    Ms = gather(wl.Md, I, J)
+    t0 = time.perf_counter()
+    sd = oracle.seed_pcp(Ms)
+    t_seed = time.perf_counter() - t0
+    k = min(sd.rank, wl.r)
+    U, sg, V = sd.U[:, :k], sd.sigma[:k], sd.V[:, :k]
+    cols = wl.Jc[plan["cpos"]]
+    rows = wl.Ic[plan["rpos"]]
+    Xc = gather(wl.Md, I, cols)                          # p x |cols|
+    Xr = gather(wl.Md, rows, wl.J).T.copy()              # q x |rows|
+    full = len(cols) == wl.nc and len(rows) == wl.mr and wl.m * wl.n <= 100_000_000
+    Mh = wl.Md.cpu().numpy().T if full else None
+    t_f = t_c = 0.0
+    passes = 0
+    Lfull = None
+    while passes == 0 or t_f + t_c < seconds:
+        t0 = time.perf_counter()
+        Q, _ = oracle.alg1_batch(Xc, U, nthreads=threads)
+        P, _ = oracle.alg1_batch(Xr, V, nthreads=threads)
+        t_f += time.perf_counter() - t0
+        if full:
+            t0 = time.perf_counter()
+            Lfull, Sfull = oracle.complete(Mh, I, J, U, sg, V, Q, P)
+            t_c += time.perf_counter() - t0
+        passes += 1
+    nreg = len(cols) + len(rows)
+    # one thread: the regressions of a slice of the sample
+    n1 = max(64, min(nreg, 4000))
+    c1, r1 = Xc[:, : n1 // 2], Xr[:, : n1 - n1 // 2]
+    t1 = 0.0
+    p1 = 0
+    while p1 == 0 or t1 < seconds_1t:
+        t0 = time.perf_counter()
+        oracle.alg1_batch(c1, U, nthreads=1)
+        oracle.alg1_batch(r1, V, nthreads=1)
+        t1 += time.perf_counter() - t0
+        p1 += 1
+    log(f"bench: cpu oracle seed {t_seed:.2f} s, {passes} x {nreg} regressions in {t_f:.2f} s, "
+        f"completion {t_c:.2f} s, threads {threads}; 1 thread {p1} x {c1.shape[1] + r1.shape[1]} "
+        f"in {t1:.2f} s")
+    # errors of each GPU snapshot on the sample
+    xc = np.searchsorted(plan["cpos"], plan["xcpos"])   # cross columns inside the sample
+    xr = np.searchsorted(plan["rpos"], plan["xrpos"])
+    nI, nJ = len(I), len(J)
+    Lx = _oracle_cross_L(np.arange(nI), np.arange(nJ), nI + len(xr), nJ + len(xc), U, sg, V,
+                         Q[:, xc], P[:, xr])
+    Mx = gather(wl.Md, np.concatenate([I, wl.Ic[plan["xrpos"]]]),
+                np.concatenate([J, wl.Jc[plan["xcpos"]]]))
+    tau = 1e-3 * float(wl.Md.abs().max().item())
+    errs = {}
+    for key, s in snaps.items():
+        e = {"relF_UQ_sampled_cols": relF(s["U"] @ s["Q"], U @ Q),
+             "relF_PV_sampled_rows": relF(s["P"].T @ s["V"].T, P.T @ V.T),
+             "relF_L_cross": relF(s["L"], Lx), "relF_S_cross": relF(s["S"], Mx - Lx),
+             "supp_mismatch_cross": supp_mismatch(s["S"], Mx - Lx, tau),
+             "cross": [int(Lx.shape[0]), int(Lx.shape[1])],
+             "rank": [int(s["U"].shape[1]), int(k)]}
+        errs[key] = {a: (float(f"{b:.3e}") if isinstance(b, float) else b) for a, b in e.items()}
+    if full and Lfull is not None:
+        # the headline form's outputs are still in wl.L / wl.S: every entry
+        Lg = wl.L.double().cpu().numpy().T
+        Sg = wl.S.double().cpu().numpy().T
+        key = next(iter(snaps))
+        errs[key].update({"relF_L_all": float(f"{relF(Lg, Lfull):.3e}"),
+                          "relF_S_all": float(f"{relF(Sg, Sfull):.3e}"),
+                          "supp_mismatch_all": supp_mismatch(Sg, Sfull, tau)})
+        del Lg, Sg
+    cpu = {"value": round(passes * nreg / (t_f + t_c), 1), "unit": "regressions/s",
+           "cores": threads, "kind": "oracle",
+           "sample": f"{len(cols)} column + {len(rows)} row regressions of the same matrix (FP64, "
+                     f"Algorithm 1 literal form, the oracle's own seed factors)"
+                     f"{' + completion of all entries' if full else ' (no completion)'}, "
+                     f"{passes} pass{'es' if passes > 1 else ''}",
+           "seconds": round(t_f + t_c, 2), "t_seed_s": round(t_seed, 3),
+           "value_1thread": round(p1 * (c1.shape[1] + r1.shape[1]) / t1, 1),
+           "sample_1thread": f"{c1.shape[1]} column + {r1.shape[1]} row regressions, {p1} passes",
+           "cpu_model": cpu_model(), "logical_cpus": os.cpu_count()}
+    return cpu, errs
+
+
+# =========================================================================== batched form (c4)
 class BatchWorkload:
     """Device-resident batch of independent problems (the c4 recipe)."""
 
@@ -237,17 +550,18 @@ class BatchWorkload:
                              self.tuning)
         self.regs = sum((s.m - s.p) + (s.n - s.q) for s in self.specs)
         self.elems = sum(s.m * s.n for s in self.specs)
-        self.filter_elems = sum((s.m - s.p) * s.q + (s.n - s.q) * s.p for s in self.specs)
 
     def seed(self):
         R = self.R
         t0 = time.perf_counter()
         st = R.rpca_batch_seed(self.batch)
         self.t_seed_ms = (time.perf_counter() - t0) * 1e3
-        self.infos = [R.rpca_batch_job_info(self.batch, k)[1] for k in range(len(self.specs))]
-        ranks = [i.r_used for i in self.infos]
-        log(f"bench: batch seed status={R.rpca_status_string(st)} t={self.t_seed_ms:.0f} ms "
-            f"r_used mean {np.mean(ranks):.2f}")
+        self.seed_status = R.rpca_status_string(st)
+        stats = [R.rpca_batch_job_info(self.batch, k) for k in range(len(self.specs))]
+        self.infos = [i for _, i in stats]
+        self.warn_rank = sum(1 for s, _ in stats if s == R.RPCA_WARN_RANK)
+        log(f"bench: batch seed status={self.seed_status} t={self.t_seed_ms:.0f} ms "
+            f"r_used mean {np.mean([i.r_used for i in self.infos]):.2f} warn_rank {self.warn_rank}")
 
     def timed(self, steps, warmup):
         torch, R = self.torch, self.R
@@ -271,6 +585,58 @@ class BatchWorkload:
         infos = [R.rpca_batch_job_info(self.batch, k)[1] for k in range(len(self.specs))]
         return elapsed, float(np.mean(fs)), float(np.mean(rs)), infos
 
+    def plain_leg(self, passes=3):
+        """Steps 3-5 of every problem one after the other, through the
+        single-problem calls (rpca_filter, then rpca_reconstruct) with the
+        batch's seed factors: the same work as one batched step, without the
+        batching.  Returns the mean wall time of one pass over all problems."""
+        R, torch = self.R, self.torch
+        dev = self.dev
+        opts = R.rpca_opts_default()
+        per = []
+        for k, (s, (Md, L, S, dI, dJ, I, J)) in enumerate(zip(self.specs, self.keep)):
+            r = self.infos[k].r_used
+            U = torch.zeros((s.r, s.p), dtype=torch.float64, device=dev)
+            sg = torch.zeros(s.r, dtype=torch.float64, device=dev)
+            V = torch.zeros((s.r, s.q), dtype=torch.float64, device=dev)
+            R.rpca_batch_job_factors(self.batch, k, U, sg, V)
+            Ic = torch.as_tensor(np.setdiff1d(np.arange(s.m), I)).to(dev)
+            Jc = torch.as_tensor(np.setdiff1d(np.arange(s.n), J)).to(dev)
+            Qt = torch.empty(max(1, (s.n - s.q) * r), dtype=torch.float32, device=dev)
+            Pt = torch.empty(max(1, (s.m - s.p) * r), dtype=torch.float32, device=dev)
+            Lp = torch.empty_like(Md)
+            Sp = torch.empty_like(Md)
+            per.append((s, Md, dI, dJ, Ic, Jc, U, sg, V, r, Qt, Pt, Lp, Sp))
+        stream = torch.cuda.current_stream()
+
+        def one_pass():
+            for s, Md, dI, dJ, Ic, Jc, U, sg, V, r, Qt, Pt, Lp, Sp in per:
+                R.rpca_filter(self.ctx, Md, s.m, s.n, s.m, dI, s.p, dJ, s.q, Jc, s.n - s.q, Ic,
+                              s.m - s.p, U, V, r, opts, Qt, None, Pt, None, stream)
+                R.rpca_reconstruct(self.ctx, Md, s.m, s.n, s.m, dI, s.p, dJ, s.q, U, sg, V, r, Qt,
+                                   Pt, Lp, s.m, Sp, s.m, stream)
+
+        one_pass()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(passes):
+            one_pass()
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / passes
+        # the plain leg's outputs equal the batch's (same kernels' arithmetic
+        # up to the form of the filter): report the largest difference
+        diff = 0.0
+        for (s, Md, dI, dJ, Ic, Jc, U, sg, V, r, Qt, Pt, Lp, Sp), keep in zip(per[:8], self.keep[:8]):
+            Lb = keep[1]
+            diff = max(diff, float(((Lp - Lb).norm() / Lb.norm()).item()))
+        del per
+        return dt, diff
+
+    def free(self):
+        self.batch.close()
+        self.ctx.close()
+        self.keep = None
+
 
 def calibrate_copy(torch, dev):
     """A plain elementwise pass reading 1 GiB and writing 1 GiB (one kernel
@@ -284,21 +650,25 @@ def calibrate_copy(torch, dev):
     del src, dst
 
 
-def main_batch(args, R, torch):
+def run_batch(name, args, R, torch, steps, warmup):
     from paper_1108_5359_amd import autotune
     tuned = None if args.no_tuned else autotune.load()
     tuning = R.rpca_batch_tuning_default(**tuned) if tuned else None
-    wl = BatchWorkload(args.config, args.seed, R, torch, tuning)
+    wl = BatchWorkload(name, args.seed, R, torch, tuning)
     wl.seed()
     if args.calibrate_copy:
         calibrate_copy(torch, wl.dev)
-    elapsed, filt_ms, recon_ms, infos = wl.timed(args.steps, args.warmup)
-    ms_per_step = elapsed * 1e3 / args.steps
-    value = wl.regs * args.steps / elapsed
+    elapsed, filt_ms, recon_ms, infos = wl.timed(steps, warmup)
+    ms_per_step = elapsed * 1e3 / steps
+    value = wl.regs * steps / elapsed
     iters_total = sum(i.filt_iters_total for i in infos)
     unconv = sum(i.filt_not_converged for i in infos)
-    log(f"bench: {wl.name} {ms_per_step:.3f} ms/step  filter {filt_ms:.3f} ms  completion "
+    log(f"bench: {name} {ms_per_step:.3f} ms/step  filter {filt_ms:.3f} ms  completion "
         f"{recon_ms:.3f} ms  K mean {iters_total / wl.regs:.1f}  unconverged {unconv}")
+    plain_s, plain_diff = wl.plain_leg() if not args.no_compare else (None, None)
+    if plain_s is not None:
+        log(f"bench: {name} plain leg (problem after problem) {plain_s * 1e3:.1f} ms per pass, "
+            f"largest relative L difference to the batch {plain_diff:.2e}")
     recon_bytes = 12.0 * wl.elems
     recon_gbs = recon_bytes / (recon_ms * 1e-3) / 1e9
     # filter: algorithmic flops of both contractions per iteration (4 p r per
@@ -313,96 +683,124 @@ def main_batch(args, R, torch):
         roofline = {"bound": "hbm", "kernel": "batch_reconstruct (+ batch_assemble)",
                     "achieved": round(recon_gbs, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
                     "frac": round(recon_gbs / PEAK_HBM_GBS, 4),
-                    "traffic": counter_traffic(f"batch_reconstruct_{args.config}", digest)}
+                    "traffic": counter_traffic(f"batch_reconstruct_{name}", digest)}
     else:
         roofline = {"bound": "mfma", "kernel": "lane_filter_kernel (fp32 4x4x1 MFMA)",
                     "achieved": round(filt_tflops, 3), "peak": PEAK_FP32_MFMA_TFLOPS,
                     "unit": "TFLOP/s", "frac": round(filt_tflops / PEAK_FP32_MFMA_TFLOPS, 4),
-                    "traffic": counter_traffic(f"lane_filter_{args.config}", digest)}
-    detail = {"overlap_chunks": args.overlap_chunks,
-              "filter_ms": round(filt_ms, 4), "reconstruct_ms": round(recon_ms, 4),
+                    "traffic": counter_traffic(f"lane_filter_{name}", digest)}
+    detail = {"filter_ms": round(filt_ms, 4), "reconstruct_ms": round(recon_ms, 4),
               "sequential_ms_per_step": round(filt_ms + recon_ms, 4),
               "reconstruct_gbs": round(recon_gbs, 1),
+              "reconstruct_frac_of_hbm_peak": round(recon_gbs / PEAK_HBM_GBS, 4),
               "filter_tflops_contraction": round(filt_tflops, 3),
+              "filter_frac_of_peak": round(filt_tflops / PEAK_FP32_MFMA_TFLOPS, 4),
               "iters_mean": round(iters_total / wl.regs, 2),
               "iters_max": int(max(i.filt_iters_max for i in infos)), "unconverged": int(unconv),
-              "t_seed_ms": round(wl.t_seed_ms, 1), "jobs": len(wl.specs),
+              "t_seed_ms": round(wl.t_seed_ms, 1), "seed_status": wl.seed_status,
+              "seed_warn_rank_problems": wl.warn_rank, "jobs": len(wl.specs),
+              "precision_note": "the lane form (p <= 80) computes in FP32 in both precision modes",
               "tuning": wl.tuning.as_dict(), "tuning_source": wl.tuning_source}
+    if plain_s is not None:
+        detail["plain_leg"] = {"what": "steps 3-5 of each problem in turn (rpca_filter + "
+                                       "rpca_reconstruct, same seed factors)",
+                               "ms_per_step": round(plain_s * 1e3, 3),
+                               "value": round(wl.regs / plain_s, 1),
+                               "batched_speedup": round(plain_s * 1e3 / ms_per_step, 3),
+                               "relF_L_vs_batched_first8": float(f"{plain_diff:.3e}")}
     cpu = None
     if not args.no_cpu_baseline:
-        cpu = cpu_baseline_batch(wl, args.cpu_sample if args.cpu_sample is not None else 6,
-                                 args.cpu_seconds)
+        cpu, errs = cpu_baseline_batch(wl, args.cpu_seconds, args.cpu_seconds_1t)
+        detail["error_vs_oracle"] = errs
     out = {
         "metric": "l1-filter solves/s (column + row l1 regressions, with completion of L and S)",
         "value": round(value, 1),
         "unit": "regressions/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
         "ms_per_step": round(ms_per_step, 4),
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
+        "steps": steps,
         "dtype": "f32",
-        "data": "synthetic",
-        "config": {"workload": BATCH[args.config]["text"], "name": args.config,
-                   "problems": len(wl.specs), "regressions": wl.regs,
-                   "elements": wl.elems},
+        "config": {"workload": BATCH[name]["text"], "name": name,
+                   "problems": len(wl.specs), "regressions": wl.regs, "elements": wl.elems},
         "roofline": roofline,
         "cpu_baseline": cpu,
         "detail": detail,
     }
-    print(json.dumps(out), flush=True)
-    wl.batch.close()
-    wl.ctx.close()
+    wl.free()
+    del wl
+    free_device(torch)
+    return out
 
 
-def cpu_baseline_batch(wl, njobs, seconds):
+def cpu_baseline_batch(wl, seconds, seconds_1t):
     """The FP64 oracle as it stands on the host cores: Algorithm 2 (seed,
     every column and row regression, completion) on the problems of the batch
-    in order, from host copies of their M: at least ``njobs`` of them, and on
-    until ``seconds`` of oracle time have been spent (or every problem is
-    done)."""
+    in order, from host copies of their M, until ``seconds`` of oracle time
+    have been spent; then the first problem again on one thread.  The GPU's L
+    and S of those problems are compared with the oracle's on every entry."""
     import oracle
-    oracle.build()
-    threads = oracle.num_threads(0)
+    threads = oracle_threads()
     regs, t, k = 0, 0.0, 0
-    while k < len(wl.specs) and (k < njobs or t < seconds):
+    worst = dict(relF_L=0.0, relF_S=0.0, supp_mismatch=0)
+    per = []
+    while k < len(wl.specs) and (k < 2 or t < seconds):
         s = wl.specs[k]
         Md, L, S, dI, dJ, I, J = wl.keep[k]
         Mh = np.asfortranarray(Md.cpu().numpy().T)
         t0 = time.perf_counter()
-        oracle.solve(Mh, s.r, I, J)
+        ref = oracle.solve(Mh, s.r, I, J, nthreads=threads)
         t += time.perf_counter() - t0
         regs += (s.m - s.p) + (s.n - s.q)
+        Lg = L.double().cpu().numpy().T
+        Sg = S.double().cpu().numpy().T
+        eL, eS = relF(Lg, ref.L), relF(Sg, ref.S)
+        sm = supp_mismatch(Sg, ref.S, 1e-3 * float(np.abs(Mh).max()))
+        worst = dict(relF_L=max(worst["relF_L"], eL), relF_S=max(worst["relF_S"], eS),
+                     supp_mismatch=max(worst["supp_mismatch"], sm))
+        per.append([k, float(f"{eL:.3e}"), float(f"{eS:.3e}")])
         k += 1
     njobs = k
-    log(f"bench: cpu oracle {regs} regressions ({njobs} problems) in {t:.2f} s, threads {threads}")
-    return {"value": round(regs / t, 1), "unit": "regressions/s", "cores": threads,
-            "kind": "oracle",
-            "sample": f"the first {njobs} problems of the batch, whole (seed, {regs} column + row "
-                      f"regressions, completion), FP64",
-            "seconds": round(t, 2)}
+    s0 = wl.specs[0]
+    Mh = np.asfortranarray(wl.keep[0][0].cpu().numpy().T)
+    t0 = time.perf_counter()
+    oracle.solve(Mh, s0.r, wl.keep[0][5], wl.keep[0][6], nthreads=1)
+    t1 = time.perf_counter() - t0
+    regs1 = (s0.m - s0.p) + (s0.n - s0.q)
+    log(f"bench: cpu oracle {regs} regressions ({njobs} problems) in {t:.2f} s, threads {threads}; "
+        f"1 thread {regs1} in {t1:.2f} s; worst relF L {worst['relF_L']:.2e}")
+    cpu = {"value": round(regs / t, 1), "unit": "regressions/s", "cores": threads,
+           "kind": "oracle",
+           "sample": f"the first {njobs} problems of the batch, whole (seed, {regs} column + row "
+                     f"regressions, completion), FP64",
+           "seconds": round(t, 2),
+           "value_1thread": round(regs1 / t1, 1),
+           "sample_1thread": f"problem 0 whole ({regs1} regressions), one thread",
+           "cpu_model": cpu_model(), "logical_cpus": os.cpu_count()}
+    errs = {"problems_compared": njobs, "every_entry": True,
+            "worst_relF_L": float(f"{worst['relF_L']:.3e}"),
+            "worst_relF_S": float(f"{worst['relF_S']:.3e}"),
+            "worst_supp_mismatch": worst["supp_mismatch"], "per_problem": per[:32]}
+    return cpu, errs
 
 
-def main_serve(args, R, torch):
+# =========================================================================== served form (c5)
+def run_serve(name, args, R, torch):
     import threading
     import synth
-    w = SERVE[args.config]
+    w = SERVE[name]
     dev = torch.device("cuda:0")
     rng = np.random.Generator(np.random.PCG64([args.seed, 0xC5]))
     # a pool of device-resident instances per class
     pool = {}
     t0 = time.perf_counter()
-    for name, m, n, r, frac, count in w["classes"]:
-        pool[name] = []
+    for cname, m, n, r, frac, count in w["classes"]:
+        pool[cname] = []
         for k in range(count):
             s = 1000 * args.seed + 10 * len(pool) + k
             Md, _, _ = synth.lowrank_plus_sparse_device(m, n, r, factor_std=np.sqrt(1.0 / max(m, n)),
                                                         sparsity=w["sparsity"], values=w["values"],
                                                         seed=s, device=dev)
             I, J = synth.seed_indices(m, n, 10 * r, 10 * r, seed=s)
-            pool[name].append((Md, m, n, r, torch.as_tensor(I).to(dev), torch.as_tensor(J).to(dev)))
+            pool[cname].append((Md, m, n, r, torch.as_tensor(I).to(dev), torch.as_tensor(J).to(dev)))
     torch.cuda.synchronize()
     log(f"bench: generated the request pool in {time.perf_counter() - t0:.1f} s")
     names = [c[0] for c in w["classes"]]
@@ -438,6 +836,7 @@ def main_serve(args, R, torch):
         del L, S
     plain_s = time.perf_counter() - t0
     plain_rate = len(plain_reqs) / plain_s
+    all_plain = [x for v in lat_plain.values() for x in v]
     log(f"bench: plain form {plain_rate:.2f} solves/s over {len(plain_reqs)} requests")
 
     srv = R.Server(opts, None, R.rpca_server_opts_default(hbm_budget_bytes=w["budget"],
@@ -445,11 +844,21 @@ def main_serve(args, R, torch):
                                                           max_batch=args.max_batch))
 
     def run_stream(reqs, qps):
-        """Submit at Poisson arrival times (qps = None: all at once); wait for all."""
+        """Submit at Poisson arrival times (qps = None: all at once); wait for
+        all.  The client allocates each request's L and S when it submits it
+        and frees them when the request is done; it keeps at most
+        ``args.client_gb`` of such outputs outstanding (a submission waits for
+        room), so a long saturation run cannot fill the device memory that
+        the request loop and the runtime need."""
         gaps = rng.exponential(1.0 / qps, len(reqs)) if qps else np.zeros(len(reqs))
         arrivals = np.cumsum(gaps)
-        tickets, bufs = [None] * len(reqs), [None] * len(reqs)
+        tickets = [None] * len(reqs)
         infos = [None] * len(reqs)
+        bufs = [None] * len(reqs)
+        need = [8 * inst[1] * inst[2] for _, inst in reqs]      # L and S, FP32
+        cap = args.client_gb * 1e9
+        room = threading.Condition()
+        outstanding = [0]
         done = threading.Event()
 
         def waiter():
@@ -458,6 +867,9 @@ def main_serve(args, R, torch):
                     time.sleep(0.0002)
                 infos[k] = srv.wait(tickets[k], check=False)
                 bufs[k] = None                                   # outputs no longer needed
+                with room:
+                    outstanding[0] -= need[k]
+                    room.notify_all()
             done.set()
 
         th = threading.Thread(target=waiter)
@@ -467,6 +879,10 @@ def main_serve(args, R, torch):
             delay = t_start + arrivals[k] - time.perf_counter()
             if delay > 0:
                 time.sleep(delay)
+            with room:
+                while outstanding[0] > 0 and outstanding[0] + need[k] > cap:
+                    room.wait()
+                outstanding[0] += need[k]
             L = torch.empty_like(Md)
             S = torch.empty_like(Md)
             bufs[k] = (L, S)
@@ -482,7 +898,7 @@ def main_serve(args, R, torch):
                 by_class[nm] = {"n": len(sel), "p50_ms": round(float(np.percentile(sel, 50)), 2),
                                 "p99_ms": round(float(np.percentile(sel, 99)), 2)}
         failed = sum(1 for i in infos if i.status < 0)
-        return {"offered_qps": round(qps, 3) if qps else None,
+        return {"offered_qps": round(qps, 3) if qps else None, "requests": len(reqs),
                 "achieved_solves_per_s": round(len(reqs) / span, 3),
                 "p50_ms": round(float(np.percentile(lat, 50)), 2),
                 "p99_ms": round(float(np.percentile(lat, 99)), 2),
@@ -490,9 +906,9 @@ def main_serve(args, R, torch):
                 "failed": failed, "by_class": by_class}, infos, reqs
 
     run_stream(draw(6), None)                                      # warm-up of the workers
-    sat, sat_infos, sat_reqs = run_stream(draw(args.requests), None)
-    log(f"bench: server at saturation {sat['achieved_solves_per_s']:.2f} solves/s "
-        f"(mean batch {sat['mean_batch']})")
+    sat, sat_infos, sat_reqs = run_stream(draw(args.requests_saturation), None)
+    log(f"bench: server at saturation {sat['achieved_solves_per_s']:.2f} solves/s over "
+        f"{sat['requests']} requests (mean batch {sat['mean_batch']}, p99 {sat['p99_ms']} ms)")
     levels = []
     for f in (0.5, 0.8, 1.0, 2.0):
         res, _, _ = run_stream(draw(args.requests), f * plain_rate)
@@ -500,6 +916,14 @@ def main_serve(args, R, torch):
         levels.append(res)
         log(f"bench: {res['load']}: {res['achieved_solves_per_s']:.2f} solves/s, p50 "
             f"{res['p50_ms']:.1f} ms, p99 {res['p99_ms']:.1f} ms, mean batch {res['mean_batch']}")
+    # one request of each class served alone, kept for the error check
+    kept = {}
+    for cname in names:
+        Md, m, n, r, dI, dJ = pool[cname][0]
+        L = torch.empty_like(Md)
+        S = torch.empty_like(Md)
+        srv.wait(srv.submit(R.job(Md, m, n, m, r, dI, 10 * r, dJ, 10 * r, L, m, S, m)))
+        kept[cname] = (Md, m, n, r, dI, dJ, L, S)
     st = srv.stats()
     srv.close()
 
@@ -512,62 +936,116 @@ def main_serve(args, R, torch):
     rb = sum(v[0] for v in batches.values())
     rt = sum(v[1] for v in batches.values()) * 1e-3
     recon_gbs = rb / rt / 1e9 if rt > 0 else 0.0
-    cpu = None
+    cpu, errs = None, None
     if not args.no_cpu_baseline:
-        import oracle
-        oracle.build()
-        Md, m, n, r, dI, dJ = pool["A"][0]
-        Mh = np.asfortranarray(Md.cpu().numpy().T)
-        I, J = dI.cpu().numpy(), dJ.cpu().numpy()
-        t0 = time.perf_counter()
-        ns = 0
-        while ns < 3 or time.perf_counter() - t0 < args.cpu_seconds:
-            oracle.solve(Mh, r, I, J)
-            ns += 1
-        tc = time.perf_counter() - t0
-        cpu = {"value": round(ns / tc, 3), "unit": "solves/s", "cores": oracle.num_threads(0),
-               "kind": "oracle",
-               "sample": f"{ns} solves of a class-A request (2000 x 2000, r = 5): seed, every "
-                         "column and row regression, completion, FP64", "seconds": round(tc, 2)}
+        cpu, errs = cpu_baseline_serve(kept, args.cpu_seconds, args.cpu_seconds_1t)
     out = {
         "metric": "served PCP solves/s (request mix, p50/p99 latency)",
         "value": sat["achieved_solves_per_s"],
         "unit": "solves/s",
-        "n_gpus": 1,
-        "steps": args.requests,
-        "warmup": 6,
         "ms_per_step": round(1e3 / sat["achieved_solves_per_s"], 3),
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
+        "steps": args.requests_saturation,
         "dtype": "f32 data, f16 contractions / f32 state (p >= 48), f64 seed",
-        "data": "synthetic",
-        "config": {"workload": w["text"], "name": args.config, "workers": args.workers,
-                   "max_batch": args.max_batch, "requests_per_level": args.requests},
+        "config": {"workload": w["text"], "name": name, "workers": args.workers,
+                   "max_batch": args.max_batch, "requests_at_saturation": args.requests_saturation,
+                   "requests_per_load_level": args.requests},
         "roofline": {"bound": "hbm", "kernel": "completion of the served batches",
                      "achieved": round(recon_gbs, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
                      "frac": round(recon_gbs / PEAK_HBM_GBS, 4), "traffic": None},
         "cpu_baseline": cpu,
         "detail": {"plain_solves_per_s": round(plain_rate, 3),
                    "served_vs_plain": round(sat["achieved_solves_per_s"] / plain_rate, 3),
-                   "plain_latency_ms": {nm: round(float(np.median(v)), 2) for nm, v in lat_plain.items() if v},
-                   "saturation": sat, "levels": levels, "server": st.as_dict()},
+                   "plain_requests": len(plain_reqs),
+                   "plain_latency_ms": {"p50": round(float(np.percentile(all_plain, 50)), 2),
+                                        "p99": round(float(np.percentile(all_plain, 99)), 2),
+                                        "by_class_median": {nm: round(float(np.median(v)), 2)
+                                                            for nm, v in lat_plain.items() if v}},
+                   "saturation": sat, "levels": levels, "server": st.as_dict(),
+                   "error_vs_oracle": errs},
     }
-    print(json.dumps(out), flush=True)
     ctx.close()
+    del pool, kept
+    free_device(torch)
+    return out
 
 
+def cpu_baseline_serve(kept, seconds, seconds_1t):
+    """The FP64 oracle as it stands on the host cores: Algorithm 2 on a
+    class-A request (2000 x 2000) repeated until ``seconds``, then once on one
+    thread.  Each class's served result is compared with the oracle: class A
+    on every entry, classes B and C on an entry cross (every seed row and
+    column plus 1000 others each)."""
+    import oracle
+    threads = oracle_threads()
+    Md, m, n, r, dI, dJ, L, S = kept["A"]
+    Mh = np.asfortranarray(Md.cpu().numpy().T)
+    I, J = dI.cpu().numpy(), dJ.cpu().numpy()
+    t0 = time.perf_counter()
+    ns = 0
+    while ns < 3 or time.perf_counter() - t0 < seconds:
+        ref = oracle.solve(Mh, r, I, J, nthreads=threads)
+        ns += 1
+    tc = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    oracle.solve(Mh, r, I, J, nthreads=1)
+    t1 = time.perf_counter() - t0
+    errs = {}
+    Lg, Sg = L.double().cpu().numpy().T, S.double().cpu().numpy().T
+    tau = 1e-3 * float(np.abs(Mh).max())
+    errs["A"] = {"relF_L_all": float(f"{relF(Lg, ref.L):.3e}"),
+                 "relF_S_all": float(f"{relF(Sg, ref.S):.3e}"),
+                 "supp_mismatch_all": supp_mismatch(Sg, ref.S, tau)}
+    rng = np.random.default_rng(5)
+    for cname in ("B", "C"):
+        Md, m, n, r, dI, dJ, L, S = kept[cname]
+        I, J = dI.cpu().numpy(), dJ.cpu().numpy()
+        Ic, Jc = np.setdiff1d(np.arange(m), I), np.setdiff1d(np.arange(n), J)
+        rs = np.sort(rng.choice(Ic, min(1000, Ic.size), replace=False))
+        cs = np.sort(rng.choice(Jc, min(1000, Jc.size), replace=False))
+        sd = oracle.seed_pcp(gather(Md, I, J))
+        k = min(sd.rank, r)
+        U, sg, V = sd.U[:, :k], sd.sigma[:k], sd.V[:, :k]
+        Q, _ = oracle.alg1_batch(gather(Md, I, cs), U, nthreads=threads)
+        P, _ = oracle.alg1_batch(gather(Md, rs, J).T.copy(), V, nthreads=threads)
+        rows, cols = np.concatenate([I, rs]), np.concatenate([J, cs])
+        Lx = _oracle_cross_L(np.arange(len(I)), np.arange(len(J)), len(rows), len(cols), U, sg, V,
+                             Q, P)
+        Mx = gather(Md, rows, cols)
+        Lgx, Sgx = gather(L, rows, cols), gather(S, rows, cols)
+        errs[cname] = {"relF_L_cross": float(f"{relF(Lgx, Lx):.3e}"),
+                       "relF_S_cross": float(f"{relF(Sgx, Mx - Lx):.3e}"),
+                       "supp_mismatch_cross": supp_mismatch(Sgx, Mx - Lx,
+                                                            1e-3 * float(Md.abs().max().item())),
+                       "cross": [len(rows), len(cols)]}
+    log(f"bench: cpu oracle {ns} class-A solves in {tc:.2f} s, threads {threads}; 1 thread "
+        f"{t1:.2f} s; errors {errs}")
+    cpu = {"value": round(ns / tc, 3), "unit": "solves/s", "cores": threads, "kind": "oracle",
+           "sample": f"{ns} solves of a class-A request (2000 x 2000, r = 5): seed, every column "
+                     "and row regression, completion, FP64",
+           "seconds": round(tc, 2), "value_1thread": round(1.0 / t1, 3),
+           "sample_1thread": "one class-A solve on one thread",
+           "cpu_model": cpu_model(), "logical_cpus": os.cpu_count()}
+    return cpu, errs
+
+
+# =========================================================================== driver
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--seed", type=int, default=1)
-    ap.add_argument("--config", default="c2", choices=sorted(WORKLOADS) + sorted(BATCH) + sorted(SERVE))
-    ap.add_argument("--requests", type=int, default=60, help="served form: requests per load level")
-    ap.add_argument("--plain-requests", type=int, default=20,
+    ap.add_argument("--config", default="all",
+                    choices=["all"] + sorted(WORKLOADS) + sorted(BATCH) + sorted(SERVE),
+                    help="all = c2 as the headline with c3, c4, c5 under detail; else one alone")
+    ap.add_argument("--requests", type=int, default=300, help="served form: requests per load level")
+    ap.add_argument("--requests-saturation", type=int, default=1000,
+                    help="served form: requests of the saturation run")
+    ap.add_argument("--plain-requests", type=int, default=40,
                     help="served form: requests of the plain-rate measurement")
     ap.add_argument("--workers", type=int, default=3, help="served form: worker threads")
+    ap.add_argument("--client-gb", type=float, default=48.0,
+                    help="served form: request outputs (L, S) the client keeps outstanding, GB")
     ap.add_argument("--no-tuned", action="store_true",
                     help="batched form: library defaults instead of the autotuner's results")
     ap.add_argument("--max-batch", type=int, default=64, help="served form: requests per batch")
@@ -577,13 +1055,15 @@ def main():
     ap.add_argument("--filter-form", type=int, default=0,
                     help="FP32 filter kernel: 0 = automatic, 1 = tile form, 2 = split form")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-compare", action="store_true", help="skip timing the other precision form")
+    ap.add_argument("--no-compare", action="store_true",
+                    help="skip the other precision / kernel forms and the batched plain leg")
     ap.add_argument("--cpu-sample", type=int, default=None,
                     help="regressions in the CPU baseline sample (0 = all; default: all at c2, "
                          "8000 at c3)")
-    ap.add_argument("--cpu-seconds", type=float, default=10.0,
-                    help="CPU baseline: repeat the sample (or take further problems of a batch) "
-                         "until this much oracle time has been spent")
+    ap.add_argument("--cpu-seconds", type=float, default=8.0,
+                    help="CPU baseline: oracle time on all host cores per workload")
+    ap.add_argument("--cpu-seconds-1t", type=float, default=3.0,
+                    help="CPU baseline: oracle time on one core per workload")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first run a plain 1 GiB device-to-device copy (for scaling the "
                          "FETCH_SIZE / WRITE_SIZE counters of a profiled run)")
@@ -598,180 +1078,36 @@ def main():
 
     import paper_1108_5359_amd.rpca as R
 
-    if args.config in BATCH:
-        return main_batch(args, R, torch)
-    if args.config in SERVE:
-        return main_serve(args, R, torch)
-    wl = Workload(args.config, args.seed, R, torch)
-    wl.seed()
-    precision = WORKLOADS[args.config]["precision"] if args.precision is None else args.precision
-    opts = R.rpca_opts_default(precision=precision, overlap_chunks=args.overlap_chunks,
-                               filter_form=args.filter_form)
-    form = R.rpca_filter_form(wl.ctx, wl.p, wl.r_used, wl.nc + wl.mr, opts)
-
-    if args.calibrate_copy:
-        calibrate_copy(torch, wl.dev)
-
-    elapsed, filt_ms, recon_ms, K, unconv = wl.timed(opts, args.steps, args.warmup)
-    ms_per_step = elapsed * 1e3 / args.steps
-    regs = wl.nc + wl.mr
-    value = regs * args.steps / elapsed
-    log(f"bench: precision={precision} form={FORM_NAMES[form]} overlap_chunks={args.overlap_chunks} "
-        f"{ms_per_step:.3f} ms/step "
-        f"(kernels one after the other: filter {filt_ms:.3f} ms + reconstruct {recon_ms:.3f} ms)  "
-        f"K mean {K.mean():.1f} max {K.max()} unconverged {unconv}")
-
-    # Algorithmic work per launch: the filter's two contractions per iteration
-    # (A^T g and A w: 4 p r flops per regression), the completion's 12 bytes
-    # per element (read M, write L, write S).
-    filt_flops = float(4.0 * wl.p * wl.r_used * K.sum())
-    recon_bytes = float(12.0 * wl.m * wl.n)
-    filt_tflops = filt_flops / (filt_ms * 1e-3) / 1e12
-    recon_gbs = recon_bytes / (recon_ms * 1e-3) / 1e9
-    if filt_ms >= recon_ms:
-        digest = source_digest(["paper_1108_5359_amd/csrc/filter_kernel.h"])
-        peak = PEAK_FP16_MFMA_TFLOPS if form == 0 else PEAK_FP32_MFMA_TFLOPS
-        roofline = {"bound": "mfma", "kernel": FORM_KERNELS[form],
-                    "achieved": round(filt_tflops, 3), "peak": peak, "unit": "TFLOP/s",
-                    "frac": round(filt_tflops / peak, 4),
-                    "traffic": counter_traffic(f"{FORM_KEYS[form]}_{args.config}", digest)}
-    else:
-        digest = source_digest(["paper_1108_5359_amd/csrc/reconstruct.hip",
-                                "paper_1108_5359_amd/csrc/recon_kernel.h"])
-        roofline = {"bound": "hbm", "kernel": "reconstruct_kernel (+ assemble_factors)",
-                    "achieved": round(recon_gbs, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                    "frac": round(recon_gbs / PEAK_HBM_GBS, 4),
-                    "traffic": counter_traffic(f"reconstruct_{args.config}", digest)}
-
-    detail = {"overlap_chunks": args.overlap_chunks, "filter_form": FORM_NAMES[form],
-              "filter_ms": round(filt_ms, 4), "reconstruct_ms": round(recon_ms, 4),
-              "sequential_ms_per_step": round(filt_ms + recon_ms, 4),
-              "filter_tflops_contraction": round(filt_tflops, 3),
-              "reconstruct_gbs": round(recon_gbs, 1), "iters_mean": round(float(K.mean()), 2),
-              "iters_max": int(K.max()), "unconverged": unconv,
-              "t_seed_ms": round(wl.t_seed_ms, 1), "seed_iters": wl.seed_iters,
-              "r_used": wl.r_used, "precision": precision}
-
-    if not args.no_compare:
-        # the other precision form on the same matrix, and how far apart they are
-        Q0 = wl.Qt.clone()
-        P0 = wl.Pt.clone()
-        other = 1 - precision
-        key = "precision_form" if other == 1 else "plain_fp32_form"
-        try:
-            e2, f2, r2, K2, u2 = wl.timed(R.rpca_opts_default(precision=other,
-                                                              overlap_chunks=args.overlap_chunks),
-                                          args.steps, 1)
-        except R.RpcaError as err:
-            detail[key] = {"unsupported": str(err)}
-            e2 = None
-    if not args.no_compare and e2 is not None:
-        Uh = wl.U.cpu().numpy()          # (r, p) = U^T
-        Vh = wl.V.cpu().numpy()
-        dq = np.linalg.norm((wl.Qt.double() - Q0.double()).cpu().numpy() @ Uh)
-        nq = np.linalg.norm(Q0.double().cpu().numpy() @ Uh)
-        dp = np.linalg.norm((wl.Pt.double() - P0.double()).cpu().numpy() @ Vh)
-        np_ = np.linalg.norm(P0.double().cpu().numpy() @ Vh)
-        detail[key] = {"value": round(regs * args.steps / e2, 1),
-                       "ms_per_step": round(e2 * 1e3 / args.steps, 4), "filter_ms": round(f2, 4),
-                       "reconstruct_ms": round(r2, 4), "iters_mean": round(float(K2.mean()), 2),
-                       "unconverged": u2,
-                       "relF_vs_headline_form": round(float(np.hypot(dq, dp) / np.hypot(nq, np_)), 10)}
-        log(f"bench: precision={other} {e2 * 1e3 / args.steps:.3f} ms/step  filter {f2:.3f} ms")
-        wl.timed(opts, 1, 0)        # leave the headline form's outputs in place
-
-    if not args.no_compare and form in (1, 2):
-        # the other FP32 kernel form on the same matrix
-        other_form = 3 - form
-        o2 = R.rpca_opts_default(precision=precision, overlap_chunks=args.overlap_chunks,
-                                 filter_form=other_form)
-        if R.rpca_filter_form(wl.ctx, wl.p, wl.r_used, wl.nc + wl.mr, o2) == other_form:
-            e3, f3, r3, K3, u3 = wl.timed(o2, args.steps, 1)
-            detail[f"{FORM_NAMES[other_form]}_form"] = {
-                "ms_per_step": round(e3 * 1e3 / args.steps, 4), "filter_ms": round(f3, 4),
-                "iters_mean": round(float(K3.mean()), 2), "unconverged": u3}
-            log(f"bench: form={FORM_NAMES[other_form]} {e3 * 1e3 / args.steps:.3f} ms/step  filter {f3:.3f} ms")
-            wl.timed(opts, 1, 0)
-
-    cpu = None
     if not args.no_cpu_baseline:
-        sample = args.cpu_sample if args.cpu_sample is not None else (0 if args.config == "c2" else 8000)
-        cpu = cpu_baseline(wl, sample, args.cpu_seconds)
-
-    out = {
-        "metric": "l1-filter solves/s (column + row l1 regressions, with completion of L and S)",
-        "value": round(value, 1),
-        "unit": "regressions/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": round(ms_per_step, 4),
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f32" if precision == 0 else "f16 contractions / f32 state",
-        "data": "synthetic",
-        "config": {"workload": WORKLOADS[args.config]["text"], "name": args.config,
-                   "m": wl.m, "n": wl.n, "r": wl.r, "seed_block": [wl.p, wl.q],
-                   "regressions": regs},
-        "roofline": roofline,
-        "cpu_baseline": cpu,
-        "detail": detail,
-    }
-    print(json.dumps(out), flush=True)
-    wl.ctx.close()
-
-
-def cpu_baseline(wl, sample, seconds):
-    """The FP64 oracle as it stands on the host cores: Algorithm 1 (literal
-    form, OpenMP over regressions) on a sample of the column and row
-    regressions of the same matrix with the same seed factors, plus (for the
-    full sample at m*n <= 1e8) the four-block completion and S = M - L; the
-    pass is repeated until ``seconds`` of oracle time have been spent."""
-    import oracle
-    oracle.build()
-    torch = wl.torch
-    threads = oracle.num_threads(0)
-    nreg = wl.nc + wl.mr
-    if sample and sample < nreg:
-        cols = wl.Jc[: sample // 2]
-        rows = wl.Ic[: sample - sample // 2]
+        oracle_threads()
+    t_start = time.perf_counter()
+    common = {"n_gpus": 1, "warmup": args.warmup, "higher_is_better": True, "scaling": "weak",
+              "vs_baseline": None, "data": "synthetic"}
+    if args.config in SERVE:
+        out = run_serve(args.config, args, R, torch)
+    elif args.config in BATCH:
+        out = run_batch(args.config, args, R, torch, args.steps, args.warmup)
+    elif args.config in WORKLOADS:
+        out = run_plain(args.config, args, R, torch, args.steps, args.warmup, args.overlap_chunks,
+                        args.filter_form, args.precision)
     else:
-        cols, rows = wl.Jc, wl.Ic
-    U = wl.U.cpu().numpy().T
-    V = wl.V.cpu().numpy().T
-    sigma = wl.sg.cpu().numpy()
-    ru = wl.r_used
-    U, V, sigma = U[:, :ru], V[:, :ru], sigma[:ru]
-    # host copies of the regression inputs (column-major M: Md[j, i] = M[i, j])
-    Xc = wl.Md[torch.as_tensor(cols).to(wl.dev)][:, torch.as_tensor(wl.I).to(wl.dev)]
-    Xc = Xc.double().cpu().numpy().T                       # p x len(cols)
-    Xr = wl.Md[torch.as_tensor(wl.J).to(wl.dev)][:, torch.as_tensor(rows).to(wl.dev)]
-    Xr = Xr.double().cpu().numpy()                          # q x len(rows)
-    full = len(cols) == wl.nc and len(rows) == wl.mr and wl.m * wl.n <= 100_000_000
-    Mh = wl.Md.cpu().numpy().T if full else None
-    t_f = t_c = 0.0
-    passes = 0
-    while passes == 0 or t_f + t_c < seconds:
-        t0 = time.perf_counter()
-        Qt, _ = oracle.alg1_batch(Xc, U)
-        Pt, _ = oracle.alg1_batch(Xr, V)
-        t_f += time.perf_counter() - t0
-        if full:
-            t0 = time.perf_counter()
-            oracle.complete(Mh, wl.I, wl.J, U, sigma, V, Qt, Pt)
-            t_c += time.perf_counter() - t0
-        passes += 1
-    t = t_f + t_c
-    log(f"bench: cpu oracle {passes} x {len(cols) + len(rows)} regressions in {t_f:.2f} s, "
-        f"completion {t_c:.2f} s, threads {threads}")
-    return {"value": round(passes * (len(cols) + len(rows)) / t, 1), "unit": "regressions/s",
-            "cores": threads, "kind": "oracle",
-            "sample": f"{len(cols)} column + {len(rows)} row regressions of the same matrix "
-                      f"(FP64, Algorithm 1 literal form)"
-                      f"{' + completion of all entries' if full else ' (no completion)'}"
-                      f", {passes} pass{'es' if passes > 1 else ''}",
-            "seconds": round(t, 2)}
+        out = run_plain("c2", args, R, torch, args.steps, args.warmup, args.overlap_chunks,
+                        args.filter_form, args.precision)
+        log(f"bench: c2 done at {time.perf_counter() - t_start:.0f} s")
+        out["detail"]["c3"] = run_plain("c3", args, R, torch, min(args.steps, 5),
+                                        min(args.warmup, 2))
+        log(f"bench: c3 done at {time.perf_counter() - t_start:.0f} s")
+        out["detail"]["c4"] = run_batch("c4", args, R, torch, args.steps, min(args.warmup, 3))
+        log(f"bench: c4 done at {time.perf_counter() - t_start:.0f} s")
+        out["detail"]["c5"] = run_serve("c5", args, R, torch)
+        log(f"bench: c5 done at {time.perf_counter() - t_start:.0f} s")
+    out["detail"]["bench_wall_s"] = round(time.perf_counter() - t_start, 1)
+    line = {k: out[k] for k in ("metric", "value", "unit")}
+    line.update(n_gpus=1, steps=out["steps"], warmup=args.warmup, ms_per_step=out["ms_per_step"])
+    line.update({k: common[k] for k in ("higher_is_better", "scaling", "vs_baseline")})
+    line.update(dtype=out["dtype"], data=common["data"], config=out["config"],
+                roofline=out["roofline"], cpu_baseline=out["cpu_baseline"], detail=out["detail"])
+    print(json.dumps(line), flush=True)
 
 
 if __name__ == "__main__":
