@@ -220,3 +220,33 @@ def test_c5_classes_served_alone_and_in_a_mix(R):
         worst = max(worst, eL, eS)
         assert eL <= REL_TOL and eS <= REL_TOL and sup == 0, (name, eL, eS, sup)
     say(f"ERR c5 summary: worst relF={worst:.3e}")
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_c5_classes_plain_form_both_precisions(R, precision):
+    # The plain GPU form (rpca_solve, one request at a time) on one request of
+    # each class, in the FP32 form and in the precision form, against the
+    # oracle on the sample's cross.
+    import torch
+    ctx = R.Context(0)
+    worst = 0.0
+    for k, (name, m, n, r) in enumerate(SERVE_CLASSES):
+        s = 1000 * 8 + k
+        Md, _, _ = synth.lowrank_plus_sparse_device(m, n, r, factor_std=np.sqrt(1.0 / max(m, n)),
+                                                    sparsity=0.10, values="pm1", seed=s, device="cuda")
+        I, J = synth.seed_indices(m, n, 10 * r, 10 * r, seed=s)
+        L = torch.empty_like(Md)
+        S = torch.empty_like(Md)
+        st, info = R.rpca_solve(ctx, Md, m, n, m, r, R.rpca_opts_default(precision=precision),
+                                dev_i64(I), dev_i64(J), L, m, S, m)
+        torch.cuda.synchronize()
+        Ms, Xc, Xr, Mx, Lg, Sg, rs, cs = compare_sampled(Md, L, S, m, n, I, J, 3000 + k)
+        Lref, kk, sd = oracle_sampled(Ms, Xc, Xr, r, I, J, rs, cs, m, n)
+        eL, eS, sup = _errors(Lref, Mx, Lg, Sg)
+        say(f"ERR c5 plain precision={precision} class={name} {m}x{n} r={r} "
+            f"status={R.rpca_status_string(st)} relL={eL:.3e} relS={eS:.3e} supp={sup}")
+        worst = max(worst, eL, eS)
+        assert eL <= REL_TOL and eS <= REL_TOL and sup == 0, (name, eL, eS, sup)
+        del Md, L, S
+    ctx.close()
+    say(f"ERR c5 plain precision={precision} summary: worst relF={worst:.3e}")

@@ -196,6 +196,8 @@ def test_solve_matches_oracle_c1(R, ctx, seed):
     assert st == R.RPCA_OK, ctx.last_error()
     assert info.r_used == 10 and info.seed_converged == 1
     Lh, Sh = host_matrix(L, pr.m), host_matrix(S, pr.m)
+    say(f"ERR c1 fp32 seed={seed} relL={relF(Lh, res.L):.3e} relS={relF(Sh, res.S):.3e} "
+        f"relL0={relF(Lh, pr.L0()):.3e}")
     assert relF(Lh, res.L) <= REL_TOL
     assert relF(Sh, res.S) <= REL_TOL
     assert support_mismatch(Sh, res.S, float(np.abs(pr.M).max())) == 0

@@ -56,6 +56,7 @@ def test_precision_solve_c1(R, ctx, seed):
     torch.cuda.synchronize()
     assert st == R.RPCA_OK, ctx.last_error()
     Lh, Sh = host_matrix(L, pr.m), host_matrix(S, pr.m)
+    say(f"ERR c1 fp16 seed={seed} relL={relF(Lh, res.L):.3e} relS={relF(Sh, res.S):.3e}")
     assert relF(Lh, res.L) <= REL_TOL and relF(Sh, res.S) <= REL_TOL
     assert support_mismatch(Sh, res.S, float(np.abs(pr.M).max())) == 0
 
