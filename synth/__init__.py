@@ -368,3 +368,31 @@ def batch_job_device(spec: BatchJobSpec, device="cuda", out=None):
     Mt.copy_(L64)
     del L64
     return Mt, A0, B0
+
+
+# ---------------------------------------------------------------------------
+# A deterministic rank-2 low-rank part: the m x n "checkerboard" image of the
+# paper's deterministic test (square cells of `cell` pixels, values 0 and 1:
+# C[i, j] = (floor(i / cell) + floor(j / cell)) mod 2, which is
+# a_i (1 - b_j) + (1 - a_i) b_j with 0/1 vectors a, b, hence rank 2), with a
+# fraction of its pixels replaced by impulsive noise: a uniformly random
+# support (counter hash of the linear index, as above), each hit pixel set
+# to 0 or 1 with equal probability.  S0 = noisy - C is zero where the noise
+# value equals the pixel's own value.
+# ---------------------------------------------------------------------------
+def checkerboard(m: int, n: int, cell: int, noise: float, seed: int = 1) -> Problem:
+    i = np.arange(m)[:, None] // cell
+    j = np.arange(n)[None, :] // cell
+    C = ((i + j) % 2).astype(np.float64)
+    lin = (np.arange(n, dtype=np.uint64)[None, :] * np.uint64(m)
+           + np.arange(m, dtype=np.uint64)[:, None])
+    hit = hash_uniform(seed, 1, lin) < noise
+    val = (hash_uniform(seed, 2, lin) < 0.5).astype(np.float64)
+    M = np.asfortranarray(np.where(hit, val, C).astype(np.float32))
+    a = (np.arange(m) // cell % 2).astype(np.float64)
+    b = (np.arange(n) // cell % 2).astype(np.float64)
+    # C = A0 B0^T with A0 = [a, 1 - a], B0 = [1 - b, b]
+    A0 = np.stack([a, 1.0 - a], axis=1)
+    B0 = np.stack([1.0 - b, b], axis=1)
+    return Problem(M=M, A0=A0, B0=B0, support=np.asfortranarray(hit & (val != C)), m=m, n=n, r=2,
+                   seed=seed)

@@ -83,3 +83,16 @@ def test_batch_job_host_and_device_agree():
         S0 = P.M.astype(np.float64) - (A0 @ B0.T)
         assert np.all(np.abs(S0[~P.support]) < 1e-6)
         assert np.all((S0[P.support] > -1e-6) & (S0[P.support] < 1 + 1e-6))   # U[0, 1] values
+
+
+def test_checkerboard_is_rank_two_plus_impulsive_noise():
+    pr = synth.checkerboard(300, 240, 30, 0.10, seed=4)
+    C = pr.L0()
+    assert np.linalg.matrix_rank(C) == 2
+    assert set(np.unique(C)) == {0.0, 1.0}
+    assert C[0, 0] == 0 and C[0, 30] == 1 and C[30, 30] == 0
+    S0 = pr.M.astype(np.float64) - C
+    assert np.array_equal(S0 != 0, pr.support)
+    hit_rate = (pr.M != C.astype(np.float32)).mean()
+    assert 0.03 < hit_rate < 0.07          # half of the 10% hits change the pixel
+    assert set(np.unique(pr.M)) == {0.0, 1.0}
