@@ -109,6 +109,16 @@ typedef struct {
                                  /* elements) where built for the class, else the tile     */
                                  /* form.  Results agree within rounding, not bit for bit. */
                                  /* (0)                                                    */
+    int32_t seed_route;          /* FP64 SVD inside the seed solver: 0 = automatic (blocks  */
+                                 /* of up to 6400 entries: Jacobi SVD in LDS; blocks up to */
+                                 /* 512 x 512 of a batch: one launch of the device-resident*/
+                                 /* subspace iteration, a workgroup each, whatever the     */
+                                 /* batch holds; one block alone (rpca_seed, rpca_solve):  */
+                                 /* the eigen-decomposition of the Gram matrix, the faster */
+                                 /* of the two there);                                     */
+                                 /* 1 = always the Gram eigen-decomposition (rocSOLVER,    */
+                                 /* one host synchronisation per ALM step); 2 = the        */
+                                 /* device-resident routes wherever they apply (0)         */
 } rpca_opts;
 
 /* What rpca_solve reports. */

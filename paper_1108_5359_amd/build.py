@@ -18,7 +18,7 @@ CSRC = HERE / "csrc"
 LIB = HERE / "librpca.so"
 BUILD = HERE / "_build"
 ROCM = pathlib.Path(os.environ.get("ROCM_PATH", "/opt/rocm"))
-SOURCES = ["api.cpp", "batch_api.cpp", "server.cpp", "pipeline.cpp", "filter.hip", "reconstruct.hip", "seed.hip", "seed_small.hip", "batch.hip", "rank.cpp"]
+SOURCES = ["api.cpp", "batch_api.cpp", "server.cpp", "pipeline.cpp", "filter.hip", "reconstruct.hip", "seed.hip", "seed_small.hip", "seed_large.hip", "batch.hip", "rank.cpp"]
 # filter_inst.hip is compiled once per tile class (one object each)
 FILTER_PT = [1, 2, 3, 4, 5, 7, 8, 10, 13, 16, 19, 26, 32]
 

@@ -115,6 +115,8 @@ int check_opts(rpca_ctx *ctx, const rpca_opts &o)
         return set_status(ctx, RPCA_ERR_ARG, "opts: overlap_chunks must be in [0, 16]");
     if (o.filter_form < 0 || o.filter_form > 2)
         return set_status(ctx, RPCA_ERR_ARG, "opts: filter_form must be 0 (automatic), 1 (tile) or 2 (split)");
+    if (o.seed_route < 0 || o.seed_route > 2)
+        return set_status(ctx, RPCA_ERR_ARG, "opts: seed_route must be 0 (automatic), 1 (eigen) or 2 (device-resident)");
     return RPCA_OK;
 }
 
@@ -197,6 +199,7 @@ void rpca_opts_default(rpca_opts *o)
     o->precision = 0;
     o->overlap_chunks = 0;
     o->filter_form = 0;
+    o->seed_route = 0;
 }
 
 const char *rpca_status_string(int s)

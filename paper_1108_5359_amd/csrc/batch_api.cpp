@@ -557,18 +557,53 @@ int rpca_batch_seed(rpca_batch_t b, hipStream_t stream)
             if ((st = note(small[k], sts[k], what)) != RPCA_OK) return st;
         }
     }
-    // the others one at a time (rocSOLVER route)
-    size_t next_small = 0;
+    std::vector<char> done(b->jobs.size(), 0);
+    for (size_t j : small) done[j] = 1;
+    // larger blocks (up to 512 x 512): one launch of the device-resident
+    // subspace-iteration solver, one workgroup each.  Every such block takes
+    // it, however many the batch holds, so that a request's result does not
+    // depend on what it is batched with.
+    std::vector<size_t> large;
+    args.clear();
     for (size_t j = 0; j < b->jobs.size(); ++j) {
-        if (next_small < small.size() && small[next_small] == j) {
-            ++next_small;
+        const rpca_job &J = b->jobs[j];
+        if (done[j] || !b->tun.seed_batched || b->opts.seed_route == 1 || !seed_large_fits(ctx, J.p, J.q))
             continue;
+        large.push_back(j);
+        args.push_back(SmallSeedArgs{J.M, J.ldm, J.seed_rows, J.seed_cols, J.p, J.q, J.r, dU(j),
+                                     dsig(j), dV(j)});
+    }
+    if (!large.empty()) {
+        const auto t0 = std::chrono::steady_clock::now();
+        int st = ensure_buf(ctx, b->seed_ws, seed_large_workspace(args.data(), (int)args.size()));
+        if (st != RPCA_OK) return st;
+        std::vector<SeedOut> outs(large.size());
+        std::vector<int> sts(large.size());
+        st = run_seed_large(ctx, args.data(), (int)args.size(), b->opts, b->seed_ws.ptr, outs.data(),
+                            sts.data(), b->bs);
+        if (st != RPCA_OK) return st;
+        const double ms =
+            std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+        for (size_t k = 0; k < large.size(); ++k) {
+            if (outs[k].fallback) continue;          // taken again by the route below
+            BatchJobState &S = b->js[large[k]];
+            S.so = outs[k];
+            S.seed_status = seed_status_message(ctx, sts[k], outs[k], b->jobs[large[k]].r);
+            S.t_seed_ms = ms;
+            done[large[k]] = 1;
+            if ((st = note(large[k], S.seed_status, ctx->last_error)) != RPCA_OK) return st;
         }
+    }
+    // the others one at a time (eigen-decomposition route)
+    rpca_opts eig = b->opts;
+    eig.seed_route = 1;
+    for (size_t j = 0; j < b->jobs.size(); ++j) {
+        if (done[j]) continue;
         const rpca_job &J = b->jobs[j];
         BatchJobState &S = b->js[j];
         const auto t0 = std::chrono::steady_clock::now();
         S.so = SeedOut{};
-        S.seed_status = run_seed(ctx, J.M, J.ldm, J.seed_rows, J.p, J.seed_cols, J.q, J.r, b->opts,
+        S.seed_status = run_seed(ctx, J.M, J.ldm, J.seed_rows, J.p, J.seed_cols, J.q, J.r, eig,
                                  dU(j), dsig(j), dV(j), &S.so, b->bs);
         S.t_seed_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
         int st = note(j, S.seed_status, ctx->last_error);

@@ -175,11 +175,15 @@ struct SeedOut {
     int32_t iters = 0;
     int32_t converged = 0;
     int32_t rank_found = 0;
+    int32_t ritz_steps = 0;      // device-resident route: Rayleigh-Ritz steps in all
+    int32_t fallback = 0;        // device-resident route: 1 = the subspace would exceed its cap
 };
 
 int run_seed(rpca_ctx *ctx, const float *M, int64_t ldm, const int64_t *seed_rows, int64_t p,
              const int64_t *seed_cols, int64_t q, int32_t r, const rpca_opts &o, double *U,
              double *sigma, double *V, SeedOut *out, hipStream_t stream);
+// Status of a seed solve as returned to callers, with its message set.
+int seed_status_message(rpca_ctx *ctx, int status, const SeedOut &so, int32_t r);
 
 // Many small seed blocks in one launch (one workgroup each, Jacobi SVD in LDS).
 struct SmallSeedArgs {
@@ -195,6 +199,14 @@ bool seed_small_fits(rpca_ctx *ctx, int64_t p, int64_t q);
 // Device workspace (bytes) run_seed_small needs for these problems.
 size_t seed_small_workspace(const SmallSeedArgs *args, int n);
 // Solve them; per problem, the status of run_seed and its SeedOut.  Synchronous.
+int run_seed_large(rpca_ctx *ctx, const SmallSeedArgs *args, int n, const rpca_opts &o, void *ws,
+                   SeedOut *outs, int *statuses, hipStream_t stream);
+// The device-resident route (seed_large.hip): whether a p x q block fits it,
+// and the workspace (bytes) n problems need.  A problem whose SVT would need
+// more directions than the route holds comes back with RPCA_ERR_UNSUPPORTED
+// and SeedOut::fallback = 1.
+bool seed_large_fits(rpca_ctx *ctx, int64_t p, int64_t q);
+size_t seed_large_workspace(const SmallSeedArgs *args, int n);
 int run_seed_small(rpca_ctx *ctx, const SmallSeedArgs *args, int n, const rpca_opts &o, void *ws,
                    SeedOut *outs, int *statuses, hipStream_t stream);
 

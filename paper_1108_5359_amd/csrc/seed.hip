@@ -171,10 +171,49 @@ unsigned blocks_for(int64_t n) { return (unsigned)((n + kThreads - 1) / kThreads
 
 } // namespace
 
+int seed_status_message(rpca_ctx *ctx, int status, const SeedOut &so, int32_t r)
+{
+    switch (status) {
+    case RPCA_ERR_NUMERIC: return set_status(ctx, status, "seed: non-finite entry in the seed block");
+    case RPCA_ERR_SEED: return set_status(ctx, status, "seed: the recovered seed has rank 0");
+    case RPCA_WARN_RANK:
+        return set_status(ctx, status, "seed: rank of L^s is " + std::to_string(so.rank_found) +
+                                           ", target " + std::to_string(r));
+    case RPCA_WARN_NOT_CONVERGED: return set_status(ctx, status, "seed: tolerance not met");
+    default: return status;
+    }
+}
+
 int run_seed(rpca_ctx *ctx, const float *M, int64_t ldm, const int64_t *seed_rows, int64_t p,
              const int64_t *seed_cols, int64_t q, int32_t r, const rpca_opts &o, double *U,
              double *sigma, double *V, SeedOut *out, hipStream_t stream)
 {
+    // The device-resident solvers where the block fits them: the whole ALM
+    // in one workgroup (Jacobi SVD in LDS up to 6400 entries, seed_small.hip;
+    // subspace iteration up to 512 x 512, seed_large.hip, only when asked
+    // for: for one block alone the eigen-decomposition route below is the
+    // faster, the subspace route pays off when a batch runs many blocks in
+    // one launch); else, or when the subspace iteration needs more
+    // directions than it holds, the eigen-decomposition route.
+    if (o.seed_route != 1) {
+        const bool small = p * q <= 6400 && seed_small_fits(ctx, p, q);
+        const bool large = !small && o.seed_route == 2 && seed_large_fits(ctx, p, q);
+        if (small || large) {
+            SmallSeedArgs a{M, ldm, seed_rows, seed_cols, p, q, r, U, sigma, V};
+            int st = ensure_buf(ctx, ctx->seed_ws, small ? seed_small_workspace(&a, 1)
+                                                         : seed_large_workspace(&a, 1));
+            if (st != RPCA_OK) return st;
+            SeedOut so;
+            int sst = RPCA_OK;
+            st = small ? run_seed_small(ctx, &a, 1, o, ctx->seed_ws.ptr, &so, &sst, stream)
+                       : run_seed_large(ctx, &a, 1, o, ctx->seed_ws.ptr, &so, &sst, stream);
+            if (st != RPCA_OK) return st;
+            if (!(large && so.fallback)) {
+                *out = so;
+                return seed_status_message(ctx, sst, so, r);
+            }
+        }
+    }
     const int64_t len = p * q;
     const int kk = (int)(p < q ? p : q);          // Gram side
     const bool gram_right = q <= p;               // G = W^T W (q x q), else W W^T (p x p)

@@ -1,0 +1,148 @@
+// One-sided Jacobi SVD (Hestenes' method) of a matrix held in LDS, and the
+// workgroup reductions around it, shared by the FP64 seed solvers
+// (seed_small.hip: the whole SVT; seed_large.hip: the SVD of the small
+// triangular factor of its Rayleigh-Ritz step).  Every function is called by
+// all kThreads threads of a workgroup.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace seedj {
+
+constexpr int kThreads = 256;
+constexpr int kG = 8;                       // lanes per column pair
+constexpr int kGroups = kThreads / kG;      // pairs in flight
+constexpr int kMaxSweeps = 40;
+constexpr double kJacobiEps = 1e-15;        // |x_i . x_j| <= eps ||x_i|| ||x_j|| counts as orthogonal
+constexpr int kColdEvery = 64;              // ALM steps between Jacobi starts from the identity
+
+__device__ __forceinline__ double group_sum(double v)
+{
+    v += __shfl_xor(v, 1);
+    v += __shfl_xor(v, 2);
+    v += __shfl_xor(v, 4);
+    return v;
+}
+
+// Sum / max over the workgroup (every thread gets the result).
+__device__ inline double block_sum(double v, double *red)
+{
+    for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o);
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    return red[0] + red[1] + red[2] + red[3];
+}
+
+__device__ inline double block_max(double v, double *red)
+{
+    for (int o = 32; o >= 1; o >>= 1) v = fmax(v, __shfl_xor(v, o));
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    return fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
+}
+
+// Pair pr of round k of a round-robin tournament on m2 (even) players.
+__device__ __forceinline__ void tournament_pair(int k, int pr, int m2, int &i, int &j)
+{
+    const int n = m2 - 1;
+    int a, b;
+    if (pr == 0) {
+        a = n;
+        b = k % n;
+    } else {
+        a = (k + pr) % n;
+        b = (k - pr + n) % n;
+    }
+    i = a < b ? a : b;
+    j = a < b ? b : a;
+}
+
+// One-sided Jacobi on the columns of X (n1 x n2, column-major in LDS) with
+// the rotations accumulated into V (n2 x n2): set to the identity first when
+// `cold`, else X already holds W V for the V of a previous step (warm start:
+// its columns are nearly orthogonal, so few sweeps are needed).
+__device__ inline void jacobi_svd(double *X, double *V, int n1, int n2, int *flag, bool cold)
+{
+    const int tid = threadIdx.x;
+    if (cold)
+        for (int t = tid; t < n2 * n2; t += kThreads) V[t] = (t % n2 == t / n2) ? 1.0 : 0.0;
+    const int m2 = n2 + (n2 & 1);
+    const int npairs = m2 / 2;
+    const int grp = tid / kG, gl = tid % kG;
+    __syncthreads();
+    for (int sweep = 0; sweep < kMaxSweeps; ++sweep) {
+        if (tid == 0) *flag = 0;
+        __syncthreads();
+        for (int round = 0; round < m2 - 1; ++round) {
+            for (int base = 0; base < npairs; base += kGroups) {
+                const int pr = base + grp;
+                int i = 0, j = 0;
+                if (pr < npairs) tournament_pair(round, pr, m2, i, j);
+                const bool live = pr < npairs && j < n2;     // same for the 8 lanes of a group
+                if (live) {
+                    double al = 0.0, be = 0.0, ga = 0.0;
+                    const double *xi = X + (int64_t)i * n1, *xj = X + (int64_t)j * n1;
+#pragma unroll 4
+                    for (int e = gl; e < n1; e += kG) {
+                        const double a = xi[e], b = xj[e];
+                        al = fma(a, a, al);
+                        be = fma(b, b, be);
+                        ga = fma(a, b, ga);
+                    }
+                    al = group_sum(al);
+                    be = group_sum(be);
+                    ga = group_sum(ga);
+                    if (ga * ga > (kJacobiEps * kJacobiEps) * (al * be)) {
+                        // t = tan of the rotation: the root of smaller modulus of
+                        // t^2 + 2 zeta t - 1 = 0, zeta = (be - al) / (2 ga), written
+                        // with one division: sign(zeta) |2 ga| / (|d| + sqrt(d^2 + 4 ga^2))
+                        const double d = be - al, g2 = 2.0 * ga;
+                        const double sg = (d == 0.0 || ((d > 0.0) == (ga > 0.0))) ? 1.0 : -1.0;
+                        const double t = sg * fabs(g2) / (fabs(d) + sqrt(fma(d, d, g2 * g2)));
+                        const double c = 1.0 / sqrt(fma(t, t, 1.0)), s = c * t;
+                        double *wi = X + (int64_t)i * n1, *wj = X + (int64_t)j * n1;
+    #pragma unroll 4
+                    for (int e = gl; e < n1; e += kG) {
+                            const double a = wi[e], b = wj[e];
+                            wi[e] = c * a - s * b;
+                            wj[e] = s * a + c * b;
+                        }
+                        double *vi = V + (int64_t)i * n2, *vj = V + (int64_t)j * n2;
+#pragma unroll 4
+                        for (int e = gl; e < n2; e += kG) {
+                            const double a = vi[e], b = vj[e];
+                            vi[e] = c * a - s * b;
+                            vj[e] = s * a + c * b;
+                        }
+                        if (gl == 0) *flag = 1;
+                    }
+                }
+            }
+            __syncthreads();      // the next round pairs columns of this one
+        }
+        if (*flag == 0) break;
+        __syncthreads();
+    }
+    __syncthreads();
+}
+
+// Column norms of X into sig[0..n2).
+__device__ inline void column_norms(const double *X, int n1, int n2, double *sig)
+{
+    const int grp = threadIdx.x / kG, gl = threadIdx.x % kG;
+    for (int c0 = 0; c0 < n2; c0 += kGroups) {
+        const int c = c0 + grp;
+        double s = 0.0;
+        if (c < n2)
+            for (int e = gl; e < n1; e += kG) s = fma(X[(int64_t)c * n1 + e], X[(int64_t)c * n1 + e], s);
+        s = group_sum(s);
+        if (c < n2 && gl == 0) sig[c] = sqrt(s);
+    }
+    __syncthreads();
+}
+
+} // namespace seedj

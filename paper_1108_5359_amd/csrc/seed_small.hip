@@ -20,6 +20,7 @@
 // doubles per problem, L2 resident); LDS holds X, V and the singular values,
 // which, with speed, bounds the problems this path accepts (seed_small_fits).
 #include "rpca_internal.h"
+#include "seed_jacobi.h"
 
 #include <cfloat>
 #include <cmath>
@@ -28,12 +29,8 @@
 
 namespace seedk {
 
-constexpr int kThreads = 256;
-constexpr int kG = 8;                       // lanes per column pair
-constexpr int kGroups = kThreads / kG;      // pairs in flight
-constexpr int kMaxSweeps = 40;
-constexpr double kJacobiEps = 1e-15;        // |x_i . x_j| <= eps ||x_i|| ||x_j|| counts as orthogonal
-constexpr int kColdEvery = 64;              // ALM steps between Jacobi starts from the identity
+using namespace seedj;
+
 constexpr int64_t kMaxElems = 80 * 80;      // largest seed block (p q) of this route
 
 struct SmallSeedJob {
@@ -50,126 +47,6 @@ struct SmallSeedConsts {
     double lam, tol, rho, mu0_scale, mu_max_scale, rank_floor;
     int32_t max_iter;
 };
-
-__device__ __forceinline__ double group_sum(double v)
-{
-    v += __shfl_xor(v, 1);
-    v += __shfl_xor(v, 2);
-    v += __shfl_xor(v, 4);
-    return v;
-}
-
-// Sum / max over the workgroup (every thread gets the result).
-__device__ double block_sum(double v, double *red)
-{
-    for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o);
-    __syncthreads();
-    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
-    __syncthreads();
-    return red[0] + red[1] + red[2] + red[3];
-}
-
-__device__ double block_max(double v, double *red)
-{
-    for (int o = 32; o >= 1; o >>= 1) v = fmax(v, __shfl_xor(v, o));
-    __syncthreads();
-    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
-    __syncthreads();
-    return fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
-}
-
-// Pair pr of round k of a round-robin tournament on m2 (even) players.
-__device__ __forceinline__ void tournament_pair(int k, int pr, int m2, int &i, int &j)
-{
-    const int n = m2 - 1;
-    int a, b;
-    if (pr == 0) {
-        a = n;
-        b = k % n;
-    } else {
-        a = (k + pr) % n;
-        b = (k - pr + n) % n;
-    }
-    i = a < b ? a : b;
-    j = a < b ? b : a;
-}
-
-// One-sided Jacobi on the columns of X (n1 x n2, column-major in LDS) with
-// the rotations accumulated into V (n2 x n2): set to the identity first when
-// `cold`, else X already holds W V for the V of a previous step (warm start:
-// its columns are nearly orthogonal, so few sweeps are needed).
-__device__ void jacobi_svd(double *X, double *V, int n1, int n2, int *flag, bool cold)
-{
-    const int tid = threadIdx.x;
-    if (cold)
-        for (int t = tid; t < n2 * n2; t += kThreads) V[t] = (t % n2 == t / n2) ? 1.0 : 0.0;
-    const int m2 = n2 + (n2 & 1);
-    const int npairs = m2 / 2;
-    const int grp = tid / kG, gl = tid % kG;
-    __syncthreads();
-    for (int sweep = 0; sweep < kMaxSweeps; ++sweep) {
-        if (tid == 0) *flag = 0;
-        __syncthreads();
-        for (int round = 0; round < m2 - 1; ++round) {
-            for (int base = 0; base < npairs; base += kGroups) {
-                const int pr = base + grp;
-                int i = 0, j = 0;
-                if (pr < npairs) tournament_pair(round, pr, m2, i, j);
-                const bool live = pr < npairs && j < n2;     // same for the 8 lanes of a group
-                if (live) {
-                    double al = 0.0, be = 0.0, ga = 0.0;
-                    const double *xi = X + (int64_t)i * n1, *xj = X + (int64_t)j * n1;
-                    for (int e = gl; e < n1; e += kG) {
-                        const double a = xi[e], b = xj[e];
-                        al = fma(a, a, al);
-                        be = fma(b, b, be);
-                        ga = fma(a, b, ga);
-                    }
-                    al = group_sum(al);
-                    be = group_sum(be);
-                    ga = group_sum(ga);
-                    if (fabs(ga) > kJacobiEps * sqrt(al * be)) {
-                        const double zeta = (be - al) / (2.0 * ga);
-                        const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-                        const double c = 1.0 / sqrt(1.0 + t * t), s = c * t;
-                        double *wi = X + (int64_t)i * n1, *wj = X + (int64_t)j * n1;
-                        for (int e = gl; e < n1; e += kG) {
-                            const double a = wi[e], b = wj[e];
-                            wi[e] = c * a - s * b;
-                            wj[e] = s * a + c * b;
-                        }
-                        double *vi = V + (int64_t)i * n2, *vj = V + (int64_t)j * n2;
-                        for (int e = gl; e < n2; e += kG) {
-                            const double a = vi[e], b = vj[e];
-                            vi[e] = c * a - s * b;
-                            vj[e] = s * a + c * b;
-                        }
-                        if (gl == 0) *flag = 1;
-                    }
-                }
-            }
-            __syncthreads();      // the next round pairs columns of this one
-        }
-        if (*flag == 0) break;
-        __syncthreads();
-    }
-    __syncthreads();
-}
-
-// Column norms of X into sig[0..n2).
-__device__ void column_norms(const double *X, int n1, int n2, double *sig)
-{
-    const int grp = threadIdx.x / kG, gl = threadIdx.x % kG;
-    for (int c0 = 0; c0 < n2; c0 += kGroups) {
-        const int c = c0 + grp;
-        double s = 0.0;
-        if (c < n2)
-            for (int e = gl; e < n1; e += kG) s = fma(X[(int64_t)c * n1 + e], X[(int64_t)c * n1 + e], s);
-        s = group_sum(s);
-        if (c < n2 && gl == 0) sig[c] = sqrt(s);
-    }
-    __syncthreads();
-}
 
 // X <- the SVT input W = Ms - S + Y inv_mu (transposed when p < q).
 __device__ void load_x(double *X, const double *Ms, const double *S, const double *Y, int p, int q,

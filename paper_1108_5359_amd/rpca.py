@@ -47,6 +47,7 @@ class rpca_opts(ctypes.Structure):
         ("filt_max_iter", ctypes.c_int32), ("filt_refresh", ctypes.c_int32),
         ("rng_seed", ctypes.c_uint64), ("precision", ctypes.c_int32),
         ("overlap_chunks", ctypes.c_int32), ("filter_form", ctypes.c_int32),
+        ("seed_route", ctypes.c_int32),
     ]
 
 

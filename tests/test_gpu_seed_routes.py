@@ -1,0 +1,143 @@
+"""GPU parity of the seed PCP (Sec. 3.1, eq. SPCP) on every route of the
+library's FP64 seed solver, against the oracle's inexact ALM with a full
+LAPACK SVD in each step:
+
+* the device-resident subspace-iteration solver (blocks above 6400 entries up
+  to 512 x 512; seed_route = 2),
+* the eigen-decomposition route (seed_route = 1, and the automatic choice for
+  one such block alone),
+* the batched form's seed launch on blocks of several sizes at once (the
+  automatic choice there: LDS Jacobi for the small block, one subspace
+  launch for the others).
+
+Compared: the rank, the ALM step count (within one step) and L^s = U Sigma V^T
+(relative Frobenius; never the factors themselves, which are defined up to
+sign).  On blocks whose PCP recovers L^s the subspace route agrees with the
+oracle to rounding (1e-9 asserted); the eigen route squares the spectrum and
+is held to 1e-7.  Seed times are printed (``SEED`` lines).
+"""
+from __future__ import annotations
+
+import functools
+import time
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from gpu_util import dev_i64, dev_matrix, relF, say
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def R():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    import paper_1108_5359_amd.rpca as R
+    return R
+
+
+@pytest.fixture(scope="module")
+def ctx(R):
+    c = R.Context(0)
+    yield c
+    c.close()
+
+
+# (p, q, r, magnitude of the full matrix the block comes from, corruption rate, seed)
+BLOCKS = {
+    "c1_100": (100, 100, 10, 1000, 0.10, 1),
+    "c2_200": (200, 200, 20, 10000, 0.10, 2),
+    "c5C_300": (300, 300, 30, 20000, 0.10, 3),
+    "c3_500": (500, 500, 50, 50000, 0.05, 4),
+    "tall_250x120": (250, 120, 12, 5000, 0.08, 5),
+    "wide_96x300": (96, 300, 9, 5000, 0.08, 6),
+}
+
+
+@functools.lru_cache(maxsize=None)
+def block(name):
+    p, q, r, big, rho, seed = BLOCKS[name]
+    pr = synth.lowrank_plus_sparse(p, q, r, factor_std=np.sqrt(1.0 / big), sparsity=rho,
+                                   values="pm1" if name != "c3_500" else "unif11", seed=seed)
+    sd = oracle.seed_pcp(pr.M.astype(np.float64))
+    return pr, r, sd
+
+
+def _seed(R, ctx, pr, r, route):
+    import torch
+    p, q = pr.m, pr.n
+    U = torch.zeros((r, p), dtype=torch.float64, device="cuda")
+    sg = torch.zeros(r, dtype=torch.float64, device="cuda")
+    V = torch.zeros((r, q), dtype=torch.float64, device="cuda")
+    Md = dev_matrix(pr.M)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st, ru, its = R.rpca_seed(ctx, Md, p, q, p, dev_i64(np.arange(p)), p, dev_i64(np.arange(q)), q, r,
+                              R.rpca_opts_default(seed_route=route), U, sg, V)
+    ms = (time.perf_counter() - t0) * 1e3
+    Uh, sh, Vh = U.cpu().numpy().T, sg.cpu().numpy(), V.cpu().numpy().T
+    return st, ru, its, (Uh * sh) @ Vh.T, Uh, sh, ms
+
+
+@pytest.mark.parametrize("name", sorted(BLOCKS))
+@pytest.mark.parametrize("route", [2, 1])
+def test_seed_route_matches_oracle(R, ctx, name, route):
+    pr, r, sd = block(name)
+    k = min(sd.rank, r)
+    Ls_ref = (sd.U[:, :k] * sd.sigma[:k]) @ sd.V[:, :k].T
+    _seed(R, ctx, pr, r, route)                                   # warm-up (code objects, workspace)
+    st, ru, its, Ls, Uh, sh, ms = _seed(R, ctx, pr, r, route)
+    e = relF(Ls, Ls_ref)
+    say(f"SEED {name} route={route} p={pr.m} q={pr.n} status={R.rpca_status_string(st)} rank={ru}/"
+        f"{sd.rank} iters={its}/{sd.iters} relF(L^s)={e:.2e} t={ms:.1f} ms")
+    assert st >= 0
+    assert ru == k
+    assert abs(its - sd.iters) <= 1
+    assert e <= (1e-9 if route == 2 else 1e-7)
+    assert np.allclose(Uh[:, :k].T @ Uh[:, :k], np.eye(k), atol=1e-10)
+    assert np.all(np.diff(sh[:k]) <= 0) and np.all(sh[k:] == 0)
+
+
+def test_batched_seeds_of_several_sizes(R, ctx):
+    # One batch with seed blocks of 50^2 (LDS Jacobi), 100^2 and 300^2
+    # (subspace iteration, one launch) and 200 x 160: each job's L^s against
+    # the oracle's seed PCP of its block.
+    import torch
+    specs = [(600, 600, 5, 50, 50), (2000, 500, 10, 100, 100), (3000, 3000, 30, 300, 300),
+             (1500, 1200, 16, 200, 160)]
+    keep, jobs, refs = [], [], []
+    for k, (m, n, r, p, q) in enumerate(specs):
+        pr = synth.lowrank_plus_sparse(m, n, r, factor_std=np.sqrt(1.0 / max(m, n)), sparsity=0.1,
+                                       values="pm1", seed=40 + k)
+        I, J = synth.seed_indices(m, n, p, q, seed=40 + k)
+        sd = oracle.seed_pcp(pr.M[np.ix_(I, J)].astype(np.float64))
+        refs.append((pr, I, J, r, sd))
+        Md = dev_matrix(pr.M)
+        L = torch.empty_like(Md)
+        S = torch.empty_like(Md)
+        dI, dJ = dev_i64(I), dev_i64(J)
+        keep.append((Md, L, S, dI, dJ))
+        jobs.append(R.job(Md, m, n, m, r, dI, p, dJ, q, L, m, S, m))
+    b = R.Batch(ctx, jobs, R.rpca_opts_default())
+    t0 = time.perf_counter()
+    R.rpca_batch_seed(b)
+    say(f"SEED batch of {len(jobs)} blocks: {1e3 * (time.perf_counter() - t0):.1f} ms")
+    for k, (pr, I, J, r, sd) in enumerate(refs):
+        p, q = len(I), len(J)
+        U = torch.zeros((r, p), dtype=torch.float64, device="cuda")
+        sg = torch.zeros(r, dtype=torch.float64, device="cuda")
+        V = torch.zeros((r, q), dtype=torch.float64, device="cuda")
+        R.rpca_batch_job_factors(b, k, U, sg, V)
+        st, info = R.rpca_batch_job_info(b, k)
+        kk = min(sd.rank, r)
+        Ls = (U.cpu().numpy().T * sg.cpu().numpy()) @ V.cpu().numpy()
+        Ls_ref = (sd.U[:, :kk] * sd.sigma[:kk]) @ sd.V[:, :kk].T
+        e = relF(Ls, Ls_ref)
+        say(f"SEED batch job {k} p={p} q={q} rank={info.r_used}/{sd.rank} iters={info.seed_iters}/"
+            f"{sd.iters} relF(L^s)={e:.2e}")
+        assert info.r_used == kk and abs(info.seed_iters - sd.iters) <= 1
+        assert e <= 1e-9
+    b.close()
