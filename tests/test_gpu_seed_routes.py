@@ -141,3 +141,68 @@ def test_batched_seeds_of_several_sizes(R, ctx):
         assert info.r_used == kk and abs(info.seed_iters - sd.iters) <= 1
         assert e <= 1e-9
     b.close()
+
+
+def _seed_block(R, ctx, Mblk, r, route):
+    """rpca_seed on the whole block (identity seed indices); L^s and factors."""
+    import torch
+    p, q = Mblk.shape
+    Md = dev_matrix(np.asfortranarray(Mblk.astype(np.float32)))
+    U = torch.zeros((r, p), dtype=torch.float64, device="cuda")
+    sg = torch.zeros(r, dtype=torch.float64, device="cuda")
+    V = torch.zeros((r, q), dtype=torch.float64, device="cuda")
+    st, ru, its = R.rpca_seed(ctx, Md, p, q, p, dev_i64(np.arange(p)), p, dev_i64(np.arange(q)), q, r,
+                              R.rpca_opts_default(seed_route=route), U, sg, V)
+    Uh, sh, Vh = U.cpu().numpy().T, sg.cpu().numpy(), V.cpu().numpy().T
+    return st, ru, its, (Uh * sh) @ Vh.T
+
+
+def _against_oracle(name, Mblk, st, ru, its, Ls, r, tol):
+    sd = oracle.seed_pcp(Mblk.astype(np.float32).astype(np.float64))
+    k = min(sd.rank, r)
+    Ls_ref = (sd.U[:, :k] * sd.sigma[:k]) @ sd.V[:, :k].T
+    e = relF(Ls, Ls_ref)
+    say(f"SEED {name} p={Mblk.shape[0]} q={Mblk.shape[1]} rank={ru}/{sd.rank} iters={its}/{sd.iters} "
+        f"relF(L^s)={e:.2e}")
+    assert st >= 0 and ru == k and abs(its - sd.iters) <= 1
+    assert e <= tol
+
+
+def test_subspace_route_falls_back_past_its_widest_basis(R, ctx):
+    # A 200 x 200 block of rank 90 with few corruptions: the iterate keeps
+    # more than the 72 directions the subspace solver holds, so it reports a
+    # fallback and the eigen route finishes (held to that route's 1e-7).
+    pr = synth.lowrank_plus_sparse(200, 200, 90, factor_std=0.1, sparsity=0.02, values="pm1", seed=11)
+    st, ru, its, Ls = _seed_block(R, ctx, pr.M, 120, 2)
+    _against_oracle("fallback_rank90", pr.M, st, ru, its, Ls, 120, 1e-7)
+    assert ru > 64
+
+
+@pytest.mark.parametrize("shape", [(512, 81), (81, 512)])
+def test_subspace_route_at_its_size_limits(R, ctx, shape):
+    p, q = shape
+    pr = synth.lowrank_plus_sparse(p, q, 8, factor_std=np.sqrt(1.0 / 5000), sparsity=0.08, values="pm1",
+                                   seed=12 + p)
+    st, ru, its, Ls = _seed_block(R, ctx, pr.M, 8, 2)
+    _against_oracle(f"limit_{p}x{q}", pr.M, st, ru, its, Ls, 8, 1e-9)
+
+
+def test_subspace_route_rank_one(R, ctx):
+    # the basis starts 16 wide for a rank-1 block
+    pr = synth.lowrank_plus_sparse(120, 150, 1, factor_std=0.05, sparsity=0.1, values="pm1", seed=13)
+    st, ru, its, Ls = _seed_block(R, ctx, pr.M, 1, 2)
+    _against_oracle("rank1_120x150", pr.M, st, ru, its, Ls, 1, 1e-9)
+
+
+@pytest.mark.parametrize("case", ["zero", "nan"])
+def test_subspace_route_error_paths(R, ctx, case):
+    Mblk = np.zeros((120, 110), dtype=np.float32)
+    if case == "nan":
+        Mblk = synth.lowrank_plus_sparse(120, 110, 4, factor_std=0.05, sparsity=0.1, values="pm1",
+                                         seed=14).M.copy()
+        Mblk[17, 33] = np.nan
+    with pytest.raises(R.RpcaError) as ei:
+        _seed_block(R, ctx, Mblk, 4, 2)
+    want = R.RPCA_ERR_SEED if case == "zero" else R.RPCA_ERR_NUMERIC
+    say(f"SEED error path {case}: {ei.value}")
+    assert ei.value.status == want
