@@ -133,7 +133,15 @@ typedef struct {
     double t_filter_ms;          /* device time of steps 3 + 4 (with overlap_chunks > 0:    */
                                  /* of steps 3-5, which then share the chip)                */
     double t_reconstruct_ms;     /* device time of step 5 (0 with overlap_chunks > 0)       */
+    int32_t seed_route;          /* how the seed's SVT ran: RPCA_SEED_ROUTE_*               */
 } rpca_info;
+
+/* Routes of the seed solver (rpca_info.seed_route, rpca_last_seed_route). */
+#define RPCA_SEED_ROUTE_EIGEN 1        /* Gram matrix + rocSOLVER eigen-decomposition     */
+#define RPCA_SEED_ROUTE_SUBSPACE 2     /* device-resident subspace iteration, completed   */
+#define RPCA_SEED_ROUTE_LDS_JACOBI 3   /* device-resident Jacobi SVD in LDS               */
+#define RPCA_SEED_ROUTE_FELL_BACK 4    /* the subspace iteration needed more directions   */
+                                       /* than it holds; the eigen route finished         */
 
 /* Which filter kernel a call with these options takes for `nreg`
  * regressions of p elements and rank r (nreg: all regressions of the call,
@@ -194,6 +202,10 @@ int rpca_seed(rpca_ctx_t ctx, const float *M, int64_t m, int64_t n, int64_t ldm,
               const int64_t *seed_rows, int64_t p, const int64_t *seed_cols, int64_t q,
               int32_t r, const rpca_opts *opts, double *U, double *sigma, double *V,
               int32_t *r_used, int32_t *seed_iters);
+
+/* Route the last rpca_seed call on ctx took (RPCA_SEED_ROUTE_*; 0 before the
+ * first).  Host only.  Errors: RPCA_ERR_ARG (null ctx or route). */
+int rpca_last_seed_route(rpca_ctx_t ctx, int32_t *route);
 
 /*
  * Step 3 (Sec. 3.2, eq. l1c'; Algorithm 1): for each k < nc, with j = cols[k],

@@ -320,9 +320,17 @@ int rpca_seed(rpca_ctx_t ctx, const float *M, int64_t m, int64_t n, int64_t ldm,
     if ((st = check_sorted_indices(ctx, seed_cols, q, n, "seed_cols", nullptr)) != RPCA_OK) return st;
     SeedOut so;
     st = run_seed(ctx, M, ldm, seed_rows, p, seed_cols, q, r, *opts, U, sigma, V, &so, nullptr);
+    ctx->last_seed_route = so.route;
     if (r_used) *r_used = so.r_used;
     if (seed_iters) *seed_iters = so.iters;
     return st;
+}
+
+int rpca_last_seed_route(rpca_ctx_t ctx, int32_t *route)
+{
+    if (!ctx || !route) return ctx ? set_status(ctx, RPCA_ERR_ARG, "last_seed_route: null route") : RPCA_ERR_ARG;
+    *route = ctx->last_seed_route;
+    return set_status(ctx, RPCA_OK, "");
 }
 
 static int make_side(rpca_ctx_t ctx, const float *M, int64_t m, int64_t n, int64_t ldm,
@@ -676,6 +684,7 @@ int rpca_solve(rpca_ctx_t ctx, const float *M, int64_t m, int64_t n, int64_t ldm
         info->r_used = ru;
         info->seed_iters = so.iters;
         info->seed_converged = so.converged;
+        info->seed_route = so.route;
         info->filt_iters_max = kmax;
         info->filt_iters_total = total;
         info->filt_not_converged = bad;
@@ -764,6 +773,7 @@ int rpca_solve_factored(rpca_ctx_t ctx, const float *M, int64_t m, int64_t n, in
         info->r_used = ru;
         info->seed_iters = so.iters;
         info->seed_converged = so.converged;
+        info->seed_route = so.route;
         info->filt_iters_max = is.max;
         info->filt_iters_total = is.total;
         info->filt_not_converged = is.not_converged;

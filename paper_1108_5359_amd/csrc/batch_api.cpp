@@ -557,7 +557,7 @@ int rpca_batch_seed(rpca_batch_t b, hipStream_t stream)
             if ((st = note(small[k], sts[k], what)) != RPCA_OK) return st;
         }
     }
-    std::vector<char> done(b->jobs.size(), 0);
+    std::vector<char> done(b->jobs.size(), 0), fell_back(b->jobs.size(), 0);
     for (size_t j : small) done[j] = 1;
     // larger blocks (up to 512 x 512): one launch of the device-resident
     // subspace-iteration solver, one workgroup each.  Every such block takes
@@ -585,7 +585,10 @@ int rpca_batch_seed(rpca_batch_t b, hipStream_t stream)
         const double ms =
             std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
         for (size_t k = 0; k < large.size(); ++k) {
-            if (outs[k].fallback) continue;          // taken again by the route below
+            if (outs[k].fallback) {                  // taken again by the route below
+                fell_back[large[k]] = 1;
+                continue;
+            }
             BatchJobState &S = b->js[large[k]];
             S.so = outs[k];
             S.seed_status = seed_status_message(ctx, sts[k], outs[k], b->jobs[large[k]].r);
@@ -605,6 +608,7 @@ int rpca_batch_seed(rpca_batch_t b, hipStream_t stream)
         S.so = SeedOut{};
         S.seed_status = run_seed(ctx, J.M, J.ldm, J.seed_rows, J.p, J.seed_cols, J.q, J.r, eig,
                                  dU(j), dsig(j), dV(j), &S.so, b->bs);
+        if (fell_back[j]) S.so.route = RPCA_SEED_ROUTE_FELL_BACK;
         S.t_seed_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
         int st = note(j, S.seed_status, ctx->last_error);
         if (st != RPCA_OK) return st;
@@ -696,6 +700,7 @@ int rpca_batch_job_info(rpca_batch_t b, int64_t job, rpca_info *info)
     info->r_used = S.so.r_used;
     info->seed_iters = S.so.iters;
     info->seed_converged = S.so.converged;
+    info->seed_route = S.so.route;
     info->filt_iters_max = kmax;
     info->filt_iters_total = total;
     info->filt_not_converged = bad;

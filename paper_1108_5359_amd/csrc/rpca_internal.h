@@ -18,6 +18,7 @@ struct DevBuf {
 
 struct rpca_ctx {
     int device = 0;
+    int32_t last_seed_route = 0;    // route of the last rpca_seed call (RPCA_SEED_ROUTE_*)
     hipStream_t aux = nullptr;      // second stream of the overlapped form (created on first use)
     hipEvent_t pev[40] = {};        // its events
     int num_cu = 0;
@@ -177,6 +178,7 @@ struct SeedOut {
     int32_t rank_found = 0;
     int32_t ritz_steps = 0;      // device-resident route: Rayleigh-Ritz steps in all
     int32_t fallback = 0;        // device-resident route: 1 = the subspace would exceed its cap
+    int32_t route = 0;           // RPCA_SEED_ROUTE_*
 };
 
 int run_seed(rpca_ctx *ctx, const float *M, int64_t ldm, const int64_t *seed_rows, int64_t p,

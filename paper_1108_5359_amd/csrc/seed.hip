@@ -195,6 +195,7 @@ int run_seed(rpca_ctx *ctx, const float *M, int64_t ldm, const int64_t *seed_row
     // faster, the subspace route pays off when a batch runs many blocks in
     // one launch); else, or when the subspace iteration needs more
     // directions than it holds, the eigen-decomposition route.
+    bool fell_back = false;
     if (o.seed_route != 1) {
         const bool small = p * q <= 6400 && seed_small_fits(ctx, p, q);
         const bool large = !small && o.seed_route == 2 && seed_large_fits(ctx, p, q);
@@ -212,6 +213,7 @@ int run_seed(rpca_ctx *ctx, const float *M, int64_t ldm, const int64_t *seed_row
                 *out = so;
                 return seed_status_message(ctx, sst, so, r);
             }
+            fell_back = true;
         }
     }
     const int64_t len = p * q;
@@ -352,6 +354,7 @@ int run_seed(rpca_ctx *ctx, const float *M, int64_t ldm, const int64_t *seed_row
     out->converged = converged ? 1 : 0;
     out->rank_found = rank;
     out->r_used = keep;
+    out->route = fell_back ? RPCA_SEED_ROUTE_FELL_BACK : RPCA_SEED_ROUTE_EIGEN;
     if (rank == 0) return set_status(ctx, RPCA_ERR_SEED, "seed: the recovered seed has rank 0");
     if (rank != r)
         return set_status(ctx, RPCA_WARN_RANK,

@@ -663,6 +663,7 @@ int run_seed_large(rpca_ctx *ctx, const SmallSeedArgs *args, int n, const rpca_o
         outs[k].rank_found = hr[8 * k + 4];
         outs[k].ritz_steps = hr[8 * k + 5];
         outs[k].fallback = hr[8 * k + 6];
+        outs[k].route = outs[k].fallback ? RPCA_SEED_ROUTE_FELL_BACK : RPCA_SEED_ROUTE_SUBSPACE;
     }
     return RPCA_OK;
 }

@@ -326,6 +326,7 @@ int run_seed_small(rpca_ctx *ctx, const SmallSeedArgs *args, int n, const rpca_o
         outs[k].iters = hr[8 * k + 2];
         outs[k].converged = hr[8 * k + 3];
         outs[k].rank_found = hr[8 * k + 4];
+        outs[k].route = RPCA_SEED_ROUTE_LDS_JACOBI;
     }
     return RPCA_OK;
 }

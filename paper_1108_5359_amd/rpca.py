@@ -30,6 +30,10 @@ RPCA_ERR_NOMEM = -2
 RPCA_ERR_DEVICE = -3
 RPCA_ERR_SEED = -4
 RPCA_ERR_NUMERIC = -5
+RPCA_SEED_ROUTE_EIGEN = 1
+RPCA_SEED_ROUTE_SUBSPACE = 2
+RPCA_SEED_ROUTE_LDS_JACOBI = 3
+RPCA_SEED_ROUTE_FELL_BACK = 4
 RPCA_ERR_UNSUPPORTED = -6
 RPCA_ITERS_BAD_INDEX = -2147483648
 RPCA_ITERS_NONFINITE = -2147483647
@@ -57,7 +61,7 @@ class rpca_info(ctypes.Structure):
         ("seed_converged", ctypes.c_int32), ("filt_iters_max", ctypes.c_int32),
         ("filt_iters_total", ctypes.c_int64), ("filt_not_converged", ctypes.c_int64),
         ("t_seed_ms", ctypes.c_double), ("t_filter_ms", ctypes.c_double),
-        ("t_reconstruct_ms", ctypes.c_double),
+        ("t_reconstruct_ms", ctypes.c_double), ("seed_route", ctypes.c_int32),
     ]
 
     def as_dict(self):
@@ -78,6 +82,7 @@ lib.rpca_status_string.argtypes = [ctypes.c_int]
 lib.rpca_status_string.restype = ctypes.c_char_p
 lib.rpca_sample_indices.argtypes = [_i64, _i64, _i64, _i64, ctypes.c_uint64, _vp, _vp]
 lib.rpca_filter_form.argtypes = [_vp, _i64, _i32, _i64, ctypes.POINTER(rpca_opts), ctypes.POINTER(_i32)]
+lib.rpca_last_seed_route.argtypes = [_vp, ctypes.POINTER(_i32)]
 lib.rpca_seed.argtypes = [_vp, _vp, _i64, _i64, _i64, _vp, _i64, _vp, _i64, _i32,
                           ctypes.POINTER(rpca_opts), _vp, _vp, _vp,
                           ctypes.POINTER(_i32), ctypes.POINTER(_i32)]
@@ -190,6 +195,13 @@ def rpca_seed(ctx: Context, M, m, n, ldm, seed_rows, p, seed_cols, q, r, opts, U
                                  _ptr(seed_cols), q, r, ctypes.byref(opts), _ptr(U), _ptr(sigma),
                                  _ptr(V), ctypes.byref(ru), ctypes.byref(it)))
     return st, ru.value, it.value
+
+
+def rpca_last_seed_route(ctx: Context) -> int:
+    """Route the last rpca_seed call on ctx took (RPCA_SEED_ROUTE_*)."""
+    route = _i32(0)
+    ctx.check(lib.rpca_last_seed_route(ctx.handle, ctypes.byref(route)))
+    return route.value
 
 
 def rpca_filter_form(ctx: Context, p: int, r: int, nreg: int, opts) -> int:

@@ -12,7 +12,15 @@ LAPACK SVD in each step:
 
 Compared: the rank, the ALM step count (within one step) and L^s = U Sigma V^T
 (relative Frobenius; never the factors themselves, which are defined up to
-sign).  On blocks whose PCP recovers L^s the subspace route agrees with the
+sign), and the route the library reports it took: the subspace solver holds
+at most 72 directions, so it completes where the iterate never keeps more
+than 64 singular values above the threshold and otherwise reports a
+fallback to the eigen route.  The first ALM step, whose input is a multiple
+of M^s (S_0 = 0, Y_0 proportional to M^s), keeps every singular value above
+about 0.44 sigma_1 (69 of the 200 x 200 block's, 107 of the 500 x 500 one's)
+and the later ones at most about the final rank, so the larger of the two
+decides.  Ritz values never exceed the singular values they approximate, so
+a peak of 64 or less never falls back; one of 68 or more does.  On blocks whose PCP recovers L^s the subspace route agrees with the
 oracle to rounding (1e-9 asserted); the eigen route squares the spectrum and
 is held to 1e-7.  Seed times are printed (``SEED`` lines).
 """
@@ -66,6 +74,28 @@ def block(name):
     return pr, r, sd
 
 
+def first_svt_rank(M):
+    """Singular values above the threshold in the first ALM step of the seed
+    PCP (S_0 = 0, Y_0 = M / max(||M||_2, ||M||_inf / lam), tau = 1 / mu_0)."""
+    M = np.asarray(M, dtype=np.float64)
+    lam = 1.0 / np.sqrt(max(M.shape))
+    s = np.linalg.svd(M, compute_uv=False)
+    mu0 = 1.25 / s[0]
+    y0 = 1.0 / max(s[0], np.abs(M).max() / lam)
+    return int(np.sum(s * (1.0 + y0 / mu0) > 1.0 / mu0))
+
+
+def expected_route(R, M, route, final_rank):
+    """The route rpca_seed should report; None where either is right (a
+    peak rank of 65 to 67, where convergence order decides)."""
+    if route == 1:
+        return R.RPCA_SEED_ROUTE_EIGEN
+    peak = max(first_svt_rank(M), final_rank)
+    if peak <= 64:
+        return R.RPCA_SEED_ROUTE_SUBSPACE
+    return R.RPCA_SEED_ROUTE_FELL_BACK if peak >= 68 else None
+
+
 def _seed(R, ctx, pr, r, route):
     import torch
     p, q = pr.m, pr.n
@@ -90,13 +120,17 @@ def test_seed_route_matches_oracle(R, ctx, name, route):
     Ls_ref = (sd.U[:, :k] * sd.sigma[:k]) @ sd.V[:, :k].T
     _seed(R, ctx, pr, r, route)                                   # warm-up (code objects, workspace)
     st, ru, its, Ls, Uh, sh, ms = _seed(R, ctx, pr, r, route)
+    taken = R.rpca_last_seed_route(ctx)
     e = relF(Ls, Ls_ref)
     say(f"SEED {name} route={route} p={pr.m} q={pr.n} status={R.rpca_status_string(st)} rank={ru}/"
-        f"{sd.rank} iters={its}/{sd.iters} relF(L^s)={e:.2e} t={ms:.1f} ms")
+        f"{sd.rank} iters={its}/{sd.iters} relF(L^s)={e:.2e} t={ms:.1f} ms taken={taken} "
+        f"first-step rank={first_svt_rank(pr.M)}")
+    want = expected_route(R, pr.M, route, sd.rank)
+    assert want is None or taken == want
     assert st >= 0
     assert ru == k
     assert abs(its - sd.iters) <= 1
-    assert e <= (1e-9 if route == 2 else 1e-7)
+    assert e <= (1e-9 if taken == R.RPCA_SEED_ROUTE_SUBSPACE else 1e-7)
     assert np.allclose(Uh[:, :k].T @ Uh[:, :k], np.eye(k), atol=1e-10)
     assert np.all(np.diff(sh[:k]) <= 0) and np.all(sh[k:] == 0)
 
@@ -132,19 +166,24 @@ def test_batched_seeds_of_several_sizes(R, ctx):
         V = torch.zeros((r, q), dtype=torch.float64, device="cuda")
         R.rpca_batch_job_factors(b, k, U, sg, V)
         st, info = R.rpca_batch_job_info(b, k)
+        Ms = pr.M[np.ix_(I, J)]
+        want = (R.RPCA_SEED_ROUTE_LDS_JACOBI if p * q <= 6400
+                else expected_route(R, Ms, 2, sd.rank))
         kk = min(sd.rank, r)
         Ls = (U.cpu().numpy().T * sg.cpu().numpy()) @ V.cpu().numpy()
         Ls_ref = (sd.U[:, :kk] * sd.sigma[:kk]) @ sd.V[:, :kk].T
         e = relF(Ls, Ls_ref)
         say(f"SEED batch job {k} p={p} q={q} rank={info.r_used}/{sd.rank} iters={info.seed_iters}/"
-            f"{sd.iters} relF(L^s)={e:.2e}")
+            f"{sd.iters} relF(L^s)={e:.2e} route={info.seed_route} first-step rank={first_svt_rank(Ms)}")
         assert info.r_used == kk and abs(info.seed_iters - sd.iters) <= 1
-        assert e <= 1e-9
+        assert want is None or info.seed_route == want
+        assert e <= (1e-7 if info.seed_route == R.RPCA_SEED_ROUTE_FELL_BACK else 1e-9)
     b.close()
 
 
 def _seed_block(R, ctx, Mblk, r, route):
-    """rpca_seed on the whole block (identity seed indices); L^s and factors."""
+    """rpca_seed on the whole block (identity seed indices); status, rank,
+    iterations, L^s."""
     import torch
     p, q = Mblk.shape
     Md = dev_matrix(np.asfortranarray(Mblk.astype(np.float32)))
@@ -154,16 +193,18 @@ def _seed_block(R, ctx, Mblk, r, route):
     st, ru, its = R.rpca_seed(ctx, Md, p, q, p, dev_i64(np.arange(p)), p, dev_i64(np.arange(q)), q, r,
                               R.rpca_opts_default(seed_route=route), U, sg, V)
     Uh, sh, Vh = U.cpu().numpy().T, sg.cpu().numpy(), V.cpu().numpy().T
-    return st, ru, its, (Uh * sh) @ Vh.T
+    return st, ru, its, (Uh * sh) @ Vh.T, R.rpca_last_seed_route(ctx)
 
 
-def _against_oracle(name, Mblk, st, ru, its, Ls, r, tol):
+def _against_oracle(R, name, Mblk, st, ru, its, Ls, taken, r, tol):
     sd = oracle.seed_pcp(Mblk.astype(np.float32).astype(np.float64))
+    want = expected_route(R, Mblk, 2, sd.rank)
     k = min(sd.rank, r)
     Ls_ref = (sd.U[:, :k] * sd.sigma[:k]) @ sd.V[:, :k].T
     e = relF(Ls, Ls_ref)
     say(f"SEED {name} p={Mblk.shape[0]} q={Mblk.shape[1]} rank={ru}/{sd.rank} iters={its}/{sd.iters} "
-        f"relF(L^s)={e:.2e}")
+        f"relF(L^s)={e:.2e} route={taken}")
+    assert want is None or taken == want
     assert st >= 0 and ru == k and abs(its - sd.iters) <= 1
     assert e <= tol
 
@@ -173,9 +214,9 @@ def test_subspace_route_falls_back_past_its_widest_basis(R, ctx):
     # more than the 72 directions the subspace solver holds, so it reports a
     # fallback and the eigen route finishes (held to that route's 1e-7).
     pr = synth.lowrank_plus_sparse(200, 200, 90, factor_std=0.1, sparsity=0.02, values="pm1", seed=11)
-    st, ru, its, Ls = _seed_block(R, ctx, pr.M, 120, 2)
-    _against_oracle("fallback_rank90", pr.M, st, ru, its, Ls, 120, 1e-7)
-    assert ru > 64
+    st, ru, its, Ls, taken = _seed_block(R, ctx, pr.M, 120, 2)
+    _against_oracle(R, "fallback_rank90", pr.M, st, ru, its, Ls, taken, 120, 1e-7)
+    assert ru > 64 and taken == R.RPCA_SEED_ROUTE_FELL_BACK
 
 
 @pytest.mark.parametrize("shape", [(512, 81), (81, 512)])
@@ -183,15 +224,15 @@ def test_subspace_route_at_its_size_limits(R, ctx, shape):
     p, q = shape
     pr = synth.lowrank_plus_sparse(p, q, 8, factor_std=np.sqrt(1.0 / 5000), sparsity=0.08, values="pm1",
                                    seed=12 + p)
-    st, ru, its, Ls = _seed_block(R, ctx, pr.M, 8, 2)
-    _against_oracle(f"limit_{p}x{q}", pr.M, st, ru, its, Ls, 8, 1e-9)
+    st, ru, its, Ls, taken = _seed_block(R, ctx, pr.M, 8, 2)
+    _against_oracle(R, f"limit_{p}x{q}", pr.M, st, ru, its, Ls, taken, 8, 1e-9)
 
 
 def test_subspace_route_rank_one(R, ctx):
     # the basis starts 16 wide for a rank-1 block
     pr = synth.lowrank_plus_sparse(120, 150, 1, factor_std=0.05, sparsity=0.1, values="pm1", seed=13)
-    st, ru, its, Ls = _seed_block(R, ctx, pr.M, 1, 2)
-    _against_oracle("rank1_120x150", pr.M, st, ru, its, Ls, 1, 1e-9)
+    st, ru, its, Ls, taken = _seed_block(R, ctx, pr.M, 1, 2)
+    _against_oracle(R, "rank1_120x150", pr.M, st, ru, its, Ls, taken, 1, 1e-9)
 
 
 @pytest.mark.parametrize("case", ["zero", "nan"])
