@@ -3,10 +3,12 @@
 #include "rpca_internal.h"
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <cmath>
 #include <numeric>
 #include <string>
+#include <thread>
 #include <vector>
 
 namespace {
@@ -70,6 +72,9 @@ struct BatchJobState {
     double t_seed_ms = 0;
 };
 
+// eigen-route seed blocks of one batch that run side by side (helper contexts)
+constexpr int kSeedHelpers = 4;
+
 struct rpca_batch {
     rpca_ctx *ctx = nullptr;       // owner context (seed solver, BLAS handle)
     rpca_ctx *wctx = nullptr;      // the batch's own workspace for tile-form / large-rank launches
@@ -87,6 +92,8 @@ struct rpca_batch {
     hipGraph_t graph[2] = {nullptr, nullptr};
     hipGraphExec_t exec[2] = {nullptr, nullptr};
     hipEvent_t ev[5] = {};
+    std::vector<rpca_ctx *> helpers;      // contexts of the eigen-route seeds run side by side
+    std::vector<hipStream_t> hstreams;    // and their streams
     std::vector<FilterSide> tile_sides;   // sides in the tile form (one launch each)
     std::vector<ReconArgs> single_recon;  // completions with R4 > 8 (one launch each)
 
@@ -597,20 +604,61 @@ int rpca_batch_seed(rpca_batch_t b, hipStream_t stream)
             if ((st = note(large[k], S.seed_status, ctx->last_error)) != RPCA_OK) return st;
         }
     }
-    // the others one at a time (eigen-decomposition route)
+    // the others on the eigen-decomposition route.  It synchronises with the
+    // host at every ALM step and leaves most of the chip idle, so up to
+    // kSeedHelpers blocks run side by side, each on a helper context of its
+    // own (BLAS handle, workspace, stream) made once per batch object; a
+    // block's result does not depend on the helper that runs it.
     rpca_opts eig = b->opts;
     eig.seed_route = 1;
-    for (size_t j = 0; j < b->jobs.size(); ++j) {
-        if (done[j]) continue;
+    std::vector<size_t> rest;
+    for (size_t j = 0; j < b->jobs.size(); ++j)
+        if (!done[j]) rest.push_back(j);
+    const size_t want = std::min(rest.size(), (size_t)kSeedHelpers);
+    while (want >= 2 && b->helpers.size() < want) {
+        rpca_ctx *h = nullptr;
+        hipStream_t hs = nullptr;
+        if (rpca_ctx_create(ctx->device, &h) != RPCA_OK) break;
+        if (hipStreamCreateWithFlags(&hs, hipStreamNonBlocking) != hipSuccess) {
+            rpca_ctx_destroy(h);
+            break;
+        }
+        b->helpers.push_back(h);
+        b->hstreams.push_back(hs);
+    }
+    const size_t nh = want >= 2 ? std::min(want, b->helpers.size()) : 0;
+    std::vector<std::string> msgs(rest.size());
+    auto one = [&](size_t i, rpca_ctx *c, hipStream_t sm) {
+        const size_t j = rest[i];
         const rpca_job &J = b->jobs[j];
         BatchJobState &S = b->js[j];
         const auto t0 = std::chrono::steady_clock::now();
         S.so = SeedOut{};
-        S.seed_status = run_seed(ctx, J.M, J.ldm, J.seed_rows, J.p, J.seed_cols, J.q, J.r, eig,
-                                 dU(j), dsig(j), dV(j), &S.so, b->bs);
+        S.seed_status = run_seed(c, J.M, J.ldm, J.seed_rows, J.p, J.seed_cols, J.q, J.r, eig, dU(j),
+                                 dsig(j), dV(j), &S.so, sm);
         if (fell_back[j]) S.so.route = RPCA_SEED_ROUTE_FELL_BACK;
         S.t_seed_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
-        int st = note(j, S.seed_status, ctx->last_error);
+        msgs[i] = c->last_error;
+    };
+    if (nh >= 2) {
+        // the helpers' streams do not wait on the batch's: everything queued
+        // there (the inputs' ordering, the launches above) is finished first
+        RPCA_HIP_TRY(ctx, hipStreamSynchronize(b->bs));
+        std::atomic<size_t> next{0};
+        auto work = [&](size_t h) {
+            (void)hipSetDevice(ctx->device);
+            for (size_t i; (i = next.fetch_add(1)) < rest.size();) one(i, b->helpers[h], b->hstreams[h]);
+            (void)hipStreamSynchronize(b->hstreams[h]);
+        };
+        std::vector<std::thread> threads;
+        for (size_t h = 1; h < nh; ++h) threads.emplace_back(work, h);
+        work(0);
+        for (auto &t : threads) t.join();
+    } else {
+        for (size_t i = 0; i < rest.size(); ++i) one(i, ctx, b->bs);
+    }
+    for (size_t i = 0; i < rest.size(); ++i) {
+        int st = note(rest[i], b->js[rest[i]].seed_status, msgs[i]);
         if (st != RPCA_OK) return st;
     }
     RPCA_HIP_TRY(ctx, hipStreamSynchronize(b->bs));
@@ -752,6 +800,11 @@ int rpca_batch_destroy(rpca_batch_t b)
     }
     for (auto &e : b->ev)
         if (e) (void)hipEventDestroy(e);
+    for (size_t h = 0; h < b->helpers.size(); ++h) {
+        (void)hipStreamSynchronize(b->hstreams[h]);
+        (void)hipStreamDestroy(b->hstreams[h]);
+        rpca_ctx_destroy(b->helpers[h]);
+    }
     if (b->bs) (void)hipStreamDestroy(b->bs);
     delete b;
     return RPCA_OK;

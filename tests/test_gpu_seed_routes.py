@@ -247,3 +247,56 @@ def test_subspace_route_error_paths(R, ctx, case):
     want = R.RPCA_ERR_SEED if case == "zero" else R.RPCA_ERR_NUMERIC
     say(f"SEED error path {case}: {ei.value}")
     assert ei.value.status == want
+
+
+def test_batched_eigen_route_seeds_side_by_side(R, ctx):
+    # Four 120 x 120 seed blocks with seed_route = 1: all take the eigen route,
+    # which a batch runs on helper contexts side by side.  Each job against
+    # the oracle, and bit for bit against the same job alone in a batch (one
+    # block: no helpers), so the result does not depend on the batch.
+    import torch
+    specs = [(1200, 1000, 12, 120, 120, 60 + k) for k in range(4)]
+    built = []
+    for m, n, r, p, q, sd_seed in specs:
+        pr = synth.lowrank_plus_sparse(m, n, r, factor_std=np.sqrt(1.0 / max(m, n)), sparsity=0.1,
+                                       values="pm1", seed=sd_seed)
+        I, J = synth.seed_indices(m, n, p, q, seed=sd_seed)
+        Md = dev_matrix(pr.M)
+        built.append((pr, I, J, r, Md, dev_i64(I), dev_i64(J)))
+    opts = R.rpca_opts_default(seed_route=1)
+
+    def run(items):
+        keep, jobs = [], []
+        for pr, I, J, r, Md, dI, dJ in items:
+            L = torch.empty_like(Md)
+            S = torch.empty_like(Md)
+            keep.append((L, S))
+            jobs.append(R.job(Md, pr.m, pr.n, pr.m, r, dI, len(I), dJ, len(J), L, pr.m, S, pr.m))
+        b = R.Batch(ctx, jobs, opts)
+        R.rpca_batch_seed(b)
+        out = []
+        for k, (pr, I, J, r, Md, dI, dJ) in enumerate(items):
+            U = torch.zeros((r, len(I)), dtype=torch.float64, device="cuda")
+            sg = torch.zeros(r, dtype=torch.float64, device="cuda")
+            V = torch.zeros((r, len(J)), dtype=torch.float64, device="cuda")
+            R.rpca_batch_job_factors(b, k, U, sg, V)
+            st, info = R.rpca_batch_job_info(b, k)
+            out.append((U.cpu().numpy(), sg.cpu().numpy(), V.cpu().numpy(), info.seed_route, info.r_used,
+                        info.seed_iters))
+        b.close()
+        return out
+
+    together = run(built)
+    for k, (pr, I, J, r, Md, dI, dJ) in enumerate(built):
+        Uh, sh, Vh, route, ru, its = together[k]
+        sd = oracle.seed_pcp(pr.M[np.ix_(I, J)].astype(np.float64))
+        kk = min(sd.rank, r)
+        Ls = (Uh.T * sh) @ Vh
+        Ls_ref = (sd.U[:, :kk] * sd.sigma[:kk]) @ sd.V[:, :kk].T
+        e = relF(Ls, Ls_ref)
+        say(f"SEED eigen side by side job {k}: rank={ru}/{sd.rank} iters={its}/{sd.iters} relF(L^s)={e:.2e} "
+            f"route={route}")
+        assert route == R.RPCA_SEED_ROUTE_EIGEN
+        assert ru == kk and abs(its - sd.iters) <= 1 and e <= 1e-7
+        alone = run([built[k]])[0]
+        assert np.array_equal(alone[0], Uh) and np.array_equal(alone[1], sh) and np.array_equal(alone[2], Vh)
