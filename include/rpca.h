@@ -108,7 +108,9 @@ typedef struct {
                                  /* waves per 16 regressions, each wave a quarter of the   */
                                  /* elements) where built for the class, else the tile     */
                                  /* form.  Results agree within rounding, not bit for bit. */
-                                 /* (0)                                                    */
+                                 /* Beyond p = 304 the FP32 filter is the quarter-tile    */
+                                 /* form (four waves per 16 regressions, a workgroup per   */
+                                 /* CU), whatever this says. (0)                           */
     int32_t seed_route;          /* FP64 SVD inside the seed solver: 0 = automatic (blocks  */
                                  /* of up to 6400 entries: Jacobi SVD in LDS; blocks up to */
                                  /* 512 x 512 of a batch: one launch of the device-resident*/
@@ -146,7 +148,8 @@ typedef struct {
 /* Which filter kernel a call with these options takes for `nreg`
  * regressions of p elements and rank r (nreg: all regressions of the call,
  * both families): *form = 0 FP16 contractions (precision form), 1 FP32 tile
- * form, 2 FP32 split form (see filter_form).  Host only; launches nothing.
+ * form, 2 FP32 split form (see filter_form), 3 FP32 quarter-tile form (p > 304).
+ * Host only; launches nothing.
  * Errors: RPCA_ERR_ARG (null pointer, bad options, p < 1, r < 1, nreg < 0). */
 int rpca_filter_form(rpca_ctx_t ctx, int64_t p, int32_t r, int64_t nreg, const rpca_opts *opts,
                      int32_t *form);
@@ -221,7 +224,7 @@ int rpca_last_seed_route(rpca_ctx_t ctx, int32_t *route);
  *              column holding Inf or NaN, RPCA_ITERS_BAD_INDEX for an index
  *              outside M.
  * Asynchronous on `stream`.  Returns RPCA_ERR_UNSUPPORTED for p or r beyond
- * the built kernel classes (p <= 304, r <= 64 with p*r bounded by LDS).
+ * the built kernel classes (p <= 512, r <= 64).
  */
 int rpca_filter_cols(rpca_ctx_t ctx, const float *M, int64_t m, int64_t n, int64_t ldm,
                      const int64_t *seed_rows, int64_t p, const int64_t *cols, int64_t nc,

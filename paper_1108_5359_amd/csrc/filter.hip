@@ -35,11 +35,13 @@ int pick_from(const int *list, int count, int need)
     return -1;
 }
 
-int pick_pt(int p, int precision)
-{
-    return precision == 1 ? pick_from(kPTh, kNumPTh, (p + 15) / 16)
-                          : pick_from(kPT, kNumPT, (p + 15) / 16);
-}
+// Both forms share the tile classes up to PT = 19; beyond, the FP32 form
+// takes the quarter-tile shape too (FP32 contractions).
+int pick_pt(int p, int /*precision*/) { return pick_from(kPTh, kNumPTh, (p + 15) / 16); }
+
+// The quarter-tile shape serves the precision form from PT = 19 and the FP32
+// form beyond the FP32 tile classes.
+bool quarter_form(int PT, int precision) { return half_form(PT) && (precision == 1 || PT > 19); }
 int pick_ks(int r) { return pick_from(kKS, kNumKS, (r + 3) / 4); }
 
 size_t lds_limit(rpca_ctx *ctx) { return ctx->max_lds ? ctx->max_lds : 65536; }
@@ -75,13 +77,14 @@ bool filter_supported(rpca_ctx *ctx, int p, int r, int precision)
     if (PT < 0 || KS < 0) return false;
     if (precision == 1)
         return (half_form(PT) ? lds_bytes_f16q(PT, KS, 1) : lds_bytes_f16(PT, KS, false)) <= lds_limit(ctx);
-    return lds_bytes(PT, KS) <= lds_limit(ctx);
+    return (quarter_form(PT, 0) ? lds_bytes_q32(PT, KS, 1) : lds_bytes(PT, KS)) <= lds_limit(ctx);
 }
 
 int filter_form_of(rpca_ctx *ctx, int p, int r, int precision, int form, int64_t regs)
 {
     if (precision == 1 && p >= kMinPHalf) return 0;
     const int PT = pick_pt(p, 0), KS = pick_ks(r);
+    if (PT >= 0 && quarter_form(PT, 0)) return 3;
     if (PT < 0 || KS < 0 || form == 1 || !split_built(PT, KS)) return 1;
     if (form == 2) return 2;
     return choose_split(PT, KS, (regs + 15) / 16, ctx->num_cu) ? 2 : 1;
@@ -89,8 +92,7 @@ int filter_form_of(rpca_ctx *ctx, int p, int r, int precision, int form, int64_t
 
 bool filter_same_class(int p0, int r0, int p1, int r1)
 {
-    // the tile lists of both modes agree up to p = 304; beyond, the second
-    // family simply launches on its own
+    // one class list serves both modes
     return pick_pt(p0, 1) == pick_pt(p1, 1) && pick_ks(r0) == pick_ks(r1);
 }
 
@@ -143,8 +145,10 @@ int launch_filter(rpca_ctx *ctx, const FilterSide *sides, int nsides, const Filt
         int st = ensure_buf(ctx, ctx->xbuf_ws, xtotal * sizeof(float));
         if (st != RPCA_OK) return st;
     }
-    if (c.precision == 1 && (half_form(PT) || lds_bytes_f16(PT, KS, true) > lds_limit(ctx))) {
-        // FP32 refresh fragments do not fit next to the FP16 ones: build them in HBM
+    const bool quarter = quarter_form(PT, c.precision);
+    if (quarter || (c.precision == 1 && lds_bytes_f16(PT, KS, true) > lds_limit(ctx))) {
+        // FP32 refresh fragments (and, in the FP32 quarter-tile form, those of
+        // v = A w) do not fit next to the staged ones: build them in HBM
         const int RT = (KS + 3) / 4;
         const size_t per = (size_t)PT * RT * 256;
         int st = ensure_buf(ctx, ctx->frag_ws, per * nsides * sizeof(float));
@@ -159,9 +163,11 @@ int launch_filter(rpca_ctx *ctx, const FilterSide *sides, int nsides, const Filt
         if (nsides == 1) L.frag32[1] = L.frag32[0];
     }
     // FP32 kernel form: the caller's choice, else from the tile count of the
-    // whole call (plan_regs) or of this launch
+    // whole call (plan_regs) or of this launch; beyond the tile classes always
+    // the quarter-tile form (its grid is sized for it below), also where a
+    // split class is built (PT 26, 32 at r <= 16)
     bool split = false;
-    if (c.precision == 0 && c.form != 1 && split_built(PT, KS)) {
+    if (c.precision == 0 && c.form != 1 && split_built(PT, KS) && !quarter) {
         if (c.form == 2) {
             split = true;
         } else {
@@ -172,12 +178,12 @@ int launch_filter(rpca_ctx *ctx, const FilterSide *sides, int nsides, const Filt
             split = choose_split(PT, KS, tiles, ctx->num_cu);
         }
     }
-    // quarter-tile precision form: persistent, one workgroup per CU, the CUs
-    // shared between the sides in proportion to their tiles; two tiles per
-    // workgroup where their LDS fits and the element indices fit 32 bits
-    const bool quarter = c.precision == 1 && half_form(PT);
+    // quarter-tile forms: persistent, one workgroup per CU, the CUs shared
+    // between the sides in proportion to their tiles; two tiles per workgroup
+    // where their LDS fits and the element indices fit 32 bits
     L.qtiles = 1;
-    if (quarter && lds_bytes_f16q(PT, KS, 2) <= lds_limit(ctx)) {
+    const size_t lds2 = c.precision == 1 ? lds_bytes_f16q(PT, KS, 2) : lds_bytes_q32(PT, KS, 2);
+    if (quarter && lds2 <= lds_limit(ctx)) {
         bool fits = true;
         for (int s = 0; s < nsides; ++s) fits = fits && sides[s].elem_bound <= INT_MAX;
         if (fits) L.qtiles = 2;

@@ -1056,7 +1056,7 @@ l1_filter_kernel_f16(FilterLaunch L)
 }
 
 // ---------------------------------------------------------------------------
-// Precision form, quarter-tile persistent variant for large p (PT >= 19).  One
+// Quarter-tile persistent form for large p (PT >= 19).  One
 // wave holding all PT element tiles of its 16 regressions needs 8 PT floats of
 // u, y per lane (256 at p = 512: the whole register file, so the tile kernel
 // spills, and the basis fragments of a contraction cannot be kept in flight).
@@ -1072,8 +1072,21 @@ l1_filter_kernel_f16(FilterLaunch L)
 // a regression wherever it sits), and a second barrier frees the buffer.  The
 // stopping test of a step is taken one step later; a stopped regression only
 // stops moving z and u, and a finished tile next to a moving one steps on
-// frozen.  The refresh reads its FP32 fragments from HBM.
+// frozen.  The refresh reads its FP32 fragments from HBM.  The same shape
+// serves the FP32 form beyond the FP32 tile classes (p > 304): the basis is
+// staged in LDS as FP32 for w = A^T g, and v = A w reads the refresh
+// fragments, one element tile ahead of its 16x16x4 FP32 MFMAs.
 // ---------------------------------------------------------------------------
+// Fourth word of a raw buffer resource on gfx950 (32-bit data, no swizzle).
+constexpr int kBufWord3 = 0x00020000;
+
+// 16 bytes per lane through a buffer resource: byte offset voff (per lane)
+// plus soff (wave-uniform, an SGPR); both must stay inside the resource.
+__device__ __forceinline__ floatx4 buf_load4(__amdgpu_buffer_rsrc_t r, int voff, int soff)
+{
+    return __builtin_bit_cast(floatx4, __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, 0));
+}
+
 template <int PT, int KS>
 struct QuarterShape {
     static constexpr int RT = (KS + 3) / 4;
@@ -1103,9 +1116,24 @@ inline size_t lds_bytes_f16q(int PT, int KS, int TPB)
            (size_t)TPB * kWavesPerBlock * NV * 64 * sizeof(float);
 }
 
-template <int PT, int KS, int TPB>
+// The same workgroup shape with FP32 contractions (the plain form beyond the
+// FP32 tile classes): the basis in the w = A^T g order is staged in LDS as
+// FP32 (the tile kernel's first fragment order), and v = A w streams the
+// refresh fragments from HBM (L2), as the refresh does with z.
+inline size_t lds_bytes_q32(int PT, int KS, int TPB)
+{
+    const int RT = (KS + 3) / 4, PP = (PT + 1) / 2, NPP = (PP + 3) / 4, TA = 8 * NPP, NV = KS + 1;
+    return (size_t)PT * RT * 256 * sizeof(float) +
+           (size_t)TA * 16 * (TPB == 2 ? sizeof(int32_t) : sizeof(int64_t)) +
+           (size_t)TPB * kWavesPerBlock * NV * 64 * sizeof(float);
+}
+
+// H = true: FP16 contractions (h1, h2 in LDS; the precision form from
+// PT = 19).  H = false: FP32 contractions (a1 in LDS, v = A w from the refresh
+// fragments; the FP32 form beyond PT = 19).
+template <int PT, int KS, int TPB, bool H>
 __global__ void __launch_bounds__(TPB * kWavesPerBlock * 64)
-l1_filter_kernel_f16q(FilterLaunch L)
+l1_filter_kernel_quarter(FilterLaunch L)
 {
     using Sh = QuarterShape<PT, KS>;
     constexpr int RT = Sh::RT, RP = Sh::RP, NPP = Sh::NPP, PPA = Sh::PPA, TA = Sh::TA;
@@ -1117,7 +1145,9 @@ l1_filter_kernel_f16q(FilterLaunch L)
     extern __shared__ __align__(16) unsigned char lds_raw[];
     _Float16 *h1 = reinterpret_cast<_Float16 *>(lds_raw);              // [PPA][RT][64][8]
     _Float16 *h2 = h1 + PPA * RT * 512;                                  // [TA][RP][64][8]
-    EIdx *eoff = reinterpret_cast<EIdx *>(h2 + TA * RP * 512);          // [TA*16]
+    float *a1 = reinterpret_cast<float *>(lds_raw);                      // FP32: [PT][RT][64][4]
+    EIdx *eoff = H ? reinterpret_cast<EIdx *>(h2 + TA * RP * 512)       // [TA*16]
+                   : reinterpret_cast<EIdx *>(a1 + PT * RT * 256);
     float *xch = reinterpret_cast<float *>(eoff + TA * 16);              // [TPB][4 waves][NV][64]
 
     const bool second = (int)blockIdx.x >= L.nblocks0;
@@ -1148,21 +1178,33 @@ l1_filter_kernel_f16q(FilterLaunch L)
     if (jbeg + (int64_t)block_in_side * TPB * 16 >= jend) return;   // no tile for this block (before any barrier)
 
     // ---- stage the basis once (padded pairs and tiles are zero) -----------
-    for (int idx = threadIdx.x; idx < PPA * RT * 512; idx += NT) {
-        const int i = idx & 7, ln = (idx >> 3) & 63, pm = idx >> 9;
-        const int pp = pm / RT, mt = pm - pp * RT;
-        const int g = ln >> 4, c = ln & 15;
-        const int e = 16 * (2 * pp + (i >> 2)) + 4 * g + (i & 3);
-        const int k = 16 * mt + 4 * (c & 3) + (c >> 2);
-        h1[idx] = (_Float16)((e < p && k < r) ? A[e + (int64_t)k * lda] : 0.0);
-    }
-    for (int idx = threadIdx.x; idx < TA * RP * 512; idx += NT) {
-        const int i = idx & 7, ln = (idx >> 3) & 63, tr = idx >> 9;
-        const int t = tr / RP, rp = tr - t * RP;
-        const int g = ln >> 4, c = ln & 15;
-        const int e = 16 * t + c;
-        const int k = 16 * (2 * rp + (i >> 2)) + 4 * (i & 3) + g;
-        h2[idx] = (_Float16)((e < p && k < r) ? A[e + (int64_t)k * lda] : 0.0);
+    if constexpr (H) {
+        for (int idx = threadIdx.x; idx < PPA * RT * 512; idx += NT) {
+            const int i = idx & 7, ln = (idx >> 3) & 63, pm = idx >> 9;
+            const int pp = pm / RT, mt = pm - pp * RT;
+            const int g = ln >> 4, c = ln & 15;
+            const int e = 16 * (2 * pp + (i >> 2)) + 4 * g + (i & 3);
+            const int k = 16 * mt + 4 * (c & 3) + (c >> 2);
+            h1[idx] = (_Float16)((e < p && k < r) ? A[e + (int64_t)k * lda] : 0.0);
+        }
+        for (int idx = threadIdx.x; idx < TA * RP * 512; idx += NT) {
+            const int i = idx & 7, ln = (idx >> 3) & 63, tr = idx >> 9;
+            const int t = tr / RP, rp = tr - t * RP;
+            const int g = ln >> 4, c = ln & 15;
+            const int e = 16 * t + c;
+            const int k = 16 * (2 * rp + (i >> 2)) + 4 * (i & 3) + g;
+            h2[idx] = (_Float16)((e < p && k < r) ? A[e + (int64_t)k * lda] : 0.0);
+        }
+    } else {
+        // register v of lane (g, c) in (t, mt): A[16 t + 4 g + v][16 mt + 4 (c & 3) + (c >> 2)],
+        // so that the MFMA's output register v is rank 16 mt + 4 v + g, as z
+        for (int idx = threadIdx.x; idx < PT * RT * 256; idx += NT) {
+            const int v = idx & 3, ln = (idx >> 2) & 63, tm = idx >> 8;
+            const int t = tm / RT, mt = tm - t * RT;
+            const int g = ln >> 4, c = ln & 15;
+            const int e = 16 * t + 4 * g + v, k = 16 * mt + 4 * (c & 3) + (c >> 2);
+            a1[idx] = (e < p && k < r) ? (float)A[e + (int64_t)k * lda] : 0.0f;
+        }
     }
     for (int e = threadIdx.x; e < TA * 16; e += NT) {
         int64_t off = -1;
@@ -1183,6 +1225,7 @@ l1_filter_kernel_f16q(FilterLaunch L)
     const int pp0 = part * NPP;                       // this quarter's first pair
     const halfx8 *H1 = reinterpret_cast<const halfx8 *>(h1) + lane;
     const halfx8 *H2 = reinterpret_cast<const halfx8 *>(h2) + lane;
+    const floatx4 *A1 = reinterpret_cast<const floatx4 *>(a1) + lane;
     const floatx4 *F2 = reinterpret_cast<const floatx4 *>(f2glob) + lane;
     float *mine = xch + wave * NV * 64 + lane;
     const float *all = xch + tl * kWavesPerBlock * NV * 64 + lane;   // this tile's quarters
@@ -1250,31 +1293,63 @@ l1_filter_kernel_f16q(FilterLaunch L)
         for (int k = 0;; ++k) {
             // after max_iter steps only the pending stopping test is left
             const bool last = k >= L.c.max_iter;
-            // partial w = A^T g over this quarter's pairs (K = 32 elements per
-            // MFMA); the quarter's fragments are read from LDS all at once, so
-            // their latency is paid once per contraction, not once per MFMA
-            halfx8 f1[NPP][RT];
-#pragma unroll
-            for (int q = 0; q < NPP; ++q)
-#pragma unroll
-                for (int mt = 0; mt < RT; ++mt) f1[q][mt] = H1[((pp0 + q) * RT + mt) * 64];
-            __builtin_amdgcn_sched_barrier(0);
             floatx4 Wp[RT];
-#pragma unroll
-            for (int mt = 0; mt < RT; ++mt) Wp[mt] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
             // g of this step, kept for the dual update (u, y do not change in between)
             float gk[2 * NPP][4];
+            if constexpr (H) {
+                // partial w = A^T g over this quarter's pairs (K = 32 elements per
+                // MFMA); the quarter's fragments are read from LDS all at once, so
+                // their latency is paid once per contraction, not once per MFMA
+                halfx8 f1[NPP][RT];
 #pragma unroll
-            for (int q = 0; q < NPP; ++q) {
+                for (int q = 0; q < NPP; ++q)
 #pragma unroll
-                for (int h = 0; h < 2; ++h)
+                    for (int mt = 0; mt < RT; ++mt) f1[q][mt] = H1[((pp0 + q) * RT + mt) * 64];
+                __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-                    for (int v = 0; v < 4; ++v)
-                        gk[2 * q + h][v] =
-                            __builtin_amdgcn_fmed3f(fmaf(beta, u[2 * q + h][v], y[2 * q + h][v]), -1.0f, 1.0f);
-                const halfx8 gb = pack8(gk[2 * q], gk[2 * q + 1]);
+                for (int mt = 0; mt < RT; ++mt) Wp[mt] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
-                for (int mt = 0; mt < RT; ++mt) Wp[mt] = mfma16h(f1[q][mt], gb, Wp[mt]);
+                for (int q = 0; q < NPP; ++q) {
+#pragma unroll
+                    for (int h = 0; h < 2; ++h)
+#pragma unroll
+                        for (int v = 0; v < 4; ++v)
+                            gk[2 * q + h][v] =
+                                __builtin_amdgcn_fmed3f(fmaf(beta, u[2 * q + h][v], y[2 * q + h][v]), -1.0f, 1.0f);
+                    const halfx8 gb = pack8(gk[2 * q], gk[2 * q + 1]);
+#pragma unroll
+                    for (int mt = 0; mt < RT; ++mt) Wp[mt] = mfma16h(f1[q][mt], gb, Wp[mt]);
+                }
+            } else {
+                // partial w = A^T g on 16x16x4 FP32 MFMAs (K = 4 elements:
+                // 16 t + 4 g + v over g), two element tiles per batch of LDS
+                // reads.  A tile past PT (the last quarter's padding) reads the
+                // last real tile's fragments against g = 0 (its x is 0), adding 0.
+#pragma unroll
+                for (int mt = 0; mt < RT; ++mt) Wp[mt] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+                for (int s0 = 0; s0 < 2 * NPP; s0 += 2) {
+                    floatx4 fa[2][RT];
+#pragma unroll
+                    for (int h = 0; h < 2; ++h) {
+                        const int t = min(2 * pp0 + s0 + h, PT - 1);
+#pragma unroll
+                        for (int mt = 0; mt < RT; ++mt) fa[h][mt] = A1[(t * RT + mt) * 64];
+                    }
+                    // (g is formed again for the dual update: registers, not VALU, bind here)
+                    float gl[2][4];
+#pragma unroll
+                    for (int h = 0; h < 2; ++h)
+#pragma unroll
+                        for (int v = 0; v < 4; ++v)
+                            gl[h][v] = __builtin_amdgcn_fmed3f(fmaf(beta, u[s0 + h][v], y[s0 + h][v]), -1.0f, 1.0f);
+#pragma unroll
+                    for (int h = 0; h < 2; ++h)
+#pragma unroll
+                        for (int v = 0; v < 4; ++v)
+#pragma unroll
+                            for (int mt = 0; mt < RT; ++mt) Wp[mt] = mfma4(fa[h][mt][v], gl[h][v], Wp[mt]);
+                }
             }
 #pragma unroll
             for (int mt = 0; mt < RT; ++mt)
@@ -1334,50 +1409,89 @@ l1_filter_kernel_f16q(FilterLaunch L)
                 for (int v = 0; v < 4; ++v)
                     if (4 * mt + v < KS) z[mt][v] = fmaf(W[mt][v], ib, z[mt][v]);
 
-            // w as the FP16 B operand of v = A w, rank-tile pairs
-            halfx8 wb[RP];
-#pragma unroll
-            for (int rp = 0; rp < RP; ++rp) {
-                float lo[4], hi[4];
-#pragma unroll
-                for (int v = 0; v < 4; ++v) {
-                    lo[v] = W[2 * rp][v];
-                    hi[v] = (2 * rp + 1 < RT) ? W[2 * rp + 1 < RT ? 2 * rp + 1 : 0][v] : 0.0f;
-                }
-                wb[rp] = pack8(lo, hi);
-            }
-            res_part = 0.0f;
-            // fragments of v = A w, read from LDS in batches of KB tile pairs
-            constexpr int KB = NPP >= 4 ? NPP / 2 : NPP;
-            halfx8 f2[2 * KB][RP];
-#pragma unroll
-            for (int s = 0; s < 2 * NPP; s += 2) {
-                if ((s / 2) % KB == 0) {
-#pragma unroll
-                    for (int b = 0; b < 2 * KB; ++b)
-#pragma unroll
-                        for (int rp = 0; rp < RP; ++rp)
-                            f2[b][rp] = (s + b < 2 * NPP) ? H2[((2 * pp0 + s + b) * RP + rp) * 64] : f2[b][rp];
-                    __builtin_amdgcn_sched_barrier(0);
-                }
-                const int sb = s % (2 * KB);
-                floatx4 Va = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
-                floatx4 Vb = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
+            if constexpr (H) {
+                // w as the FP16 B operand of v = A w, rank-tile pairs
+                halfx8 wb[RP];
 #pragma unroll
                 for (int rp = 0; rp < RP; ++rp) {
-                    Va = mfma16h(f2[sb][rp], wb[rp], Va);
-                    Vb = mfma16h(f2[sb + 1][rp], wb[rp], Vb);
-                }
-#pragma unroll
-                for (int h = 0; h < 2; ++h) {
-                    const floatx4 Vt = h ? Vb : Va;
+                    float lo[4], hi[4];
 #pragma unroll
                     for (int v = 0; v < 4; ++v) {
-                        const float yo = y[s + h][v];
-                        const float yn = gk[s + h][v] - Vt[v];
+                        lo[v] = W[2 * rp][v];
+                        hi[v] = (2 * rp + 1 < RT) ? W[2 * rp + 1 < RT ? 2 * rp + 1 : 0][v] : 0.0f;
+                    }
+                    wb[rp] = pack8(lo, hi);
+                }
+                res_part = 0.0f;
+                // fragments of v = A w, read from LDS in batches of KB tile pairs
+                constexpr int KB = NPP >= 4 ? NPP / 2 : NPP;
+                halfx8 f2[2 * KB][RP];
+#pragma unroll
+                for (int s = 0; s < 2 * NPP; s += 2) {
+                    if ((s / 2) % KB == 0) {
+#pragma unroll
+                        for (int b = 0; b < 2 * KB; ++b)
+#pragma unroll
+                            for (int rp = 0; rp < RP; ++rp)
+                                f2[b][rp] = (s + b < 2 * NPP) ? H2[((2 * pp0 + s + b) * RP + rp) * 64] : f2[b][rp];
+                        __builtin_amdgcn_sched_barrier(0);
+                    }
+                    const int sb = s % (2 * KB);
+                    floatx4 Va = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
+                    floatx4 Vb = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+                    for (int rp = 0; rp < RP; ++rp) {
+                        Va = mfma16h(f2[sb][rp], wb[rp], Va);
+                        Vb = mfma16h(f2[sb + 1][rp], wb[rp], Vb);
+                    }
+#pragma unroll
+                    for (int h = 0; h < 2; ++h) {
+                        const floatx4 Vt = h ? Vb : Va;
+#pragma unroll
+                        for (int v = 0; v < 4; ++v) {
+                            const float yo = y[s + h][v];
+                            const float yn = gk[s + h][v] - Vt[v];
+                            res_part = fmaxf(res_part, fabsf(yn - yo));
+                            u[s + h][v] = fmaf(-Vt[v], ib, u[s + h][v]);
+                            y[s + h][v] = yn;
+                        }
+                    }
+                }
+            } else {
+                // v = A w on 16x16x4 FP32 MFMAs from the refresh fragments in
+                // HBM (L2), one element tile at a time with the next tile's
+                // loads in flight under this tile's MFMAs; a tile past PT reads
+                // the last real tile and contributes 0
+                res_part = 0.0f;
+                const __amdgpu_buffer_rsrc_t f2r =
+                    __builtin_amdgcn_make_buffer_rsrc(const_cast<float *>(f2glob), 0, PT * RT * 1024, kBufWord3);
+                floatx4 fb[2][RT];
+#pragma unroll
+                for (int mt = 0; mt < RT; ++mt) fb[0][mt] = buf_load4(f2r, 16 * lane, (min(2 * pp0, PT - 1) * RT + mt) * 1024);
+#pragma unroll
+                for (int s = 0; s < 2 * NPP; ++s) {
+                    const int cur = s & 1;
+                    if (s + 1 < 2 * NPP) {
+                        const int t = min(2 * pp0 + s + 1, PT - 1);
+#pragma unroll
+                        for (int mt = 0; mt < RT; ++mt) fb[cur ^ 1][mt] = buf_load4(f2r, 16 * lane, (t * RT + mt) * 1024);
+                    }
+                    floatx4 Vq = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+                    for (int mt = 0; mt < RT; ++mt)
+#pragma unroll
+                        for (int v = 0; v < 4; ++v)
+                            if (4 * mt + v < KS) Vq = mfma4(fb[cur][mt][v], W[mt][v], Vq);
+                    const bool real = 2 * pp0 + s < PT;
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) {
+                        const float Vt = real ? Vq[v] : 0.0f;
+                        const float yo = y[s][v];
+                        const float gs = __builtin_amdgcn_fmed3f(fmaf(beta, u[s][v], yo), -1.0f, 1.0f);
+                        const float yn = gs - Vt;
                         res_part = fmaxf(res_part, fabsf(yn - yo));
-                        u[s + h][v] = fmaf(-Vt[v], ib, u[s + h][v]);
-                        y[s + h][v] = yn;
+                        u[s][v] = fmaf(-Vt, ib, u[s][v]);
+                        y[s][v] = yn;
                     }
                 }
             }
@@ -1389,38 +1503,75 @@ l1_filter_kernel_f16q(FilterLaunch L)
             // one batch before any of their MFMAs, so the load latency is paid
             // once per batch (the compiler's own order waited once per rank tile)
             if (L.c.refresh > 0 && ((k + 1) % L.c.refresh) == 0) {
-                constexpr int QB = 2;
+                if constexpr (H) {
+                    constexpr int QB = 2;
 #pragma unroll
-                for (int s0 = 0; s0 < 2 * NPP; s0 += QB) {
-                    const int t0 = 2 * pp0 + s0;
-                    if (t0 < PT) {                    // wave-uniform
-                        floatx4 fa[QB][RT], xq[QB];
-                        const floatx4 zero4 = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
+                    for (int s0 = 0; s0 < 2 * NPP; s0 += QB) {
+                        const int t0 = 2 * pp0 + s0;
+                        if (t0 < PT) {                    // wave-uniform
+                            floatx4 fa[QB][RT], xq[QB];
+                            const floatx4 zero4 = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
-                        for (int h = 0; h < QB; ++h) {
-                            const bool on = s0 + h < 2 * NPP && t0 + h < PT;
+                            for (int h = 0; h < QB; ++h) {
+                                const bool on = s0 + h < 2 * NPP && t0 + h < PT;
 #pragma unroll
-                            for (int mt = 0; mt < RT; ++mt) fa[h][mt] = on ? F2[((t0 + h) * RT + mt) * 64] : zero4;
-                            xq[h] = (on && tile_in) ? xtile[(t0 + h) * 64] : zero4;
+                                for (int mt = 0; mt < RT; ++mt) fa[h][mt] = on ? F2[((t0 + h) * RT + mt) * 64] : zero4;
+                                xq[h] = (on && tile_in) ? xtile[(t0 + h) * 64] : zero4;
+                            }
+                            __builtin_amdgcn_sched_barrier(0);
+                            floatx4 Az[QB];
+#pragma unroll
+                            for (int h = 0; h < QB; ++h) Az[h] = zero4;
+#pragma unroll
+                            for (int mt = 0; mt < RT; ++mt)
+#pragma unroll
+                                for (int v = 0; v < 4; ++v)
+                                    if (4 * mt + v < KS)
+#pragma unroll
+                                        for (int h = 0; h < QB; ++h) Az[h] = mfma4(fa[h][mt][v], z[mt][v], Az[h]);
+#pragma unroll
+                            for (int h = 0; h < QB; ++h) {
+                                if (s0 + h < 2 * NPP && t0 + h < PT) {
+#pragma unroll
+                                    for (int v = 0; v < 4; ++v) u[s0 + h][v] = xq[h][v] - Az[h][v];
+                                }
+                            }
                         }
-                        __builtin_amdgcn_sched_barrier(0);
-                        floatx4 Az[QB];
+                    }
+                } else {
+                    // one element tile at a time, the next tile's fragments and x
+                    // in flight under this tile's MFMAs (x of an idle tile: the
+                    // first tile's slot, never used)
+                    const __amdgpu_buffer_rsrc_t f2r =
+                        __builtin_amdgcn_make_buffer_rsrc(const_cast<float *>(f2glob), 0, PT * RT * 1024, kBufWord3);
+                    const __amdgpu_buffer_rsrc_t xr = __builtin_amdgcn_make_buffer_rsrc(
+                        xbuf + (tile_in ? tile : 0) * PT * 64, 0, PT * 1024, kBufWord3);
+                    floatx4 fr[2][RT], xv[2];
+                    {
+                        const int t = min(2 * pp0, PT - 1);
 #pragma unroll
-                        for (int h = 0; h < QB; ++h) Az[h] = zero4;
+                        for (int mt = 0; mt < RT; ++mt) fr[0][mt] = buf_load4(f2r, 16 * lane, (t * RT + mt) * 1024);
+                        xv[0] = buf_load4(xr, 16 * lane, t * 1024);
+                    }
+#pragma unroll
+                    for (int s = 0; s < 2 * NPP; ++s) {
+                        const int cur = s & 1;
+                        if (s + 1 < 2 * NPP) {
+                            const int t = min(2 * pp0 + s + 1, PT - 1);
+#pragma unroll
+                            for (int mt = 0; mt < RT; ++mt) fr[cur ^ 1][mt] = buf_load4(f2r, 16 * lane, (t * RT + mt) * 1024);
+                            xv[cur ^ 1] = buf_load4(xr, 16 * lane, t * 1024);
+                        }
+                        floatx4 Az = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
                         for (int mt = 0; mt < RT; ++mt)
 #pragma unroll
                             for (int v = 0; v < 4; ++v)
-                                if (4 * mt + v < KS)
+                                if (4 * mt + v < KS) Az = mfma4(fr[cur][mt][v], z[mt][v], Az);
+                        const bool real = 2 * pp0 + s < PT;
 #pragma unroll
-                                    for (int h = 0; h < QB; ++h) Az[h] = mfma4(fa[h][mt][v], z[mt][v], Az[h]);
-#pragma unroll
-                        for (int h = 0; h < QB; ++h) {
-                            if (s0 + h < 2 * NPP && t0 + h < PT) {
-#pragma unroll
-                                for (int v = 0; v < 4; ++v) u[s0 + h][v] = xq[h][v] - Az[h][v];
-                            }
-                        }
+                        for (int v = 0; v < 4; ++v)
+                            u[s][v] = real ? (tile_in ? xv[cur][v] : 0.0f) - Az[v] : u[s][v];
                     }
                 }
             }
@@ -1443,8 +1594,11 @@ l1_filter_kernel_f16q(FilterLaunch L)
     }
 }
 
-// FP32 refresh fragments of the precision form, for classes whose LDS cannot
-// hold them: out[(t RT + mt) 256 + lane 4 + v] = A[16 t + c][16 mt + 4 v + g].
+
+
+// FP32 refresh fragments of the precision form (and of the FP32 quarter-tile
+// form's v = A w), for classes whose LDS cannot hold them:
+// out[(t RT + mt) 256 + lane 4 + v] = A[16 t + c][16 mt + 4 v + g].
 static __global__ void prep_frag32(const double *__restrict__ A, int lda, int p, int r, int PT, int RT,
                             float *__restrict__ out)
 {
@@ -1479,10 +1633,10 @@ int launch_pt_ks(rpca_ctx *ctx, const FilterLaunch &L, int nblocks, bool split, 
                 // once per process (thread-safe static initialisation), before
                 // any launch can be captured in a graph
                 static const hipError_t attr =
-                    hipFuncSetAttribute((const void *)l1_filter_kernel_f16q<PT, KS, TPB>,
+                    hipFuncSetAttribute((const void *)l1_filter_kernel_quarter<PT, KS, TPB, true>,
                                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
                 RPCA_HIP_TRY(ctx, attr);
-                hipLaunchKernelGGL((l1_filter_kernel_f16q<PT, KS, TPB>), dim3(nblocks),
+                hipLaunchKernelGGL((l1_filter_kernel_quarter<PT, KS, TPB, true>), dim3(nblocks),
                                    dim3(TPB * kWavesPerBlock * 64), lds, stream, L);
                 RPCA_HIP_TRY(ctx, hipGetLastError());
                 return RPCA_OK;
@@ -1502,7 +1656,25 @@ int launch_pt_ks(rpca_ctx *ctx, const FilterLaunch &L, int nblocks, bool split, 
         RPCA_HIP_TRY(ctx, hipGetLastError());
         return RPCA_OK;
     }
-    if constexpr (PT <= 19) {
+    if constexpr (half_form(PT) && PT > 19) {
+        // FP32 beyond the tile classes: the quarter-tile shape with FP32
+        // contractions (v = A w from the fragments the launcher prepared)
+        if (!L.frag32[0] || !L.frag32[1])
+            return set_status(ctx, RPCA_ERR_ARG, "filter: FP32 quarter-tile form without its fragments");
+        auto go = [&](auto tpb_tag) -> int {
+            constexpr int TPB = decltype(tpb_tag)::value;
+            const size_t lds = lds_bytes_q32(PT, KS, TPB);
+            static const hipError_t attr =
+                hipFuncSetAttribute((const void *)l1_filter_kernel_quarter<PT, KS, TPB, false>,
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+            RPCA_HIP_TRY(ctx, attr);
+            hipLaunchKernelGGL((l1_filter_kernel_quarter<PT, KS, TPB, false>), dim3(nblocks),
+                               dim3(TPB * kWavesPerBlock * 64), lds, stream, L);
+            RPCA_HIP_TRY(ctx, hipGetLastError());
+            return RPCA_OK;
+        };
+        return L.qtiles == 2 ? go(std::integral_constant<int, 2>{}) : go(std::integral_constant<int, 1>{});
+    } else if constexpr (PT <= 19) {
         const size_t lds = lds_bytes(PT, KS);
         static const hipError_t attr = hipFuncSetAttribute(
             (const void *)l1_filter_kernel<PT, KS>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
