@@ -123,6 +123,44 @@ def test_batch_matches_oracle_per_job(R, ctx):
     b.close()
 
 
+def test_batch_large_p_fp32_jobs(R, ctx):
+    # jobs beyond the FP32 tile classes in one batch (p = 410 and 500: the
+    # FP32 quarter-tile form on both sides of each) next to a lane-form job,
+    # each against the oracle run on that job alone (the random low-rank +
+    # sparse problems of the single-problem tests, whose seeds reach their
+    # rank at the default tolerance on both sides)
+    import torch
+    from test_gpu_parity import small_case
+    cases = [(2600, 2333, 41, 48, 2600), (2700, 2517, 50, 57, 2703), (900, 400, 5, 12, 900)]
+    keep, jobs, ref = [], [], []
+    for m, n, r, seed, ldm in cases:
+        pr, I, J, res = small_case(m, n, r, 0.05, seed)
+        Md = _upload(pr, ldm)
+        L = torch.full((n, ldm), float("nan"), dtype=torch.float32, device="cuda")
+        S = torch.full((n, ldm), float("nan"), dtype=torch.float32, device="cuda")
+        dI, dJ = dev_i64(I), dev_i64(J)
+        keep.append((Md, L, S, dI, dJ))
+        jobs.append(R.job(Md, m, n, ldm, r, dI, len(I), dJ, len(J), L, ldm, S, ldm))
+        ref.append((pr, r, res))
+    say(f"batch with large-p FP32 jobs: {[(m, n, r, 10 * r) for m, n, r, _, _ in cases]}")
+    b = R.Batch(ctx, jobs, R.rpca_opts_default(), None)
+    st = R.rpca_batch_seed(b)
+    assert st >= 0, ctx.last_error()
+    R.rpca_batch_run(b)
+    torch.cuda.synchronize()
+    for k, (Md, L, S, dI, dJ) in enumerate(keep):
+        pr, r, res = ref[k]
+        st, info = R.rpca_batch_job_info(b, k)
+        assert info.r_used == min(res.seed.rank, r) and info.filt_not_converged == 0
+        Lh = L[:, :pr.m].double().cpu().numpy().T
+        Sh = S[:, :pr.m].double().cpu().numpy().T
+        eL, eS = relF(Lh, res.L), relF(Sh, res.S)
+        say(f"ERR batch large-p job {k} relL={eL:.3e} relS={eS:.3e}")
+        assert eL <= REL_TOL and eS <= REL_TOL, (k, eL, eS)
+        assert support_mismatch(Sh, res.S, float(np.abs(pr.M).max())) == 0, k
+    b.close()
+
+
 def test_batch_graph_replays_are_bitwise_equal(R, ctx):
     import torch
     ref = _small_batch_reference()[9:]

@@ -5,9 +5,9 @@ and every element of L, S is computed by the same code; only the order of the
 launches and the stream they run on change), and therefore the oracle's
 result within the stated 1e-5.  Cases: the oracle-sized workload in both
 precision forms, the precision form's quarter-tile kernel (p = 300), chunk
-counts from 1 to 16, the full-size plain workload, ragged shapes with padded
-leading dimensions, slabs with no column regressions, a seed taking every
-row."""
+counts from 1 to 16, the FP32 quarter-tile kernel (p = 410), the full-size
+plain workload, ragged shapes with padded leading dimensions, slabs with no
+column regressions, a seed taking every row."""
 from __future__ import annotations
 
 import numpy as np
@@ -109,6 +109,18 @@ def test_overlapped_quarter_tile_precision(R, ctx, chunks):
     k = res.U.shape[1]
     say(f"overlap quarter-tile precision form chunks={chunks}")
     Lh, Sh = _run_both(R, ctx, pr, I, J, res.U, res.sigma, res.V, k, chunks, 1)
+    assert relF(Lh, res.L) <= REL_TOL and relF(Sh, res.S) <= REL_TOL
+
+
+@pytest.mark.parametrize("chunks,ld_pad", [(3, 0), (6, 7)])
+def test_overlapped_quarter_tile_fp32(R, ctx, chunks, ld_pad):
+    # p = q = 410 (class PT = 26) in the FP32 form: the quarter-tile kernel
+    # with FP32 contractions, reading its regression range from the device in
+    # every column slab, with and without a padded leading dimension
+    pr, I, J, res = small_case(2600, 2333, 41, 0.05, 48)
+    k = res.U.shape[1]
+    say(f"overlap quarter-tile FP32 form chunks={chunks} ld+{ld_pad}")
+    Lh, Sh = _run_both(R, ctx, pr, I, J, res.U, res.sigma, res.V, k, chunks, 0, ld=pr.m + ld_pad)
     assert relF(Lh, res.L) <= REL_TOL and relF(Sh, res.S) <= REL_TOL
 
 
