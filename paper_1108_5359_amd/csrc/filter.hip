@@ -135,11 +135,13 @@ int launch_filter(rpca_ctx *ctx, const FilterSide *sides, int nsides, const Filt
     FilterLaunch L{};
     L.c = c;
     L.frag32[0] = L.frag32[1] = nullptr;
-    // workspace for x in fragment order: 16 PT floats per regression (padded to tiles)
+    // workspace for x in fragment order: 16 PT floats per regression (padded to
+    // tiles, and to tile pairs: the quarter-tile form keeps one x slot per tile
+    // slot of its workgroups)
     size_t xoff[2] = {0, 0}, xtotal = 0;
     for (int s = 0; s < nsides; ++s) {
         xoff[s] = xtotal;
-        xtotal += (size_t)((sides[s].nreg + 15) / 16) * PT * 256;
+        xtotal += (size_t)((sides[s].nreg + 31) / 32 * 2) * PT * 256;
     }
     {
         int st = ensure_buf(ctx, ctx->xbuf_ws, xtotal * sizeof(float));

@@ -1220,7 +1220,7 @@ l1_filter_kernel_quarter(FilterLaunch L)
     const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const int lane = threadIdx.x & 63;
     const int g = lane >> 4, c = lane & 15;
-    const int tl = wave / kWavesPerBlock;             // this wave's tile of the block
+    const int tl = wave / kWavesPerBlock;             // this wave's tile slot of the block
     const int part = wave % kWavesPerBlock;           // its quarter
     const int pp0 = part * NPP;                       // this quarter's first pair
     const halfx8 *H1 = reinterpret_cast<const halfx8 *>(h1) + lane;
@@ -1228,355 +1228,48 @@ l1_filter_kernel_quarter(FilterLaunch L)
     const floatx4 *A1 = reinterpret_cast<const floatx4 *>(a1) + lane;
     const floatx4 *F2 = reinterpret_cast<const floatx4 *>(f2glob) + lane;
     float *mine = xch + wave * NV * 64 + lane;
-    const float *all = xch + tl * kWavesPerBlock * NV * 64 + lane;   // this tile's quarters
+    const float *all = xch + tl * kWavesPerBlock * NV * 64 + lane;   // this slot's quarters
 
-#pragma unroll 1
-    for (int64_t tb = block_in_side; jbeg + tb * TPB * 16 < jend; tb += side_blocks) {
-        const int64_t tile = tb * TPB + tl;
-        const bool tile_in = jbeg + tile * 16 < jend;      // wave-uniform: the tile holds regressions
-        const int64_t j = jbeg + tile * 16 + c;
-        bool valid = j < jend;
-        int64_t roff = 0;
-        if (valid) {
-            const int64_t ri = reg_idx[j];
-            if (ri >= 0 && ri < reg_bound) roff = ri * reg_stride;
-            else valid = false;
+    // ---- the slot's regressions ------------------------------------------
+    // A slot serves the regressions of its tiles (tb TPB + slot, tb =
+    // block_in_side, + side_blocks, ...) as one sequence, one regression per
+    // column at a time: a column whose regression has stopped takes the next
+    // one of the sequence at the next refill point.  Refill points are one
+    // refresh period apart, so every regression starts its steps at the same
+    // phase of the refresh schedule; with the per-column arithmetic of the
+    // contractions (an MFMA output column depends on its own input column
+    // only) and the per-column sums, a regression's result does not depend
+    // on its column-mates.  A refilled column loads its x (refill step), sums
+    // its norms over the quarters (next step, in place of its w partials) and
+    // takes its step 0 one step later.
+    const int RA = L.c.refresh > 0 ? L.c.refresh : 1;
+    auto seq_pos = [&](int64_t i) -> int64_t {        // position of sequence entry i
+        return jbeg + ((block_in_side + (i >> 4) * side_blocks) * TPB + tl) * 16 + (i & 15);
+    };
+    constexpr int64_t kNone = INT64_MAX;              // a column holding no regression
+    // x of the slot's columns in fragment order (read back by the refresh)
+    floatx4 *xslot_base = xbuf + ((int64_t)block_in_side * TPB + tl) * PT * 64;
+    floatx4 *xslot = xslot_base + lane;
+    int64_t cursor = 0;                               // next sequence entry (uniform)
+    uint64_t fresh_m = 0;                             // lanes of columns set up in this step
+    int64_t j = kNone, roff = 0;
+    bool valid = false, bad = false, done = true;
+    int K = 0;
+    float u[2 * NPP][4], y[2 * NPP][4];
+    floatx4 z[RT];
+#pragma unroll
+    for (int s = 0; s < 2 * NPP; ++s)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            u[s][v] = 0.0f;
+            y[s][v] = 0.0f;
         }
+#pragma unroll
+    for (int mt = 0; mt < RT; ++mt) z[mt] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
+    float beta = 1.0f, beta_bar = 1.0f, tol = 0.0f, inv_beta_prev = 0.0f, res_part = 0.0f;
 
-        // ---- x of this quarter, its partial norms, the state ---------------
-        float u[2 * NPP][4], y[2 * NPP][4];
-        float xinf = 0.0f, xx = 0.0f;
-        floatx4 *xtile = xbuf + tile * PT * 64 + lane;
-#pragma unroll
-        for (int s = 0; s < 2 * NPP; ++s) {
-            const int t = 2 * pp0 + s;
-            floatx4 xv;
-#pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                const int64_t e = eoff[16 * t + 4 * g + v];
-                const int64_t off = TPB == 2 ? e * elem_stride : e;
-                const float x = (valid && e >= 0) ? M[roff + off] : 0.0f;
-                xv[v] = x;
-                u[s][v] = x;
-                y[s][v] = 0.0f;
-                xinf = fmaxf(xinf, fabsf(x));
-                xx = fmaf(x, x, xx);
-            }
-            if (t < PT && tile_in) xtile[t * 64] = xv;   // (no x slot for an idle tile)
-        }
-        // norms over the quarters, in quarter order
-        mine[0] = xinf;
-        mine[64] = xx;
-        __syncthreads();
-        xinf = all[0];
-        xx = all[64];
-#pragma unroll
-        for (int w = 1; w < kWavesPerBlock; ++w) {
-            xinf = fmaxf(xinf, all[w * NV * 64]);
-            xx += all[w * NV * 64 + 64];
-        }
-        xinf = colmax(xinf);
-        xx = colsum(xx);
-        __syncthreads();                              // the buffer is reused below
-
-        float beta = xx > 0.0f ? L.c.beta0_scale / sqrtf(xx) : 1.0f;
-        const float beta_bar = L.c.beta_max_scale * beta;
-        const float tol = L.c.eps * xinf;
-        const bool bad = valid && nonfinite_norm(xx);     // x holds Inf / NaN
-        bool done = !(valid && xinf > 0.0f) || bad;
-        int K = 0;
-        float inv_beta_prev = 0.0f, res_part = 0.0f;
-        floatx4 z[RT];
-#pragma unroll
-        for (int mt = 0; mt < RT; ++mt) z[mt] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
-
-        for (int k = 0;; ++k) {
-            // after max_iter steps only the pending stopping test is left
-            const bool last = k >= L.c.max_iter;
-            floatx4 Wp[RT];
-            // g of this step, kept for the dual update (u, y do not change in between)
-            float gk[2 * NPP][4];
-            if constexpr (H) {
-                // partial w = A^T g over this quarter's pairs (K = 32 elements per
-                // MFMA); the quarter's fragments are read from LDS all at once, so
-                // their latency is paid once per contraction, not once per MFMA
-                halfx8 f1[NPP][RT];
-#pragma unroll
-                for (int q = 0; q < NPP; ++q)
-#pragma unroll
-                    for (int mt = 0; mt < RT; ++mt) f1[q][mt] = H1[((pp0 + q) * RT + mt) * 64];
-                __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-                for (int mt = 0; mt < RT; ++mt) Wp[mt] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
-#pragma unroll
-                for (int q = 0; q < NPP; ++q) {
-#pragma unroll
-                    for (int h = 0; h < 2; ++h)
-#pragma unroll
-                        for (int v = 0; v < 4; ++v)
-                            gk[2 * q + h][v] =
-                                __builtin_amdgcn_fmed3f(fmaf(beta, u[2 * q + h][v], y[2 * q + h][v]), -1.0f, 1.0f);
-                    const halfx8 gb = pack8(gk[2 * q], gk[2 * q + 1]);
-#pragma unroll
-                    for (int mt = 0; mt < RT; ++mt) Wp[mt] = mfma16h(f1[q][mt], gb, Wp[mt]);
-                }
-            } else {
-                // partial w = A^T g on 16x16x4 FP32 MFMAs (K = 4 elements:
-                // 16 t + 4 g + v over g), two element tiles per batch of LDS
-                // reads.  A tile past PT (the last quarter's padding) reads the
-                // last real tile's fragments against g = 0 (its x is 0), adding 0.
-#pragma unroll
-                for (int mt = 0; mt < RT; ++mt) Wp[mt] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
-#pragma unroll
-                for (int s0 = 0; s0 < 2 * NPP; s0 += 2) {
-                    floatx4 fa[2][RT];
-#pragma unroll
-                    for (int h = 0; h < 2; ++h) {
-                        const int t = min(2 * pp0 + s0 + h, PT - 1);
-#pragma unroll
-                        for (int mt = 0; mt < RT; ++mt) fa[h][mt] = A1[(t * RT + mt) * 64];
-                    }
-                    // (g is formed again for the dual update: registers, not VALU, bind here)
-                    float gl[2][4];
-#pragma unroll
-                    for (int h = 0; h < 2; ++h)
-#pragma unroll
-                        for (int v = 0; v < 4; ++v)
-                            gl[h][v] = __builtin_amdgcn_fmed3f(fmaf(beta, u[s0 + h][v], y[s0 + h][v]), -1.0f, 1.0f);
-#pragma unroll
-                    for (int h = 0; h < 2; ++h)
-#pragma unroll
-                        for (int v = 0; v < 4; ++v)
-#pragma unroll
-                            for (int mt = 0; mt < RT; ++mt) Wp[mt] = mfma4(fa[h][mt][v], gl[h][v], Wp[mt]);
-                }
-            }
-#pragma unroll
-            for (int mt = 0; mt < RT; ++mt)
-#pragma unroll
-                for (int v = 0; v < 4; ++v)
-                    if (4 * mt + v < KS) mine[(4 * mt + v) * 64] = Wp[mt][v];
-            // the residual partial, or -1 for a stopped regression (its
-            // residual is not used again): the sign tells the block which
-            // regressions were still moving after the previous test
-            mine[(NV - 1) * 64] = done ? -1.0f : res_part;
-            __syncthreads();
-            floatx4 W[RT];
-            float res = all[(NV - 1) * 64];
-#pragma unroll
-            for (int mt = 0; mt < RT; ++mt)
-#pragma unroll
-                for (int v = 0; v < 4; ++v) W[mt][v] = (4 * mt + v < KS) ? all[(4 * mt + v) * 64] : 0.0f;
-#pragma unroll
-            for (int w = 1; w < kWavesPerBlock; ++w) {
-#pragma unroll
-                for (int mt = 0; mt < RT; ++mt)
-#pragma unroll
-                    for (int v = 0; v < 4; ++v)
-                        if (4 * mt + v < KS) W[mt][v] += all[(w * NV + 4 * mt + v) * 64];
-                res = fmaxf(res, all[(w * NV + NV - 1) * 64]);
-            }
-            // two tiles: whether any regression of the block was still moving
-            // after the previous test, from the flags both tiles published
-            // (every wave reads the same values: the same in every wave)
-            bool live_prev = true;
-            if constexpr (TPB == 2) {
-                const float f0 = xch[(NV - 1) * 64 + lane];
-                const float f1 = xch[(kWavesPerBlock * NV + NV - 1) * 64 + lane];
-                live_prev = __any(f0 >= 0.0f || f1 >= 0.0f);
-            }
-            res = colmax(res);
-            // the stopping test of step k - 1
-            if (k > 0 && !done) {
-                ++K;
-                if (!(res * inv_beta_prev >= tol)) done = true;
-            }
-            __syncthreads();                          // every wave has read the partials
-            if constexpr (TPB == 1) {
-                if (last || !__any(!done)) break;     // the same in every wave of the block
-            } else {
-                // a finished tile keeps stepping frozen, as a finished
-                // regression does; the block stops one step after its last
-                // regression
-                if (last || !live_prev) break;
-            }
-
-            const float inv_beta = __builtin_amdgcn_rcpf(beta);
-            const float ib = done ? 0.0f : inv_beta;
-#pragma unroll
-            for (int mt = 0; mt < RT; ++mt)
-#pragma unroll
-                for (int v = 0; v < 4; ++v)
-                    if (4 * mt + v < KS) z[mt][v] = fmaf(W[mt][v], ib, z[mt][v]);
-
-            if constexpr (H) {
-                // w as the FP16 B operand of v = A w, rank-tile pairs
-                halfx8 wb[RP];
-#pragma unroll
-                for (int rp = 0; rp < RP; ++rp) {
-                    float lo[4], hi[4];
-#pragma unroll
-                    for (int v = 0; v < 4; ++v) {
-                        lo[v] = W[2 * rp][v];
-                        hi[v] = (2 * rp + 1 < RT) ? W[2 * rp + 1 < RT ? 2 * rp + 1 : 0][v] : 0.0f;
-                    }
-                    wb[rp] = pack8(lo, hi);
-                }
-                res_part = 0.0f;
-                // fragments of v = A w, read from LDS in batches of KB tile pairs
-                constexpr int KB = NPP >= 4 ? NPP / 2 : NPP;
-                halfx8 f2[2 * KB][RP];
-#pragma unroll
-                for (int s = 0; s < 2 * NPP; s += 2) {
-                    if ((s / 2) % KB == 0) {
-#pragma unroll
-                        for (int b = 0; b < 2 * KB; ++b)
-#pragma unroll
-                            for (int rp = 0; rp < RP; ++rp)
-                                f2[b][rp] = (s + b < 2 * NPP) ? H2[((2 * pp0 + s + b) * RP + rp) * 64] : f2[b][rp];
-                        __builtin_amdgcn_sched_barrier(0);
-                    }
-                    const int sb = s % (2 * KB);
-                    floatx4 Va = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
-                    floatx4 Vb = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
-#pragma unroll
-                    for (int rp = 0; rp < RP; ++rp) {
-                        Va = mfma16h(f2[sb][rp], wb[rp], Va);
-                        Vb = mfma16h(f2[sb + 1][rp], wb[rp], Vb);
-                    }
-#pragma unroll
-                    for (int h = 0; h < 2; ++h) {
-                        const floatx4 Vt = h ? Vb : Va;
-#pragma unroll
-                        for (int v = 0; v < 4; ++v) {
-                            const float yo = y[s + h][v];
-                            const float yn = gk[s + h][v] - Vt[v];
-                            res_part = fmaxf(res_part, fabsf(yn - yo));
-                            u[s + h][v] = fmaf(-Vt[v], ib, u[s + h][v]);
-                            y[s + h][v] = yn;
-                        }
-                    }
-                }
-            } else {
-                // v = A w on 16x16x4 FP32 MFMAs from the refresh fragments in
-                // HBM (L2), one element tile at a time with the next tile's
-                // loads in flight under this tile's MFMAs; a tile past PT reads
-                // the last real tile and contributes 0
-                res_part = 0.0f;
-                const __amdgpu_buffer_rsrc_t f2r =
-                    __builtin_amdgcn_make_buffer_rsrc(const_cast<float *>(f2glob), 0, PT * RT * 1024, kBufWord3);
-                floatx4 fb[2][RT];
-#pragma unroll
-                for (int mt = 0; mt < RT; ++mt) fb[0][mt] = buf_load4(f2r, 16 * lane, (min(2 * pp0, PT - 1) * RT + mt) * 1024);
-#pragma unroll
-                for (int s = 0; s < 2 * NPP; ++s) {
-                    const int cur = s & 1;
-                    if (s + 1 < 2 * NPP) {
-                        const int t = min(2 * pp0 + s + 1, PT - 1);
-#pragma unroll
-                        for (int mt = 0; mt < RT; ++mt) fb[cur ^ 1][mt] = buf_load4(f2r, 16 * lane, (t * RT + mt) * 1024);
-                    }
-                    floatx4 Vq = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
-#pragma unroll
-                    for (int mt = 0; mt < RT; ++mt)
-#pragma unroll
-                        for (int v = 0; v < 4; ++v)
-                            if (4 * mt + v < KS) Vq = mfma4(fb[cur][mt][v], W[mt][v], Vq);
-                    const bool real = 2 * pp0 + s < PT;
-#pragma unroll
-                    for (int v = 0; v < 4; ++v) {
-                        const float Vt = real ? Vq[v] : 0.0f;
-                        const float yo = y[s][v];
-                        const float gs = __builtin_amdgcn_fmed3f(fmaf(beta, u[s][v], yo), -1.0f, 1.0f);
-                        const float yn = gs - Vt;
-                        res_part = fmaxf(res_part, fabsf(yn - yo));
-                        u[s][v] = fmaf(-Vt, ib, u[s][v]);
-                        y[s][v] = yn;
-                    }
-                }
-            }
-            inv_beta_prev = inv_beta;
-            beta = fminf(L.c.rho * beta, beta_bar);
-
-            // FP32 residual refinement: u = x - A z from the input, two element
-            // tiles at a time: their fragments and x are loaded from HBM (L2) in
-            // one batch before any of their MFMAs, so the load latency is paid
-            // once per batch (the compiler's own order waited once per rank tile)
-            if (L.c.refresh > 0 && ((k + 1) % L.c.refresh) == 0) {
-                if constexpr (H) {
-                    constexpr int QB = 2;
-#pragma unroll
-                    for (int s0 = 0; s0 < 2 * NPP; s0 += QB) {
-                        const int t0 = 2 * pp0 + s0;
-                        if (t0 < PT) {                    // wave-uniform
-                            floatx4 fa[QB][RT], xq[QB];
-                            const floatx4 zero4 = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
-#pragma unroll
-                            for (int h = 0; h < QB; ++h) {
-                                const bool on = s0 + h < 2 * NPP && t0 + h < PT;
-#pragma unroll
-                                for (int mt = 0; mt < RT; ++mt) fa[h][mt] = on ? F2[((t0 + h) * RT + mt) * 64] : zero4;
-                                xq[h] = (on && tile_in) ? xtile[(t0 + h) * 64] : zero4;
-                            }
-                            __builtin_amdgcn_sched_barrier(0);
-                            floatx4 Az[QB];
-#pragma unroll
-                            for (int h = 0; h < QB; ++h) Az[h] = zero4;
-#pragma unroll
-                            for (int mt = 0; mt < RT; ++mt)
-#pragma unroll
-                                for (int v = 0; v < 4; ++v)
-                                    if (4 * mt + v < KS)
-#pragma unroll
-                                        for (int h = 0; h < QB; ++h) Az[h] = mfma4(fa[h][mt][v], z[mt][v], Az[h]);
-#pragma unroll
-                            for (int h = 0; h < QB; ++h) {
-                                if (s0 + h < 2 * NPP && t0 + h < PT) {
-#pragma unroll
-                                    for (int v = 0; v < 4; ++v) u[s0 + h][v] = xq[h][v] - Az[h][v];
-                                }
-                            }
-                        }
-                    }
-                } else {
-                    // one element tile at a time, the next tile's fragments and x
-                    // in flight under this tile's MFMAs (x of an idle tile: the
-                    // first tile's slot, never used)
-                    const __amdgpu_buffer_rsrc_t f2r =
-                        __builtin_amdgcn_make_buffer_rsrc(const_cast<float *>(f2glob), 0, PT * RT * 1024, kBufWord3);
-                    const __amdgpu_buffer_rsrc_t xr = __builtin_amdgcn_make_buffer_rsrc(
-                        xbuf + (tile_in ? tile : 0) * PT * 64, 0, PT * 1024, kBufWord3);
-                    floatx4 fr[2][RT], xv[2];
-                    {
-                        const int t = min(2 * pp0, PT - 1);
-#pragma unroll
-                        for (int mt = 0; mt < RT; ++mt) fr[0][mt] = buf_load4(f2r, 16 * lane, (t * RT + mt) * 1024);
-                        xv[0] = buf_load4(xr, 16 * lane, t * 1024);
-                    }
-#pragma unroll
-                    for (int s = 0; s < 2 * NPP; ++s) {
-                        const int cur = s & 1;
-                        if (s + 1 < 2 * NPP) {
-                            const int t = min(2 * pp0 + s + 1, PT - 1);
-#pragma unroll
-                            for (int mt = 0; mt < RT; ++mt) fr[cur ^ 1][mt] = buf_load4(f2r, 16 * lane, (t * RT + mt) * 1024);
-                            xv[cur ^ 1] = buf_load4(xr, 16 * lane, t * 1024);
-                        }
-                        floatx4 Az = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
-#pragma unroll
-                        for (int mt = 0; mt < RT; ++mt)
-#pragma unroll
-                            for (int v = 0; v < 4; ++v)
-                                if (4 * mt + v < KS) Az = mfma4(fr[cur][mt][v], z[mt][v], Az);
-                        const bool real = 2 * pp0 + s < PT;
-#pragma unroll
-                        for (int v = 0; v < 4; ++v)
-                            u[s][v] = real ? (tile_in ? xv[cur][v] : 0.0f) - Az[v] : u[s][v];
-                    }
-                }
-            }
-        }
-
+    // the result of the column's regression (quarter 0 writes it)
+    auto store = [&]() __attribute__((always_inline)) {
         if (part == 0 && j < jend) {
             if (valid) {
 #pragma unroll
@@ -1588,10 +1281,389 @@ l1_filter_kernel_quarter(FilterLaunch L)
                     }
             }
             if (iters && g == 0)
-                iters[j] = !valid ? RPCA_ITERS_BAD_INDEX
-                               : (bad ? RPCA_ITERS_NONFINITE : (done ? K : -L.c.max_iter));
+                iters[j] = !valid ? RPCA_ITERS_BAD_INDEX : (bad ? RPCA_ITERS_NONFINITE : K);
+        }
+    };
+
+    // Block steps from -2: the first refill (step -2) and norm sums (step -1)
+    // of every column, then step 0 of the first regressions.
+#pragma unroll 1
+    for (int k = -2;; ++k) {
+        const bool fl = (fresh_m >> lane) & 1;        // this column is set up in this step
+        floatx4 Wp[RT];
+        // g of this step, kept for the dual update (u, y do not change in between)
+        float gk[2 * NPP][4];
+        if constexpr (H) {
+            // partial w = A^T g over this quarter's pairs (K = 32 elements per
+            // MFMA); the quarter's fragments are read from LDS all at once, so
+            // their latency is paid once per contraction, not once per MFMA
+            halfx8 f1[NPP][RT];
+#pragma unroll
+            for (int q = 0; q < NPP; ++q)
+#pragma unroll
+                for (int mt = 0; mt < RT; ++mt) f1[q][mt] = H1[((pp0 + q) * RT + mt) * 64];
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int mt = 0; mt < RT; ++mt) Wp[mt] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+            for (int q = 0; q < NPP; ++q) {
+#pragma unroll
+                for (int h = 0; h < 2; ++h)
+#pragma unroll
+                    for (int v = 0; v < 4; ++v)
+                        gk[2 * q + h][v] =
+                            __builtin_amdgcn_fmed3f(fmaf(beta, u[2 * q + h][v], y[2 * q + h][v]), -1.0f, 1.0f);
+                const halfx8 gb = pack8(gk[2 * q], gk[2 * q + 1]);
+#pragma unroll
+                for (int mt = 0; mt < RT; ++mt) Wp[mt] = mfma16h(f1[q][mt], gb, Wp[mt]);
+            }
+        } else {
+            // partial w = A^T g on 16x16x4 FP32 MFMAs (K = 4 elements:
+            // 16 t + 4 g + v over g), two element tiles per batch of LDS
+            // reads.  A tile past PT (the last quarter's padding) reads the
+            // last real tile's fragments against g = 0 (its x is 0), adding 0.
+#pragma unroll
+            for (int mt = 0; mt < RT; ++mt) Wp[mt] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+            for (int s0 = 0; s0 < 2 * NPP; s0 += 2) {
+                floatx4 fa[2][RT];
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    const int t = min(2 * pp0 + s0 + h, PT - 1);
+#pragma unroll
+                    for (int mt = 0; mt < RT; ++mt) fa[h][mt] = A1[(t * RT + mt) * 64];
+                }
+                // (g is formed again for the dual update: registers, not VALU, bind here)
+                float gl[2][4];
+#pragma unroll
+                for (int h = 0; h < 2; ++h)
+#pragma unroll
+                    for (int v = 0; v < 4; ++v)
+                        gl[h][v] = __builtin_amdgcn_fmed3f(fmaf(beta, u[s0 + h][v], y[s0 + h][v]), -1.0f, 1.0f);
+#pragma unroll
+                for (int h = 0; h < 2; ++h)
+#pragma unroll
+                    for (int v = 0; v < 4; ++v)
+#pragma unroll
+                        for (int mt = 0; mt < RT; ++mt) Wp[mt] = mfma4(fa[h][mt][v], gl[h][v], Wp[mt]);
+            }
+        }
+        // partial w (a column being set up publishes its x norms in slots 0
+        // and NV - 1 instead, written in the refill step); the residual
+        // partial, or -1 for a stopped regression (0 in one lane while the
+        // slot still has regressions to take: the block goes on)
+        const bool pend = seq_pos(cursor) < jend;
+#pragma unroll
+        for (int mt = 0; mt < RT; ++mt)
+#pragma unroll
+            for (int v = 0; v < 4; ++v)
+                if (4 * mt + v < KS && (4 * mt + v > 0 || !fl)) mine[(4 * mt + v) * 64] = Wp[mt][v];
+        if (!fl) mine[(NV - 1) * 64] = done ? ((pend && lane == 0) ? 0.0f : -1.0f) : res_part;
+        __syncthreads();
+        floatx4 W[RT];
+        float res = all[(NV - 1) * 64];
+#pragma unroll
+        for (int mt = 0; mt < RT; ++mt)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) W[mt][v] = (4 * mt + v < KS) ? all[(4 * mt + v) * 64] : 0.0f;
+#pragma unroll
+        for (int w = 1; w < kWavesPerBlock; ++w) {
+#pragma unroll
+            for (int mt = 0; mt < RT; ++mt)
+#pragma unroll
+                for (int v = 0; v < 4; ++v)
+                    if (4 * mt + v < KS) W[mt][v] += all[(w * NV + 4 * mt + v) * 64];
+            res = fmaxf(res, all[(w * NV + NV - 1) * 64]);
+        }
+        // whether any column of the block was still moving (or being set up,
+        // or could take a regression) at this step's publication: the same in
+        // every wave
+        bool live_prev;
+        {
+            const float f0 = xch[(NV - 1) * 64 + lane];
+            if constexpr (TPB == 2) {
+                const float f1 = xch[(kWavesPerBlock * NV + NV - 1) * 64 + lane];
+                live_prev = __any(f0 >= 0.0f || f1 >= 0.0f);
+            } else {
+                live_prev = __any(f0 >= 0.0f);
+            }
+        }
+        res = colmax(res);
+        // the stopping test of the previous step (a column past its step 0);
+        // after max_iter steps a regression stops unconverged
+        if (inv_beta_prev > 0.0f && !done) {
+            ++K;
+            if (!(res * inv_beta_prev >= tol)) done = true;
+            else if (K >= L.c.max_iter) {
+                done = true;
+                K = -L.c.max_iter;
+            }
+        }
+        // columns being set up: their norms over the four quarters (slot 0
+        // holds each quarter's max, slot NV - 1 its sum of squares)
+        if (fresh_m != 0) {
+            float xinf = all[0], xx = all[(NV - 1) * 64];
+#pragma unroll
+            for (int w = 1; w < kWavesPerBlock; ++w) {
+                xinf = fmaxf(xinf, all[w * NV * 64]);
+                xx += all[(w * NV + NV - 1) * 64];
+            }
+            if (fl) {
+                beta = xx > 0.0f ? L.c.beta0_scale / sqrtf(xx) : 1.0f;
+                beta_bar = L.c.beta_max_scale * beta;
+                tol = L.c.eps * xinf;
+                bad = valid && nonfinite_norm(xx);     // x holds Inf / NaN
+                done = !(valid && xinf > 0.0f) || bad;
+                K = 0;
+                res_part = 0.0f;
+            }
+        }
+        __syncthreads();                              // every wave has read the partials
+        if (!live_prev) break;                        // the same in every wave of the block
+
+        const float inv_beta = __builtin_amdgcn_rcpf(beta);
+        // (a column set up in this step is frozen until its step 0)
+        const float ib = (done || fl) ? 0.0f : inv_beta;
+#pragma unroll
+        for (int mt = 0; mt < RT; ++mt)
+#pragma unroll
+            for (int v = 0; v < 4; ++v)
+                if (4 * mt + v < KS) z[mt][v] = fmaf(W[mt][v], ib, z[mt][v]);
+
+        if constexpr (H) {
+            // w as the FP16 B operand of v = A w, rank-tile pairs
+            halfx8 wb[RP];
+#pragma unroll
+            for (int rp = 0; rp < RP; ++rp) {
+                float lo[4], hi[4];
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    lo[v] = W[2 * rp][v];
+                    hi[v] = (2 * rp + 1 < RT) ? W[2 * rp + 1 < RT ? 2 * rp + 1 : 0][v] : 0.0f;
+                }
+                wb[rp] = pack8(lo, hi);
+            }
+            res_part = 0.0f;
+            // fragments of v = A w, read from LDS in batches of KB tile pairs
+            constexpr int KB = NPP >= 4 ? NPP / 2 : NPP;
+            halfx8 f2[2 * KB][RP];
+#pragma unroll
+            for (int s = 0; s < 2 * NPP; s += 2) {
+                if ((s / 2) % KB == 0) {
+#pragma unroll
+                    for (int b = 0; b < 2 * KB; ++b)
+#pragma unroll
+                        for (int rp = 0; rp < RP; ++rp)
+                            f2[b][rp] = (s + b < 2 * NPP) ? H2[((2 * pp0 + s + b) * RP + rp) * 64] : f2[b][rp];
+                    __builtin_amdgcn_sched_barrier(0);
+                }
+                const int sb = s % (2 * KB);
+                floatx4 Va = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
+                floatx4 Vb = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+                for (int rp = 0; rp < RP; ++rp) {
+                    Va = mfma16h(f2[sb][rp], wb[rp], Va);
+                    Vb = mfma16h(f2[sb + 1][rp], wb[rp], Vb);
+                }
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    const floatx4 Vt = h ? Vb : Va;
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) {
+                        const float yo = y[s + h][v];
+                        const float yn = gk[s + h][v] - Vt[v];
+                        res_part = fmaxf(res_part, fabsf(yn - yo));
+                        u[s + h][v] = fmaf(-Vt[v], ib, u[s + h][v]);
+                        y[s + h][v] = yn;
+                    }
+                }
+            }
+        } else {
+            // v = A w on 16x16x4 FP32 MFMAs from the refresh fragments in
+            // HBM (L2), one element tile at a time with the next tile's
+            // loads in flight under this tile's MFMAs; a tile past PT reads
+            // the last real tile and contributes 0
+            res_part = 0.0f;
+            const __amdgpu_buffer_rsrc_t f2r =
+                __builtin_amdgcn_make_buffer_rsrc(const_cast<float *>(f2glob), 0, PT * RT * 1024, kBufWord3);
+            floatx4 fb[2][RT];
+#pragma unroll
+            for (int mt = 0; mt < RT; ++mt) fb[0][mt] = buf_load4(f2r, 16 * lane, (min(2 * pp0, PT - 1) * RT + mt) * 1024);
+#pragma unroll
+            for (int s = 0; s < 2 * NPP; ++s) {
+                const int cur = s & 1;
+                if (s + 1 < 2 * NPP) {
+                    const int t = min(2 * pp0 + s + 1, PT - 1);
+#pragma unroll
+                    for (int mt = 0; mt < RT; ++mt) fb[cur ^ 1][mt] = buf_load4(f2r, 16 * lane, (t * RT + mt) * 1024);
+                }
+                floatx4 Vq = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+                for (int mt = 0; mt < RT; ++mt)
+#pragma unroll
+                    for (int v = 0; v < 4; ++v)
+                        if (4 * mt + v < KS) Vq = mfma4(fb[cur][mt][v], W[mt][v], Vq);
+                const bool real = 2 * pp0 + s < PT;
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const float Vt = real ? Vq[v] : 0.0f;
+                    const float yo = y[s][v];
+                    const float gs = __builtin_amdgcn_fmed3f(fmaf(beta, u[s][v], yo), -1.0f, 1.0f);
+                    const float yn = gs - Vt;
+                    res_part = fmaxf(res_part, fabsf(yn - yo));
+                    u[s][v] = fmaf(-Vt, ib, u[s][v]);
+                    y[s][v] = yn;
+                }
+            }
+        }
+        inv_beta_prev = fl ? 0.0f : inv_beta;
+        beta = fl ? beta : fminf(L.c.rho * beta, beta_bar);
+
+        // FP32 residual refinement: u = x - A z from the input, two element
+        // tiles at a time: their fragments and x are loaded from HBM (L2) in
+        // one batch before any of their MFMAs, so the load latency is paid
+        // once per batch (the compiler's own order waited once per rank tile)
+        if (L.c.refresh > 0 && ((k + 1) % L.c.refresh) == 0) {
+            if constexpr (H) {
+                constexpr int QB = 2;
+#pragma unroll
+                for (int s0 = 0; s0 < 2 * NPP; s0 += QB) {
+                    const int t0 = 2 * pp0 + s0;
+                    if (t0 < PT) {                    // wave-uniform
+                        floatx4 fa[QB][RT], xq[QB];
+                        const floatx4 zero4 = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+                        for (int h = 0; h < QB; ++h) {
+                            const bool on = s0 + h < 2 * NPP && t0 + h < PT;
+#pragma unroll
+                            for (int mt = 0; mt < RT; ++mt) fa[h][mt] = on ? F2[((t0 + h) * RT + mt) * 64] : zero4;
+                            xq[h] = on ? xslot[(t0 + h) * 64] : zero4;
+                        }
+                        __builtin_amdgcn_sched_barrier(0);
+                        floatx4 Az[QB];
+#pragma unroll
+                        for (int h = 0; h < QB; ++h) Az[h] = zero4;
+#pragma unroll
+                        for (int mt = 0; mt < RT; ++mt)
+#pragma unroll
+                            for (int v = 0; v < 4; ++v)
+                                if (4 * mt + v < KS)
+#pragma unroll
+                                    for (int h = 0; h < QB; ++h) Az[h] = mfma4(fa[h][mt][v], z[mt][v], Az[h]);
+#pragma unroll
+                        for (int h = 0; h < QB; ++h) {
+                            if (s0 + h < 2 * NPP && t0 + h < PT) {
+#pragma unroll
+                                for (int v = 0; v < 4; ++v) u[s0 + h][v] = xq[h][v] - Az[h][v];
+                            }
+                        }
+                    }
+                }
+            } else {
+                // one element tile at a time, the next tile's fragments and x
+                // in flight under this tile's MFMAs (x of an idle tile: the
+                // first tile's slot, never used)
+                const __amdgpu_buffer_rsrc_t f2r =
+                    __builtin_amdgcn_make_buffer_rsrc(const_cast<float *>(f2glob), 0, PT * RT * 1024, kBufWord3);
+                const __amdgpu_buffer_rsrc_t xr = __builtin_amdgcn_make_buffer_rsrc(
+                    xslot_base, 0, PT * 1024, kBufWord3);
+                floatx4 fr[2][RT], xv[2];
+                {
+                    const int t = min(2 * pp0, PT - 1);
+#pragma unroll
+                    for (int mt = 0; mt < RT; ++mt) fr[0][mt] = buf_load4(f2r, 16 * lane, (t * RT + mt) * 1024);
+                    xv[0] = buf_load4(xr, 16 * lane, t * 1024);
+                }
+#pragma unroll
+                for (int s = 0; s < 2 * NPP; ++s) {
+                    const int cur = s & 1;
+                    if (s + 1 < 2 * NPP) {
+                        const int t = min(2 * pp0 + s + 1, PT - 1);
+#pragma unroll
+                        for (int mt = 0; mt < RT; ++mt) fr[cur ^ 1][mt] = buf_load4(f2r, 16 * lane, (t * RT + mt) * 1024);
+                        xv[cur ^ 1] = buf_load4(xr, 16 * lane, t * 1024);
+                    }
+                    floatx4 Az = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+                    for (int mt = 0; mt < RT; ++mt)
+#pragma unroll
+                        for (int v = 0; v < 4; ++v)
+                            if (4 * mt + v < KS) Az = mfma4(fr[cur][mt][v], z[mt][v], Az);
+                    const bool real = 2 * pp0 + s < PT;
+#pragma unroll
+                    for (int v = 0; v < 4; ++v)
+                        u[s][v] = real ? xv[cur][v] - Az[v] : u[s][v];
+                }
+            }
+        }
+        if (fresh_m != 0) {
+            // the dual state of a column set up in this step starts at 0
+#pragma unroll
+            for (int s = 0; s < 2 * NPP; ++s)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) y[s][v] = fl ? 0.0f : y[s][v];
+            res_part = fl ? 0.0f : res_part;
+            fresh_m = 0;
+        }
+
+        // refill point: stopped columns store their result and take the next
+        // regressions of the sequence, in column order
+        if ((k + 2) % RA == 0 && pend) {
+            const uint32_t cm = (uint32_t)(__ballot(done) & 0xFFFFull);   // lanes 0..15: one per column
+            if (cm != 0) {                            // wave-uniform
+                const bool fr = (cm >> c) & 1;
+                if (fr) store();
+                const int64_t pos = seq_pos(cursor + __popc(cm & ((1u << c) - 1u)));
+                float xinf = 0.0f, xx = 0.0f;
+                if (fr) {
+                    j = pos < jend ? pos : kNone;
+                    valid = j < jend;
+                    roff = 0;
+                    if (valid) {
+                        const int64_t ri = reg_idx[j];
+                        if (ri >= 0 && ri < reg_bound) roff = ri * reg_stride;
+                        else valid = false;
+                    }
+#pragma unroll
+                    for (int mt = 0; mt < RT; ++mt) z[mt] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
+                    // every load issued before the first use (an element outside
+                    // the block reads M[0] and is replaced by 0): one memory
+                    // latency per refill
+#pragma unroll
+                    for (int s = 0; s < 2 * NPP; ++s)
+#pragma unroll
+                        for (int v = 0; v < 4; ++v) {
+                            const int64_t e = eoff[16 * (2 * pp0 + s) + 4 * g + v];
+                            const bool ok = valid && e >= 0;
+                            const int64_t off = ok ? roff + (TPB == 2 ? e * elem_stride : e) : 0;
+                            const float x = M[off];
+                            u[s][v] = ok ? x : 0.0f;
+                        }
+#pragma unroll
+                    for (int s = 0; s < 2 * NPP; ++s) {
+                        const int t = 2 * pp0 + s;
+#pragma unroll
+                        for (int v = 0; v < 4; ++v) {
+                            y[s][v] = 0.0f;
+                            xinf = fmaxf(xinf, fabsf(u[s][v]));
+                            xx = fmaf(u[s][v], u[s][v], xx);
+                        }
+                        if (t < PT) xslot[t * 64] = floatx4{u[s][0], u[s][1], u[s][2], u[s][3]};
+                    }
+                }
+                // the column's norms over this quarter, published for the next step
+                xinf = colmax(xinf);
+                xx = colsum(xx);
+                if (fr) {
+                    mine[0] = xinf;
+                    mine[(NV - 1) * 64] = xx;
+                }
+                fresh_m = __ballot(fr);
+                cursor += __popc(cm);
+            }
         }
     }
+    store();                                          // the regressions still held
 }
 
 
