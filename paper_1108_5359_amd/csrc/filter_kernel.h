@@ -1061,18 +1061,19 @@ l1_filter_kernel_f16(FilterLaunch L)
 // u, y per lane (256 at p = 512: the whole register file, so the tile kernel
 // spills, and the basis fragments of a contraction cannot be kept in flight).
 // Here four waves serve one 16-regression tile together, each holding a
-// quarter of the element-tile pairs; a workgroup serves one or two tiles
-// (TPB, below) that step together.  The workgroup stages the
-// FP16 basis fragments in LDS once and then takes the tiles of its side in
-// turn (its index, plus the side's workgroup count, ...), so the staging is
-// paid once per workgroup, not once per tile.  Per step each wave contracts its
-// quarter (w = A^T g) and publishes the partial w and the previous step's
-// residual partial in LDS; after a barrier every wave adds the four partials
-// in quarter order (identical w and z in all four waves, and the same bits for
-// a regression wherever it sits), and a second barrier frees the buffer.  The
-// stopping test of a step is taken one step later; a stopped regression only
-// stops moving z and u, and a finished tile next to a moving one steps on
-// frozen.  The refresh reads its FP32 fragments from HBM.  The same shape
+// quarter of the element-tile pairs; a workgroup serves one or two tile
+// slots (TPB, below) that step together.  The workgroup stages the FP16
+// basis fragments in LDS once; each slot then serves the regressions of its
+// tiles (its index, plus the side's workgroup count, ...) as one sequence,
+// one regression per column at a time, a stopped regression's column taking
+// the next one at the next refill point (one refresh period apart).  Per step
+// each wave contracts its quarter (w = A^T g) and publishes the partial w and
+// the previous step's residual partial in LDS; after a barrier every wave
+// adds the four partials in quarter order (identical w and z in all four
+// waves, and the same bits for a regression wherever it sits), and a second
+// barrier frees the buffer.  The stopping test of a step is taken one step
+// later; a stopped regression only stops moving z and u until its column is
+// refilled.  The refresh reads its FP32 fragments from HBM.  The same shape
 // serves the FP32 form beyond the FP32 tile classes (p > 304): the basis is
 // staged in LDS as FP32 for w = A^T g, and v = A w reads the refresh
 // fragments, one element tile ahead of its 16x16x4 FP32 MFMAs.
