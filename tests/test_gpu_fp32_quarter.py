@@ -187,3 +187,53 @@ def test_fp32_c3_full_size_sampled(R, ctx):
     assert eL <= REL_TOL and eS <= REL_TOL
     L0 = (A0[rows] * B0[cols]).sum(1)
     assert relF(Lg, L0) <= 1e-5
+
+
+# Enough regressions (10 000 on one side) that every tile slot serves a long
+# sequence and refills its columns: the same seven regressions repeated over
+# the sequence land in different columns and start at different refill points,
+# and must give the same bits and step counts each time; zero regressions stop
+# at once (count 0, z = 0) and free their column; with an iteration cap every
+# regression stops at the cap (count -cap, z = the oracle's after cap steps).
+@pytest.mark.parametrize("precision", [0, 1])
+def test_quarter_refill_repeats_zeros_caps(R, ctx, precision):
+    m, n, r = 2600, 2333, 41
+    pr, I, J, res = small_case(m, n, r, 0.05, 48)
+    Jc = oracle.complement(J, n)
+    k = res.U.shape[1]
+    o = R.rpca_opts_default(precision=precision)
+    pick = Jc[[5, 99, 400, 800, 1200, 1500, 1900]]
+    cols = np.tile(pick, 1429)                        # 10 003 regressions
+    zero = np.arange(3, cols.size, 977)               # some of them all-zero
+    M0 = pr.M.copy(order="F")
+    zcol = np.setdiff1d(Jc, pick)[:zero.size]
+    M0[np.ix_(I, zcol)] = 0.0
+    cols[zero] = zcol
+    pr0 = synth.Problem(M=M0, A0=pr.A0, B0=pr.B0, support=None, m=m, n=n, r=r, seed=0)
+    say(f"quarter-tile refill: repeats, zeros (precision={precision})")
+    st, Qt, it = _filter_cols_gpu(R, ctx, pr0, I, cols, res.U, k, opts=o)
+    assert st == R.RPCA_OK, ctx.last_error()
+    assert (it[zero] == 0).all() and not Qt[:, zero].any()
+    rep = np.setdiff1d(np.arange(cols.size), zero)
+    first = {}
+    for i in rep:
+        a = first.setdefault(int(cols[i]), i)
+        assert it[i] == it[a] and np.array_equal(Qt[:, i], Qt[:, a]), (i, a)
+    Zo, Ko = oracle.alg1_batch(pr.M[np.ix_(I, pick)].astype(np.float64), res.U)
+    Qp = np.stack([Qt[:, first[int(c)]] for c in pick], axis=1)
+    assert relF(res.U @ Qp, res.U @ Zo) <= REL_TOL
+    if precision == 0:
+        base = Jc[:1200]
+        capcols = np.tile(base, 9)                    # 10 800 regressions
+        for cap in (1, 3, 9, 12):                   # below every step count of these regressions
+            say(f"quarter-tile refill: max_iter={cap}")
+            st, Qt, it = _filter_cols_gpu(R, ctx, pr, I, capcols, res.U, k,
+                                          opts=R.rpca_opts_default(precision=0, filt_max_iter=cap))
+            assert st == R.RPCA_OK, ctx.last_error()
+            Zo, Ko = oracle.alg1_batch(pr.M[np.ix_(I, base)].astype(np.float64), res.U,
+                                       oracle.Alg1Params(max_iter=cap))
+            assert (Ko == -cap).all()
+            assert np.array_equal(it, np.tile(Ko, 9)), cap
+            for rpt in range(9):
+                sl = slice(rpt * base.size, (rpt + 1) * base.size)
+                assert relF(res.U @ Qt[:, sl], res.U @ Zo) <= REL_TOL, (cap, rpt)
