@@ -1140,6 +1140,11 @@ l1_filter_kernel_quarter(FilterLaunch L)
     constexpr int RT = Sh::RT, RP = Sh::RP, NPP = Sh::NPP, PPA = Sh::PPA, TA = Sh::TA;
     constexpr int NV = Sh::NV;
     constexpr int NT = TPB * kWavesPerBlock * 64;    // threads of the workgroup
+    // FP32 mode: when the last rank tile holds a single quad of ranks (KS =
+    // 4 RT - 3), its part of w = A^T g runs on v_mfma_f32_4x4x1_16b_f32 (a
+    // quarter of the cycles of the padded 16x16x4 tile)
+    constexpr int LT = RT - 1;
+    constexpr bool kQ1 = !H && KS == 4 * LT + 1;
     // element index of the gathered x: offset (TPB = 1) or 32-bit row/column
     // index, scaled by the stride when read (TPB = 2)
     using EIdx = typename std::conditional<TPB == 2, int32_t, int64_t>::type;
@@ -1203,7 +1208,10 @@ l1_filter_kernel_quarter(FilterLaunch L)
             const int v = idx & 3, ln = (idx >> 2) & 63, tm = idx >> 8;
             const int t = tm / RT, mt = tm - t * RT;
             const int g = ln >> 4, c = ln & 15;
-            const int e = 16 * t + 4 * g + v, k = 16 * mt + 4 * (c & 3) + (c >> 2);
+            // (4x4x1 quad: lane (g, c) is row c % 4 of block 4 g + c / 4, whose
+            // K-step is element 16 t + 4 g + v)
+            const int e = 16 * t + 4 * g + v;
+            const int k = (kQ1 && mt == LT) ? 16 * LT + (c & 3) : 16 * mt + 4 * (c & 3) + (c >> 2);
             a1[idx] = (e < p && k < r) ? (float)A[e + (int64_t)k * lda] : 0.0f;
         }
     }
@@ -1346,7 +1354,9 @@ l1_filter_kernel_quarter(FilterLaunch L)
 #pragma unroll
                     for (int v = 0; v < 4; ++v)
 #pragma unroll
-                        for (int mt = 0; mt < RT; ++mt) Wp[mt] = mfma4(fa[h][mt][v], gl[h][v], Wp[mt]);
+                        for (int mt = 0; mt < RT; ++mt)
+                            Wp[mt] = (kQ1 && mt == LT) ? mfma4x4(fa[h][mt][v], gl[h][v], Wp[mt])
+                                                       : mfma4(fa[h][mt][v], gl[h][v], Wp[mt]);
             }
         }
         // partial w (a column being set up publishes its x norms in slots 0
@@ -1354,6 +1364,12 @@ l1_filter_kernel_quarter(FilterLaunch L)
         // partial, or -1 for a stopped regression (0 in one lane while the
         // slot still has regressions to take: the block goes on)
         const bool pend = seq_pos(cursor) < jend;
+        if constexpr (kQ1) {
+            // quad part: lane (g, c) register i holds rank 16 LT + i of regression
+            // c over this lane's elements; summed over the four g lanes and
+            // scattered, lane (g, c) holds rank 16 LT + g: the 16x16 layout
+            Wp[LT][0] = colsum4_scatter(Wp[LT][0], Wp[LT][1], Wp[LT][2], Wp[LT][3]);
+        }
 #pragma unroll
         for (int mt = 0; mt < RT; ++mt)
 #pragma unroll
