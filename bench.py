@@ -1170,7 +1170,7 @@ def run_paper(args, R, torch):
                            wall_s=round(time.perf_counter() - t_start, 1))}
 
 
-# =========================================================================== driver
+# =========================================================================== entry point
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
