@@ -237,3 +237,24 @@ def test_quarter_refill_repeats_zeros_caps(R, ctx, precision):
             for rpt in range(9):
                 sl = slice(rpt * base.size, (rpt + 1) * base.size)
                 assert relF(res.U @ Qt[:, sl], res.U @ Zo) <= REL_TOL, (cap, rpt)
+
+
+def test_form_table_and_size_limit(R, ctx):
+    # which kernel a call takes, by p and precision form; p = 513 is beyond
+    # every built class and is refused before any launch
+    import torch
+    f = lambda p, r, prec: R.rpca_filter_form(ctx, p, r, 20000, R.rpca_opts_default(precision=prec))
+    assert f(304, 20, 0) in (1, 2) and f(305, 20, 0) == FORM_QUARTER32
+    assert f(512, 64, 0) == FORM_QUARTER32 and f(410, 1, 0) == FORM_QUARTER32
+    assert f(500, 50, 1) == 0 and f(300, 30, 1) == 0
+    assert f(40, 4, 1) in (1, 2)                      # below 48 elements the precision form stays FP32
+    m, n, r, p = 700, 300, 5, 513
+    pr = synth.lowrank_plus_sparse(m, n, r, factor_std=np.sqrt(1.0 / m), sparsity=0.05, values="pm1", seed=3)
+    I, J = synth.seed_indices(m, n, p, 50, seed=3)
+    U, _ = np.linalg.qr(pr.A0[I])
+    cols = oracle.complement(J, n)[:10]
+    for prec in (0, 1):
+        say(f"filter beyond the classes: p = {p}, precision = {prec}")
+        with pytest.raises(R.RpcaError) as e:
+            _filter_cols_gpu(R, ctx, pr, I, cols, U, r, opts=R.rpca_opts_default(precision=prec))
+        assert e.value.status == R.RPCA_ERR_UNSUPPORTED
