@@ -12,17 +12,17 @@
 namespace seedj {
 
 constexpr int kThreads = 256;
-constexpr int kG = 8;                       // lanes per column pair
+constexpr int kG = 4;                       // lanes per column pair (every pair of an 80-column
+                                            // round in one pass of the workgroup)
 constexpr int kGroups = kThreads / kG;      // pairs in flight
 constexpr int kMaxSweeps = 40;
-constexpr double kJacobiEps = 1e-15;        // |x_i . x_j| <= eps ||x_i|| ||x_j|| counts as orthogonal
+constexpr double kJacobiEps = 1e-15;        // |x_i . x_j| <= eps ||X||_F max(||x_i||, ||x_j||): orthogonal
 constexpr int kColdEvery = 64;              // ALM steps between Jacobi starts from the identity
 
 __device__ __forceinline__ double group_sum(double v)
 {
     v += __shfl_xor(v, 1);
     v += __shfl_xor(v, 2);
-    v += __shfl_xor(v, 4);
     return v;
 }
 
@@ -73,6 +73,17 @@ __device__ inline void jacobi_svd(double *X, double *V, int n1, int n2, int *fla
     const int m2 = n2 + (n2 & 1);
     const int npairs = m2 / 2;
     const int grp = tid / kG, gl = tid % kG;
+    // ||X||_F, which the rotations keep.  A pair counts as orthogonal once
+    // its inner product is below eps ||X||_F times its larger norm: rotating
+    // it could then move a singular value by no more than about eps ||X||_F,
+    // the absolute accuracy of a backward-stable SVD (the SVT needs no more).
+    // Measured against the pair's own norms (eps ||x_i|| ||x_j||, high
+    // relative accuracy for the smallest singular values too) the sweeps went
+    // on longer for the many small columns of the SVT input.
+    __shared__ double fro_red[4];
+    double f2 = 0.0;
+    for (int t = tid; t < n1 * n2; t += kThreads) f2 = fma(X[t], X[t], f2);
+    const double fro2 = block_sum(f2, fro_red);
     __syncthreads();
     for (int sweep = 0; sweep < kMaxSweeps; ++sweep) {
         if (tid == 0) *flag = 0;
@@ -96,7 +107,7 @@ __device__ inline void jacobi_svd(double *X, double *V, int n1, int n2, int *fla
                     al = group_sum(al);
                     be = group_sum(be);
                     ga = group_sum(ga);
-                    if (ga * ga > (kJacobiEps * kJacobiEps) * (al * be)) {
+                    if (ga * ga > (kJacobiEps * kJacobiEps) * (fro2 * fmax(al, be))) {
                         // t = tan of the rotation: the root of smaller modulus of
                         // t^2 + 2 zeta t - 1 = 0, zeta = (be - al) / (2 ga), written
                         // with one division: sign(zeta) |2 ga| / (|d| + sqrt(d^2 + 4 ga^2))
