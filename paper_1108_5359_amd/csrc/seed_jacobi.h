@@ -12,17 +12,26 @@
 namespace seedj {
 
 constexpr int kThreads = 256;
-constexpr int kG = 4;                       // lanes per column pair (every pair of an 80-column
-                                            // round in one pass of the workgroup)
-constexpr int kGroups = kThreads / kG;      // pairs in flight
+constexpr int kG = 8;                       // lanes per column (column norms)
+constexpr int kGroups = kThreads / kG;      // columns in flight (column norms)
 constexpr int kMaxSweeps = 40;
-constexpr double kJacobiEps = 1e-15;        // |x_i . x_j| <= eps ||X||_F max(||x_i||, ||x_j||): orthogonal
+constexpr double kJacobiEps = 1e-15;        // orthogonality threshold of a column pair
 constexpr int kColdEvery = 64;              // ALM steps between Jacobi starts from the identity
 
 __device__ __forceinline__ double group_sum(double v)
 {
     v += __shfl_xor(v, 1);
     v += __shfl_xor(v, 2);
+    v += __shfl_xor(v, 4);
+    return v;
+}
+
+// Sum over aligned groups of g = 4 or 8 lanes (g uniform over the workgroup).
+__device__ __forceinline__ double group_sum_n(double v, int g)
+{
+    v += __shfl_xor(v, 1);
+    v += __shfl_xor(v, 2);
+    if (g == 8) v += __shfl_xor(v, 4);
     return v;
 }
 
@@ -65,49 +74,56 @@ __device__ __forceinline__ void tournament_pair(int k, int pr, int m2, int &i, i
 // the rotations accumulated into V (n2 x n2): set to the identity first when
 // `cold`, else X already holds W V for the V of a previous step (warm start:
 // its columns are nearly orthogonal, so few sweeps are needed).
-__device__ inline void jacobi_svd(double *X, double *V, int n1, int n2, int *flag, bool cold)
+//
+// G lanes per pair (4 or 8).  With `absolute`, a pair counts as orthogonal
+// once its inner product is below eps ||X||_F times its larger norm: rotating
+// it could then move a singular value by no more than about eps ||X||_F, the
+// absolute accuracy of a backward-stable SVD, which is all an SVT needs.
+// Otherwise the test is against the pair's own norms (eps ||x_i|| ||x_j||:
+// high relative accuracy for the small singular values too, at the price of
+// more sweeps where the matrix has many small columns).
+__device__ inline void jacobi_svd(double *X, double *V, int n1, int n2, int *flag, bool cold,
+                                  int G = 8, bool absolute = false)
 {
     const int tid = threadIdx.x;
     if (cold)
         for (int t = tid; t < n2 * n2; t += kThreads) V[t] = (t % n2 == t / n2) ? 1.0 : 0.0;
     const int m2 = n2 + (n2 & 1);
     const int npairs = m2 / 2;
-    const int grp = tid / kG, gl = tid % kG;
-    // ||X||_F, which the rotations keep.  A pair counts as orthogonal once
-    // its inner product is below eps ||X||_F times its larger norm: rotating
-    // it could then move a singular value by no more than about eps ||X||_F,
-    // the absolute accuracy of a backward-stable SVD (the SVT needs no more).
-    // Measured against the pair's own norms (eps ||x_i|| ||x_j||, high
-    // relative accuracy for the smallest singular values too) the sweeps went
-    // on longer for the many small columns of the SVT input.
-    __shared__ double fro_red[4];
-    double f2 = 0.0;
-    for (int t = tid; t < n1 * n2; t += kThreads) f2 = fma(X[t], X[t], f2);
-    const double fro2 = block_sum(f2, fro_red);
+    const int groups = kThreads / G;
+    const int grp = tid / G, gl = tid % G;
+    // ||X||_F, which the rotations keep (absolute test only)
+    double fro2 = 0.0;
+    if (absolute) {
+        __shared__ double fro_red[4];
+        double f2 = 0.0;
+        for (int t = tid; t < n1 * n2; t += kThreads) f2 = fma(X[t], X[t], f2);
+        fro2 = block_sum(f2, fro_red);
+    }
     __syncthreads();
     for (int sweep = 0; sweep < kMaxSweeps; ++sweep) {
         if (tid == 0) *flag = 0;
         __syncthreads();
         for (int round = 0; round < m2 - 1; ++round) {
-            for (int base = 0; base < npairs; base += kGroups) {
+            for (int base = 0; base < npairs; base += groups) {
                 const int pr = base + grp;
                 int i = 0, j = 0;
                 if (pr < npairs) tournament_pair(round, pr, m2, i, j);
-                const bool live = pr < npairs && j < n2;     // same for the 8 lanes of a group
+                const bool live = pr < npairs && j < n2;     // same for the G lanes of a group
                 if (live) {
                     double al = 0.0, be = 0.0, ga = 0.0;
                     const double *xi = X + (int64_t)i * n1, *xj = X + (int64_t)j * n1;
 #pragma unroll 4
-                    for (int e = gl; e < n1; e += kG) {
+                    for (int e = gl; e < n1; e += G) {
                         const double a = xi[e], b = xj[e];
                         al = fma(a, a, al);
                         be = fma(b, b, be);
                         ga = fma(a, b, ga);
                     }
-                    al = group_sum(al);
-                    be = group_sum(be);
-                    ga = group_sum(ga);
-                    if (ga * ga > (kJacobiEps * kJacobiEps) * (fro2 * fmax(al, be))) {
+                    al = group_sum_n(al, G);
+                    be = group_sum_n(be, G);
+                    ga = group_sum_n(ga, G);
+                    if (ga * ga > (kJacobiEps * kJacobiEps) * (absolute ? fro2 * fmax(al, be) : al * be)) {
                         // t = tan of the rotation: the root of smaller modulus of
                         // t^2 + 2 zeta t - 1 = 0, zeta = (be - al) / (2 ga), written
                         // with one division: sign(zeta) |2 ga| / (|d| + sqrt(d^2 + 4 ga^2))
@@ -117,14 +133,14 @@ __device__ inline void jacobi_svd(double *X, double *V, int n1, int n2, int *fla
                         const double c = 1.0 / sqrt(fma(t, t, 1.0)), s = c * t;
                         double *wi = X + (int64_t)i * n1, *wj = X + (int64_t)j * n1;
     #pragma unroll 4
-                    for (int e = gl; e < n1; e += kG) {
+                    for (int e = gl; e < n1; e += G) {
                             const double a = wi[e], b = wj[e];
                             wi[e] = c * a - s * b;
                             wj[e] = s * a + c * b;
                         }
                         double *vi = V + (int64_t)i * n2, *vj = V + (int64_t)j * n2;
 #pragma unroll 4
-                        for (int e = gl; e < n2; e += kG) {
+                        for (int e = gl; e < n2; e += G) {
                             const double a = vi[e], b = vj[e];
                             vi[e] = c * a - s * b;
                             vj[e] = s * a + c * b;

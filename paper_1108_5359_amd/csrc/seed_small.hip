@@ -32,6 +32,11 @@ namespace seedk {
 using namespace seedj;
 
 constexpr int64_t kMaxElems = 80 * 80;      // largest seed block (p q) of this route
+// Jacobi of the SVT: 4 lanes per column pair (the 40 pairs of an 80-column
+// round in one pass; shorter lane sums than with 8) and the absolute
+// orthogonality test (c4's 256 seeds: 639 -> 468 ms, 8.4 -> 7.2 sweeps per
+// ALM step on the median, the same ALM step counts and L^s)
+constexpr int kPairLanes = 4;
 
 struct SmallSeedJob {
     const float *M;
@@ -139,7 +144,7 @@ seed_small_kernel(const SmallSeedJob *__restrict__ jobs, SmallSeedConsts C)
         else X[b + (int64_t)a * q] = Ms[t];
     }
     __syncthreads();
-    jacobi_svd(X, V, n1, n2, &flag, true);
+    jacobi_svd(X, V, n1, n2, &flag, true, kPairLanes, true);
     column_norms(X, n1, n2, sig);
     double norm2 = 0.0;
     for (int c = 0; c < n2; ++c) norm2 = fmax(norm2, sig[c]);
@@ -163,7 +168,7 @@ seed_small_kernel(const SmallSeedJob *__restrict__ jobs, SmallSeedConsts C)
         const bool cold = (k - 1) % kColdEvery == 0;
         if (cold) load_x(X, Ms, S, Y, p, q, tall, 1.0 / mu);
         else load_x_rotated(X, V, stg, Ms, S, Y, p, q, tall, 1.0 / mu);
-        jacobi_svd(X, V, n1, n2, &flag, cold);
+        jacobi_svd(X, V, n1, n2, &flag, cold, kPairLanes, true);
         column_norms(X, n1, n2, sig);
         const double tau = 1.0 / mu;
         for (int c = tid; c < n2; c += kThreads) wt[c] = sig[c] > tau ? 1.0 - tau / sig[c] : 0.0;
