@@ -18,14 +18,6 @@ constexpr int kMaxSweeps = 40;
 constexpr double kJacobiEps = 1e-15;        // orthogonality threshold of a column pair
 constexpr int kColdEvery = 64;              // ALM steps between Jacobi starts from the identity
 
-__device__ __forceinline__ double group_sum(double v)
-{
-    v += __shfl_xor(v, 1);
-    v += __shfl_xor(v, 2);
-    v += __shfl_xor(v, 4);
-    return v;
-}
-
 // Sum over aligned groups of g = 4 or 8 lanes (g uniform over the workgroup).
 __device__ __forceinline__ double group_sum_n(double v, int g)
 {
@@ -34,6 +26,9 @@ __device__ __forceinline__ double group_sum_n(double v, int g)
     if (g == 8) v += __shfl_xor(v, 4);
     return v;
 }
+
+// Sum over the kG lanes of a column group.
+__device__ __forceinline__ double group_sum(double v) { return group_sum_n(v, kG); }
 
 // Sum / max over the workgroup (every thread gets the result).
 __device__ inline double block_sum(double v, double *red)
