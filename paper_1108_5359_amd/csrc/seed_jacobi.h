@@ -86,6 +86,11 @@ __device__ inline void jacobi_svd(double *X, double *V, int n1, int n2, int *fla
     const int m2 = n2 + (n2 & 1);
     const int npairs = m2 / 2;
     const int groups = kThreads / G;
+    // 16-byte accesses where every column starts 16-byte aligned (X and V
+    // aligned, even n1 and n2); with 4 lanes per pair only, which keeps the
+    // 8-lane callers' code and results as they were
+    const bool pairs2 = G == 4 && (n1 & 1) == 0 && (n2 & 1) == 0 &&
+                        ((reinterpret_cast<uintptr_t>(X) | reinterpret_cast<uintptr_t>(V)) & 15) == 0;
     const int grp = tid / G, gl = tid % G;
     // ||X||_F, which the rotations keep (absolute test only)
     double fro2 = 0.0;
@@ -108,12 +113,27 @@ __device__ inline void jacobi_svd(double *X, double *V, int n1, int n2, int *fla
                 if (live) {
                     double al = 0.0, be = 0.0, ga = 0.0;
                     const double *xi = X + (int64_t)i * n1, *xj = X + (int64_t)j * n1;
+                    if (pairs2) {
+                        // two adjacent elements per lane and load (16-byte LDS accesses)
+#pragma unroll 2
+                        for (int e = 2 * gl; e < n1; e += 2 * G) {
+                            const double2 a = *reinterpret_cast<const double2 *>(xi + e);
+                            const double2 b = *reinterpret_cast<const double2 *>(xj + e);
+                            al = fma(a.x, a.x, al);
+                            be = fma(b.x, b.x, be);
+                            ga = fma(a.x, b.x, ga);
+                            al = fma(a.y, a.y, al);
+                            be = fma(b.y, b.y, be);
+                            ga = fma(a.y, b.y, ga);
+                        }
+                    } else {
 #pragma unroll 4
-                    for (int e = gl; e < n1; e += G) {
-                        const double a = xi[e], b = xj[e];
-                        al = fma(a, a, al);
-                        be = fma(b, b, be);
-                        ga = fma(a, b, ga);
+                        for (int e = gl; e < n1; e += G) {
+                            const double a = xi[e], b = xj[e];
+                            al = fma(a, a, al);
+                            be = fma(b, b, be);
+                            ga = fma(a, b, ga);
+                        }
                     }
                     al = group_sum_n(al, G);
                     be = group_sum_n(be, G);
@@ -127,18 +147,35 @@ __device__ inline void jacobi_svd(double *X, double *V, int n1, int n2, int *fla
                         const double t = sg * fabs(g2) / (fabs(d) + sqrt(fma(d, d, g2 * g2)));
                         const double c = 1.0 / sqrt(fma(t, t, 1.0)), s = c * t;
                         double *wi = X + (int64_t)i * n1, *wj = X + (int64_t)j * n1;
-    #pragma unroll 4
-                    for (int e = gl; e < n1; e += G) {
-                            const double a = wi[e], b = wj[e];
-                            wi[e] = c * a - s * b;
-                            wj[e] = s * a + c * b;
-                        }
                         double *vi = V + (int64_t)i * n2, *vj = V + (int64_t)j * n2;
+                        if (pairs2) {
+#pragma unroll 2
+                            for (int e = 2 * gl; e < n1; e += 2 * G) {
+                                const double2 a = *reinterpret_cast<const double2 *>(wi + e);
+                                const double2 b = *reinterpret_cast<const double2 *>(wj + e);
+                                *reinterpret_cast<double2 *>(wi + e) = double2{c * a.x - s * b.x, c * a.y - s * b.y};
+                                *reinterpret_cast<double2 *>(wj + e) = double2{s * a.x + c * b.x, s * a.y + c * b.y};
+                            }
+#pragma unroll 2
+                            for (int e = 2 * gl; e < n2; e += 2 * G) {
+                                const double2 a = *reinterpret_cast<const double2 *>(vi + e);
+                                const double2 b = *reinterpret_cast<const double2 *>(vj + e);
+                                *reinterpret_cast<double2 *>(vi + e) = double2{c * a.x - s * b.x, c * a.y - s * b.y};
+                                *reinterpret_cast<double2 *>(vj + e) = double2{s * a.x + c * b.x, s * a.y + c * b.y};
+                            }
+                        } else {
 #pragma unroll 4
-                        for (int e = gl; e < n2; e += G) {
-                            const double a = vi[e], b = vj[e];
-                            vi[e] = c * a - s * b;
-                            vj[e] = s * a + c * b;
+                            for (int e = gl; e < n1; e += G) {
+                                const double a = wi[e], b = wj[e];
+                                wi[e] = c * a - s * b;
+                                wj[e] = s * a + c * b;
+                            }
+#pragma unroll 4
+                            for (int e = gl; e < n2; e += G) {
+                                const double a = vi[e], b = vj[e];
+                                vi[e] = c * a - s * b;
+                                vj[e] = s * a + c * b;
+                            }
                         }
                         if (gl == 0) *flag = 1;
                     }

@@ -98,7 +98,7 @@ __device__ void load_x_rotated(double *X, const double *V, double *stg, const do
 __global__ void __launch_bounds__(kThreads)
 seed_small_kernel(const SmallSeedJob *__restrict__ jobs, SmallSeedConsts C)
 {
-    extern __shared__ double lds[];
+    extern __shared__ __align__(16) double lds[];
     __shared__ double red[4];
     __shared__ int flag;
     const SmallSeedJob &J = jobs[blockIdx.x];
