@@ -1213,7 +1213,7 @@ def main():
                          "FETCH_SIZE / WRITE_SIZE counters of a profiled run)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
+        print(f"bench.py: this library runs on one GPU only (asked for --gpus {args.gpus}); "
               "the method shards by regressions and row blocks, see the design notes",
               file=sys.stderr)
         sys.exit(2)
