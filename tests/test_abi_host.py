@@ -92,3 +92,21 @@ def test_context_without_device_fails_cleanly(R):
     with pytest.raises(R.RpcaError) as e:
         R.Context(0)
     assert e.value.status == R.RPCA_ERR_DEVICE
+
+
+def test_committed_tuning_applies_to_the_library(R):
+    # The autotuner's results file: every tuned field is a field of
+    # rpca_batch_tuning, each value lies in the grid the tuner searched, and
+    # the tuned choice was at least as fast as the defaults it was timed against.
+    import json
+    from paper_1108_5359_amd import autotune
+    tuned = autotune.load()
+    assert tuned, "tuning_mi355x.json holds no batch_tuning"
+    t = R.rpca_batch_tuning_default(**tuned)
+    for k, v in tuned.items():
+        assert getattr(t, k) == v
+    assert (tuned["lane_split2_p"], tuned["lane_split4_p"]) in [tuple(x) for x in autotune.GRID["lane_split"]]
+    for k in ("filter_waves_per_cu", "order", "recon_cols_per_wave", "recon_waves_per_cu"):
+        assert tuned[k] in autotune.GRID[k], k
+    doc = json.loads(autotune.DEFAULT_OUT.read_text())
+    assert doc["best_ms"] <= doc["default_ms"]
